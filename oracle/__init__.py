@@ -1,0 +1,236 @@
+"""Plain CPU oracle for sampled sub-block hashing (ctypes over oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
+benchmark's CPU-baseline leg are the only code that may import this package.
+The GPU library never imports, links or runs it, and it never imports the
+GPU library.
+
+Every routine follows the paper's definitions (see the header of oracle.c):
+Toeplitz hashing K = T.A' (Sec. I), sampling by i.i.d. uniform V_i, the
+sub-block length threshold L_S^UB, per-sub-block extraction and concatenation
+(Sec. III.B, Sec. III.D).  Bit strings are LSB-first uint64 arrays.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "_oracle.so")
+_lib = None
+
+U64P = ctypes.POINTER(ctypes.c_uint64)
+U32P = ctypes.POINTER(ctypes.c_uint32)
+
+SAMPLE_IID, SAMPLE_PERMUTE, SAMPLE_EXPLICIT = 0, 1, 2
+OUT_FIXED, OUT_RATIO = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into _oracle.so with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-std=c11", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or (os.path.getmtime(_LIB)
+                                        < os.path.getmtime(_SRC)):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        lib.ssbo_splitmix64.restype = u64
+        lib.ssbo_splitmix64.argtypes = [u64, u64]
+        lib.ssbo_splitmix64_seq.restype = None
+        lib.ssbo_splitmix64_seq.argtypes = [u64, u64, U64P]
+        lib.ssbo_draw_v.restype = u32
+        lib.ssbo_draw_v.argtypes = [u64, u64, u32]
+        lib.ssbo_assign_iid.restype = None
+        lib.ssbo_assign_iid.argtypes = [u64, u32, u64, U32P]
+        lib.ssbo_seed_from_key.restype = None
+        lib.ssbo_seed_from_key.argtypes = [u64, u64, U64P]
+        lib.ssbo_lengths.restype = None
+        lib.ssbo_lengths.argtypes = [U32P, u64, u32, U64P, U64P]
+        lib.ssbo_partition.restype = i32
+        lib.ssbo_partition.argtypes = [U64P, u64, U32P, u32, U64P, u64, U64P,
+                                       U64P]
+        lib.ssbo_permute_split.restype = i32
+        lib.ssbo_permute_split.argtypes = [U64P, u64, U32P, u32, U64P, U64P,
+                                           U64P]
+        lib.ssbo_out_lengths.restype = None
+        lib.ssbo_out_lengths.argtypes = [U64P, u32, i32, u64, u64, U64P]
+        lib.ssbo_toeplitz_row.restype = i32
+        lib.ssbo_toeplitz_row.argtypes = [U64P, u64, U64P, u64, u64, u64]
+        lib.ssbo_toeplitz_rowwin.restype = i32
+        lib.ssbo_toeplitz_rowwin.argtypes = [U64P, u64, U64P, u64, u64, u64,
+                                             u64]
+        for name in ("ssbo_toeplitz_bits", "ssbo_toeplitz_window"):
+            f = getattr(lib, name)
+            f.restype = i32
+            f.argtypes = [U64P, u64, U64P, u64, u64, u64, u64, U64P, u64]
+        lib.ssbo_hash_batch.restype = ctypes.c_int64
+        lib.ssbo_hash_batch.argtypes = [U64P, U64P, U64P, u32, U64P, U64P,
+                                        u64, u64, u64, U64P, u64, i32]
+        _lib = lib
+    return _lib
+
+
+def _p64(a: np.ndarray):
+    return a.ctypes.data_as(U64P)
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(U32P)
+
+
+def _u64(a) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+    if a.size == 0:
+        a = np.zeros(1, dtype=np.uint64)
+    return a
+
+
+def _nw(n_bits: int) -> int:
+    return (int(n_bits) + 63) // 64
+
+
+# ----------------------------------------------------------------- PRNG ---
+
+def splitmix64(key: int, t: int) -> int:
+    """Output ``t`` (0-based) of the SplitMix64 stream seeded with ``key``."""
+    return int(_load().ssbo_splitmix64(key & (2**64 - 1), t))
+
+
+def splitmix64_seq(key: int, count: int) -> np.ndarray:
+    out = np.zeros(max(1, count), dtype=np.uint64)
+    _load().ssbo_splitmix64_seq(key & (2**64 - 1), count, _p64(out))
+    return out[:count]
+
+
+def draw_v(key: int, i: int, n_sub: int) -> int:
+    return int(_load().ssbo_draw_v(key & (2**64 - 1), i, n_sub))
+
+
+def assign_iid(n: int, n_sub: int, key: int) -> np.ndarray:
+    v = np.zeros(max(1, n), dtype=np.uint32)
+    _load().ssbo_assign_iid(n, n_sub, key & (2**64 - 1), _p32(v))
+    return v[:n]
+
+
+def seed_from_key(key: int, n_bits: int) -> np.ndarray:
+    s = np.zeros(max(1, _nw(n_bits)), dtype=np.uint64)
+    _load().ssbo_seed_from_key(key & (2**64 - 1), n_bits, _p64(s))
+    return s[: _nw(n_bits)]
+
+
+# ------------------------------------------------------------- sampling ---
+
+def partition(a, n: int, v, n_sub: int):
+    """Sub-blocks by an explicit assignment: returns (sub, len, word_off)."""
+    a = _u64(a)
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.uint32))
+    cap = _nw(n) + n_sub
+    sub = np.zeros(max(1, cap), dtype=np.uint64)
+    ln = np.zeros(max(1, n_sub), dtype=np.uint64)
+    wo = np.zeros(max(1, n_sub), dtype=np.uint64)
+    rc = _load().ssbo_partition(_p64(a), n, _p32(v) if v.size else None,
+                                n_sub, _p64(sub), cap, _p64(ln), _p64(wo))
+    if rc:
+        raise ValueError("bad assignment")
+    used = int(wo[n_sub - 1] + (ln[n_sub - 1] + 63) // 64) if n_sub else 0
+    return sub[:used], ln[:n_sub], wo[:n_sub]
+
+
+def permute_split(a, n: int, perm, n_sub: int):
+    a = _u64(a)
+    perm = np.ascontiguousarray(np.asarray(perm, dtype=np.uint32))
+    L = n // n_sub
+    wl = _nw(L)
+    sub = np.zeros(max(1, wl * n_sub), dtype=np.uint64)
+    ln = np.zeros(n_sub, dtype=np.uint64)
+    wo = np.zeros(n_sub, dtype=np.uint64)
+    rc = _load().ssbo_permute_split(_p64(a), n, _p32(perm), n_sub, _p64(sub),
+                                    _p64(ln), _p64(wo))
+    if rc:
+        raise ValueError("bad permutation split")
+    return sub[: wl * n_sub], ln, wo
+
+
+def sample(a, n: int, n_sub: int, mode: int, key: int = 0, assign=None,
+           l_ub: int = 0):
+    """Sampling step with the abort rule: returns (sub, len, word_off, abort)."""
+    if mode == SAMPLE_IID:
+        v = assign_iid(n, n_sub, key)
+        sub, ln, wo = partition(a, n, v, n_sub)
+    elif mode == SAMPLE_EXPLICIT:
+        sub, ln, wo = partition(a, n, assign, n_sub)
+    elif mode == SAMPLE_PERMUTE:
+        sub, ln, wo = permute_split(a, n, assign, n_sub)
+    else:
+        raise ValueError(mode)
+    abort = bool(l_ub) and n_sub > 0 and int(ln.max()) > int(l_ub)
+    return sub, ln, wo, abort
+
+
+def out_lengths(ln, rule: int, a: int, b: int = 1) -> np.ndarray:
+    ln = _u64(ln)
+    n_sub = int(np.asarray(ln).size)
+    out = np.zeros(n_sub, dtype=np.uint64)
+    _load().ssbo_out_lengths(_p64(ln), n_sub, rule, a, b, _p64(out))
+    return out
+
+
+# ------------------------------------------------------------- Toeplitz ---
+
+def toeplitz_row(x, n: int, seed, base: int, cap: int, r: int) -> int:
+    return int(_load().ssbo_toeplitz_row(_p64(_u64(x)), n, _p64(_u64(seed)),
+                                         base, cap, r))
+
+
+def toeplitz_rowwin(x, n: int, seed, seed_bits: int, base: int, cap: int,
+                    r: int) -> int:
+    return int(_load().ssbo_toeplitz_rowwin(_p64(_u64(x)), n,
+                                            _p64(_u64(seed)), seed_bits, base,
+                                            cap, r))
+
+
+def toeplitz(x, n: int, seed, seed_bits: int, m: int, base: int = 0,
+             cap: int | None = None, level: int = 1) -> np.ndarray:
+    """K = T.x for one block (m output bits, packed)."""
+    cap = m if cap is None else cap
+    out = np.zeros(max(1, _nw(m)), dtype=np.uint64)
+    f = _load().ssbo_toeplitz_bits if level == 0 else _load().ssbo_toeplitz_window
+    rc = f(_p64(_u64(x)), n, _p64(_u64(seed)), seed_bits, base, cap, m,
+           _p64(out), 0)
+    if rc:
+        raise ValueError("seed too short or m > cap")
+    return out[: _nw(m)]
+
+
+def hash_batch(sub, ln, wo, out_len, seed, seed_bits: int, stride: int,
+               cap: int, level: int = 1):
+    """Hash every sub-block and concatenate: returns (out, total_bits)."""
+    n_sub = int(np.asarray(out_len).size)
+    if int(np.asarray(ln).size) != n_sub or int(np.asarray(wo).size) != n_sub:
+        raise ValueError("len, word_off and out_len must have n_sub entries")
+    ln = _u64(ln)
+    wo = _u64(wo)
+    out_len = _u64(out_len)
+    total = int(out_len[:n_sub].sum()) if n_sub else 0
+    out = np.zeros(max(1, _nw(total)), dtype=np.uint64)
+    rc = _load().ssbo_hash_batch(_p64(_u64(sub)), _p64(ln), _p64(wo), n_sub,
+                                 _p64(out_len), _p64(_u64(seed)), seed_bits,
+                                 stride, cap, _p64(out), max(total, 1), level)
+    if rc < 0:
+        raise ValueError("bad hash arguments")
+    return out[: _nw(total)], int(rc)

@@ -1,0 +1,413 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by mathematics.
+
+Nothing here re-types the oracle's own formulas.  The Toeplitz product is
+pinned by two independent algorithms (carry-less polynomial multiplication on
+Python integers, and a float64 FFT correlation with a proven rounding margin),
+by closed forms (impulse seed, all-ones input, one output row), by GF(2)
+linearity and by diagonal constancy.  Sampling is pinned by published
+SplitMix64 outputs, by numpy boolean selection / fancy indexing (library
+routines), by the bijection property and by the abort rule of Sec. III.B.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from workloads import (assignment, bernoulli_bits, pack_bits, permutation,
+                       uniform_bits, unpack_bits)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------ independent algorithms ---
+
+def seed_window_bits(seed_words, start, length):
+    """Bits start .. start+length-1 of a packed seed as a 0/1 array."""
+    allbits = unpack_bits(seed_words, seed_words.size * 64)
+    return allbits[start:start + length]
+
+
+def clmul(a: int, b: int) -> int:
+    """Carry-less (GF(2)[z]) product of two bit-polynomials held in ints."""
+    r = 0
+    while b:
+        if b & 1:
+            r ^= a
+        a <<= 1
+        b >>= 1
+    return r
+
+
+def toeplitz_by_clmul(xbits, sbits, m, cap):
+    """K[r] as the coefficient of z^{n-1+(cap-1-r)} of S(z) * X~(z), where
+    S = sum s_k z^k over the seed window and X~ = sum x_c z^{n-1-c}."""
+    n = len(xbits)
+    S = 0
+    for k, b in enumerate(sbits):
+        if b:
+            S |= 1 << k
+    X = 0
+    for c, b in enumerate(xbits):
+        if b:
+            X |= 1 << (n - 1 - c)
+    P = clmul(S, X)
+    return np.array([(P >> (n - 1 + cap - 1 - r)) & 1 for r in range(m)],
+                    dtype=np.uint8)
+
+
+def toeplitz_by_fft(xbits, sbits, m, cap):
+    """Integer correlation by float64 FFT, rounded, reduced mod 2.  The
+    rounding residual is asserted below 0.25 so the result is exact."""
+    n = len(xbits)
+    if n == 0 or m == 0:
+        return np.zeros(m, dtype=np.uint8)
+    s = np.asarray(sbits, dtype=np.float64)
+    x = np.asarray(xbits, dtype=np.float64)[::-1]
+    L = 1
+    while L < s.size + x.size:
+        L *= 2
+    conv = np.fft.irfft(np.fft.rfft(s, L) * np.fft.rfft(x, L), L)
+    u = cap - 1 - np.arange(m)
+    vals = conv[u + n - 1]
+    resid = np.abs(vals - np.round(vals)).max()
+    assert resid < 0.25, resid
+    return (np.round(vals).astype(np.int64) & 1).astype(np.uint8)
+
+
+def rand_bits(n, seed):
+    return unpack_bits(uniform_bits(n, seed), n)
+
+
+# ------------------------------------------------------------- SplitMix64 ---
+
+def test_splitmix64_published_values(orc):
+    with open(os.path.join(GOLDEN, "splitmix64.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) >= 6
+    for seed, idx, val in rows:
+        assert orc.splitmix64(int(seed), int(idx)) == int(val)
+
+
+def test_splitmix64_counter_form_equals_sequential(orc):
+    for key in (0, 1, 1234567, 2**64 - 1, 0x2308028560000103):
+        seq = orc.splitmix64_seq(key, 257)
+        cnt = np.array([orc.splitmix64(key, t) for t in range(257)],
+                       dtype=np.uint64)
+        assert np.array_equal(seq, cnt)
+
+
+def test_draw_v_power_of_two_takes_top_bits(orc):
+    key = 0xABCDEF
+    for log2 in (0, 1, 3, 11, 13):
+        ns = 1 << log2
+        for i in range(200):
+            r = orc.splitmix64(key, i // 2)
+            u = (r >> 32) if (i & 1) else (r & 0xFFFFFFFF)
+            want = (u >> (32 - log2)) if log2 else 0
+            assert orc.draw_v(key, i, ns) == want
+
+
+def test_draw_v_range_and_uniformity(orc):
+    ns, n = 7, 70000
+    v = orc.assign_iid(n, ns, 99)
+    assert v.max() < ns
+    counts = np.bincount(v, minlength=ns)
+    chi2 = (((counts - n / ns) ** 2) / (n / ns)).sum()
+    assert chi2 < 30.0  # 6 dof; p ~ 4e-5
+
+
+def test_assign_iid_matches_single_draws(orc):
+    v = orc.assign_iid(1001, 13, 5)
+    assert all(int(v[i]) == orc.draw_v(5, i, 13) for i in range(1001))
+
+
+def test_seed_from_key(orc):
+    s = orc.seed_from_key(77, 200)
+    assert s.size == 4
+    for t in range(3):
+        assert int(s[t]) == orc.splitmix64(77, t)
+    assert int(s[3]) == orc.splitmix64(77, 3) & ((1 << 8) - 1)
+
+
+# ---------------------------------------------------------------- sampling ---
+
+@pytest.mark.parametrize("n,ns", [(1, 1), (10007, 13), (4096, 64), (777, 1),
+                                  (5000, 2048)])
+def test_partition_equals_boolean_selection(orc, n, ns):
+    a = bernoulli_bits(n, 0.3, n + ns)
+    v = assignment(n, ns, 1000 + n)
+    sub, ln, wo = orc.partition(a, n, v, ns)
+    abits = unpack_bits(a, n)
+    assert np.array_equal(ln, np.bincount(v, minlength=ns).astype(np.uint64))
+    words = (ln + 63) // 64
+    assert np.array_equal(wo, np.concatenate([[0], np.cumsum(words)[:-1]])
+                          .astype(np.uint64))
+    recon = np.zeros(n, dtype=np.uint8)
+    for j in range(ns):
+        got = unpack_bits(sub[int(wo[j]):int(wo[j] + words[j])],
+                          int(words[j]) * 64)
+        want = abits[v == j]           # ascending-i selection
+        assert np.array_equal(got[:int(ln[j])], want)
+        assert not got[int(ln[j]):].any()   # pad bits are zero
+        recon[np.nonzero(v == j)[0]] = got[:int(ln[j])]
+    assert np.array_equal(recon, abits)     # every bit lands exactly once
+
+
+def test_sample_iid_is_partition_by_splitmix_assignment(orc):
+    n, ns, key = 20000, 37, 0x1234
+    a = uniform_bits(n, 3)
+    sub, ln, wo, abort = orc.sample(a, n, ns, orc.SAMPLE_IID, key=key)
+    sub2, ln2, wo2 = orc.partition(a, n, orc.assign_iid(n, ns, key), ns)
+    assert not abort
+    assert np.array_equal(sub, sub2) and np.array_equal(ln, ln2)
+    assert int(ln.sum()) == n
+
+
+def test_abort_threshold(orc):
+    n, ns = 30000, 16
+    a = uniform_bits(n, 4)
+    _, ln, _, _ = orc.sample(a, n, ns, orc.SAMPLE_IID, key=9)
+    mx = int(ln.max())
+    assert orc.sample(a, n, ns, orc.SAMPLE_IID, key=9, l_ub=mx - 1)[3]
+    assert not orc.sample(a, n, ns, orc.SAMPLE_IID, key=9, l_ub=mx)[3]
+    assert not orc.sample(a, n, ns, orc.SAMPLE_IID, key=9, l_ub=0)[3]
+
+
+@pytest.mark.parametrize("n,ns", [(1 << 12, 8), (960, 3), (64 * 5, 5)])
+def test_permute_split_equals_fancy_indexing(orc, n, ns):
+    a = uniform_bits(n, 11)
+    perm = permutation(n, 12)
+    assert np.array_equal(np.sort(perm), np.arange(n, dtype=np.uint32))
+    sub, ln, wo = orc.permute_split(a, n, perm, ns)
+    b = unpack_bits(a, n)[perm]
+    L = n // ns
+    wl = (L + 63) // 64
+    for j in range(ns):
+        got = unpack_bits(sub[j * wl:(j + 1) * wl], wl * 64)
+        assert np.array_equal(got[:L], b[j * L:(j + 1) * L])
+        assert not got[L:].any()
+    assert np.all(ln == L)
+
+
+def test_permute_split_rejects_indivisible(orc):
+    with pytest.raises(ValueError):
+        orc.permute_split(uniform_bits(100, 1), 100, permutation(100, 2), 3)
+
+
+def test_out_lengths(orc):
+    ln = np.array([0, 1, 5, 131072, 131073, 2**40 + 3], dtype=np.uint64)
+    assert list(orc.out_lengths(ln, orc.OUT_FIXED, 99)) == [99] * 6
+    got = orc.out_lengths(ln, orc.OUT_RATIO, 2, 5)
+    assert [int(g) for g in got] == [(int(v) * 2) // 5 for v in ln]
+    assert int(got[3]) == 52428
+    big = orc.out_lengths(np.array([2**62], dtype=np.uint64), orc.OUT_RATIO,
+                          3, 7)
+    assert int(big[0]) == (2**62 * 3) // 7
+
+
+# ---------------------------------------------------------------- Toeplitz ---
+
+def oracle_bits(orc, xbits, sbits, m, cap=None, base=0, level=1):
+    n = len(xbits)
+    cap = m if cap is None else cap
+    x = pack_bits(xbits) if n else np.zeros(1, dtype=np.uint64)
+    s = pack_bits(sbits) if len(sbits) else np.zeros(1, dtype=np.uint64)
+    out = orc.toeplitz(x, n, s, len(sbits), m, base=base, cap=cap,
+                       level=level)
+    return unpack_bits(out, m)
+
+
+def test_toeplitz_exhaustive_tiny_against_clmul(orc):
+    for n in range(1, 5):
+        for m in range(1, 5):
+            ls = n + m - 1
+            for sv in range(1 << ls):
+                sbits = [(sv >> k) & 1 for k in range(ls)]
+                for xv in range(1 << n):
+                    xbits = [(xv >> k) & 1 for k in range(n)]
+                    want = toeplitz_by_clmul(xbits, sbits, m, m)
+                    for level in (0, 1):
+                        got = oracle_bits(orc, np.array(xbits), np.array(sbits),
+                                          m, level=level)
+                        assert np.array_equal(got, want), (n, m, sv, xv, level)
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (63, 65), (64, 64), (100, 37),
+                                 (1000, 1500), (4097, 2049), (3000, 1),
+                                 (1, 700)])
+def test_toeplitz_against_fft_and_clmul(orc, n, m):
+    xbits = rand_bits(n, n * 7 + m)
+    sbits = rand_bits(n + m - 1, n * 11 + m)
+    want = toeplitz_by_fft(xbits, sbits, m, m)
+    assert np.array_equal(want, toeplitz_by_clmul(xbits, sbits, m, m))
+    for level in (0, 1):
+        assert np.array_equal(oracle_bits(orc, xbits, sbits, m, level=level),
+                              want)
+
+
+def test_toeplitz_large_against_fft(orc):
+    n, m = 32768 + 45, 16384 + 13
+    xbits = rand_bits(n, 21)
+    sbits = rand_bits(n + m - 1, 22)
+    got = oracle_bits(orc, xbits, sbits, m, level=1)
+    assert np.array_equal(got, toeplitz_by_fft(xbits, sbits, m, m))
+
+
+def test_toeplitz_seed_offset_and_row_cap(orc):
+    # T[r][c] = s[base + c - r + cap - 1]: the block reads the seed window that
+    # starts at `base`, and a cap above m selects the top rows of the taller
+    # cap x n matrix.
+    n, m, cap, base = 777, 300, 450, 1234
+    xbits = rand_bits(n, 31)
+    sbits = rand_bits(base + n + cap - 1 + 50, 32)
+    got = oracle_bits(orc, xbits, sbits, m, cap=cap, base=base, level=1)
+    window = sbits[base:base + n + cap - 1]
+    want = toeplitz_by_fft(xbits, window, m, cap)
+    assert np.array_equal(got, want)
+    tall = toeplitz_by_fft(xbits, window, cap, cap)
+    assert np.array_equal(got, tall[:m])
+    assert np.array_equal(oracle_bits(orc, xbits, sbits, m, cap=cap,
+                                      base=base, level=0), want)
+
+
+def test_toeplitz_closed_forms(orc):
+    n, m = 257, 130
+    x = rand_bits(n, 41)
+    s = rand_bits(n + m - 1, 42)
+    z = np.zeros
+    assert not oracle_bits(orc, x, z(n + m - 1, np.uint8), m).any()
+    assert not oracle_bits(orc, z(n, np.uint8), s, m).any()
+    # one output row: inner product of x with the first n seed bits
+    got = oracle_bits(orc, x, s[:n], 1)
+    assert got[0] == (int(np.dot(x.astype(int), s[:n].astype(int))) & 1)
+    # impulse seed e_k shifts the input: K[r] = x[r + k - m + 1]
+    for k in (0, m - 1, m + 5, n + m - 2):
+        e = z(n + m - 1, np.uint8)
+        e[k] = 1
+        got = oracle_bits(orc, x, e, m)
+        want = np.array([x[r + k - m + 1] if 0 <= r + k - m + 1 < n else 0
+                         for r in range(m)], dtype=np.uint8)
+        assert np.array_equal(got, want), k
+    # identity when m = n and the impulse sits at m - 1
+    e = z(2 * n - 1, np.uint8)
+    e[n - 1] = 1
+    assert np.array_equal(oracle_bits(orc, x, e, n), x)
+    # all-ones input: K[r] = P[n+m-1-r] xor P[m-1-r], P = prefix xor of s
+    P = np.concatenate([[0], np.bitwise_xor.accumulate(s)]).astype(np.uint8)
+    got = oracle_bits(orc, np.ones(n, np.uint8), s, m)
+    want = np.array([P[n + m - 1 - r] ^ P[m - 1 - r] for r in range(m)],
+                    dtype=np.uint8)
+    assert np.array_equal(got, want)
+
+
+def test_toeplitz_linearity(orc):
+    n, m = 999, 321
+    a, b = rand_bits(n, 51), rand_bits(n, 52)
+    s, t = rand_bits(n + m - 1, 53), rand_bits(n + m - 1, 54)
+    assert np.array_equal(oracle_bits(orc, a ^ b, s, m),
+                          oracle_bits(orc, a, s, m) ^ oracle_bits(orc, b, s, m))
+    assert np.array_equal(oracle_bits(orc, a, s ^ t, m),
+                          oracle_bits(orc, a, s, m) ^ oracle_bits(orc, a, t, m))
+
+
+def test_toeplitz_is_diagonal_constant(orc):
+    n, m = 40, 33
+    s = rand_bits(n + m - 1, 61)
+    cols = []
+    for c in range(n):
+        e = np.zeros(n, np.uint8)
+        e[c] = 1
+        cols.append(oracle_bits(orc, e, s, m, level=0))
+    T = np.stack(cols, axis=1)                       # m x n
+    assert np.array_equal(T[1:, 1:], T[:-1, :-1])    # T[r+1][c+1] = T[r][c]
+    # every seed bit appears: first row and first column hold all n+m-1 bits
+    assert T.shape == (m, n)
+
+
+def test_toeplitz_edge_cases(orc):
+    s = uniform_bits(200, 71)
+    out = orc.toeplitz(np.zeros(1, np.uint64), 0, s, 200, 50)
+    assert not out.any() and out.size == 1
+    assert orc.toeplitz(uniform_bits(64, 1), 64, s, 200, 0).size == 0
+    with pytest.raises(ValueError):
+        orc.toeplitz(uniform_bits(100, 1), 100, s, 150, 60)  # needs 159 bits
+    with pytest.raises(ValueError):
+        orc.toeplitz(uniform_bits(10, 1), 10, s, 200, 20, cap=10)  # m > cap
+
+
+def test_row_functions_agree_with_block(orc):
+    n, m = 5000, 700
+    x = uniform_bits(n, 81)
+    s = uniform_bits(n + m - 1, 82)
+    blk = unpack_bits(orc.toeplitz(x, n, s, n + m - 1, m), m)
+    for r in (0, 1, 63, 64, 399, m - 1):
+        assert orc.toeplitz_row(x, n, s, 0, m, r) == blk[r]
+        assert orc.toeplitz_rowwin(x, n, s, n + m - 1, 0, m, r) == blk[r]
+
+
+# ----------------------------------------------------------- concatenation ---
+
+@pytest.mark.parametrize("stride_mode", ["shared", "independent"])
+def test_hash_batch_concatenates_per_block_hashes(orc, stride_mode):
+    n, ns = 20000, 9
+    a = bernoulli_bits(n, 0.4, 91)
+    sub, ln, wo, _ = orc.sample(a, n, ns, orc.SAMPLE_IID, key=92)
+    m = orc.out_lengths(ln, orc.OUT_RATIO, 2, 5)
+    cap = int(m.max())
+    nmax = int(ln.max())
+    stride = 0 if stride_mode == "shared" else nmax + cap - 1
+    seed_bits = (ns - 1) * stride + nmax + cap - 1
+    seed = uniform_bits(seed_bits, 93)
+    out, total = orc.hash_batch(sub, ln, wo, m, seed, seed_bits, stride, cap,
+                                level=1)
+    assert total == int(m.sum())
+    obits = unpack_bits(out, out.size * 64)
+    sbits = unpack_bits(seed, seed_bits)
+    off = 0
+    for j in range(ns):
+        nj, mj = int(ln[j]), int(m[j])
+        xj = unpack_bits(sub[int(wo[j]):], nj)
+        window = sbits[j * stride: j * stride + nj + cap - 1]
+        want = toeplitz_by_fft(xj, window, mj, cap)
+        assert np.array_equal(obits[off:off + mj], want), j
+        off += mj
+    assert not obits[total:].any()
+    out0, _ = orc.hash_batch(sub, ln, wo, m, seed, seed_bits, stride, cap,
+                             level=0)
+    assert np.array_equal(out0, out)
+
+
+# ---------------------------------------------------------- input helpers ---
+
+def test_pack_roundtrip_and_tail():
+    for n in (1, 63, 64, 65, 1000):
+        b = rand_bits(n, n)
+        w = pack_bits(b)
+        assert w.size == (n + 63) // 64
+        assert np.array_equal(unpack_bits(w, n), b)
+        assert not unpack_bits(w, w.size * 64)[n:].any()
+
+
+def test_bernoulli_density():
+    n = 1 << 20
+    for p in (0.2, 0.3, 0.5):
+        frac = unpack_bits(bernoulli_bits(n, p, 5), n).mean()
+        assert abs(frac - p) < 5 * np.sqrt(p * (1 - p) / n)
+
+
+def test_toeplitz_ignores_input_bits_past_n(orc):
+    # Bits beyond n in the last input word are not part of the input.
+    for n, m in ((100, 40), (65, 65), (1000, 3)):
+        x = uniform_bits(n, 101)
+        dirty = x.copy()
+        dirty[-1] |= ~np.uint64((1 << (n % 64)) - 1) if n % 64 else np.uint64(0)
+        s = uniform_bits(n + m - 1, 102)
+        for level in (0, 1):
+            assert np.array_equal(orc.toeplitz(dirty, n, s, n + m - 1, m,
+                                               level=level),
+                                  orc.toeplitz(x, n, s, n + m - 1, m,
+                                               level=level))
+        for r in (0, m - 1):
+            assert (orc.toeplitz_rowwin(dirty, n, s, n + m - 1, 0, m, r)
+                    == orc.toeplitz_row(x, n, s, 0, m, r))

@@ -1,0 +1,122 @@
+"""The five workloads of this project and the serving job stream.
+
+Each workload is described by plain numbers; the keys are fixed so that every
+run (tests, benchmark, smoke check) sees the same synthetic data.
+
+* ``small``       N = 2^18 uniform bits, Fisher-Yates permutation then a
+                  contiguous split into 8 sub-blocks of 2^15 bits, each hashed
+                  to 2^14 bits with its own seed of 2^15 + 2^14 - 1 bits.
+* ``single``      one block, n = 2^24 uniform bits hashed to m = 2^23 bits
+                  with a seed of n + m - 1 bits (no sampling).
+* ``batched``     N = 2^28 Bernoulli(0.3) bits, i.i.d. uniform assignment to
+                  2048 sub-blocks, output floor(0.4 * n_j) bits each, one
+                  shared seed of max n_j + max m_j - 1 bits.
+* ``contraction`` N = 2^30 uniform bits, permutation then split into 8192
+                  sub-blocks of 2^17 bits, shared seed, 2^16 output bits each.
+* ``serving``     a Poisson stream (mean 200 jobs/s) of jobs with block sizes
+                  log-uniform in 2^20..2^28, Bernoulli(p), p ~ U[0.2, 0.5],
+                  sub-block size log-uniform in 2^16..2^18, output ratio
+                  q/1000 with q uniform in 200..600, fresh keys per job.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .gen import bernoulli_bits
+
+_KEY_BASE = 0x2308028560000000
+
+CONFIGS = {
+    "small": dict(
+        name="small", n_bits=1 << 18, p=0.5, n_sub=8, sampling="permute",
+        out_rule="fixed", out_a=1 << 14, out_b=1,
+        seed_mode="independent", sub_bits=1 << 15,
+        input_seed=1, perm_seed=101, seed_seed=201,
+    ),
+    "single": dict(
+        name="single", n_bits=1 << 24, p=0.5, n_sub=1, sampling="none",
+        out_rule="fixed", out_a=1 << 23, out_b=1, seed_mode="shared",
+        input_seed=2, seed_seed=202,
+    ),
+    "batched": dict(
+        name="batched", n_bits=1 << 28, p=0.3, n_sub=2048, sampling="iid",
+        out_rule="ratio", out_a=2, out_b=5, seed_mode="shared",
+        input_seed=3, sample_key=_KEY_BASE + 0x103, seed_seed=203,
+    ),
+    "contraction": dict(
+        name="contraction", n_bits=1 << 30, p=0.5, n_sub=8192,
+        sampling="permute", out_rule="fixed", out_a=1 << 16, out_b=1,
+        seed_mode="shared", sub_bits=1 << 17,
+        input_seed=4, perm_seed=104, seed_seed=204,
+    ),
+    "serving": dict(
+        name="serving", rate_hz=200.0, log2_n=(20, 28), p=(0.2, 0.5),
+        log2_sub=(16, 18), q=(200, 600), stream_seed=5,
+        sample_key_base=_KEY_BASE + 0x105, seed_key_base=_KEY_BASE + 0x205,
+    ),
+}
+
+
+def config(name: str) -> dict:
+    return dict(CONFIGS[name])
+
+
+def serving_jobs(count: int, seed: int = 5, rate_hz: float = 200.0,
+                 log2_n=(20, 28), log2_sub=(16, 18), q=(200, 600),
+                 p=(0.2, 0.5), max_n_bits: int | None = None) -> list[dict]:
+    """A reproducible Poisson job stream.
+
+    Every job carries its arrival time (seconds from stream start), its block
+    size, Bernoulli parameter, sub-block count, output ratio ``q/1000`` and
+    two fresh 64-bit keys (sampling variables and Toeplitz seed).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    jobs = []
+    for k in range(int(count)):
+        t += float(rng.exponential(1.0 / rate_hz))
+        u = float(rng.random())
+        n_bits = int(math.floor(2.0 ** (log2_n[0] + (log2_n[1] - log2_n[0]) * u)))
+        if max_n_bits is not None:
+            n_bits = min(n_bits, int(max_n_bits))
+        us = float(rng.random())
+        sub = int(math.floor(2.0 ** (log2_sub[0] + (log2_sub[1] - log2_sub[0]) * us)))
+        n_sub = max(1, int(round(n_bits / sub)))
+        qq = int(rng.integers(q[0], q[1] + 1))
+        pp = float(p[0] + (p[1] - p[0]) * rng.random())
+        jobs.append(dict(
+            index=k, arrival_s=t, n_bits=n_bits, p=pp, n_sub=n_sub,
+            ratio_num=qq, ratio_den=1000,
+            sample_key=int(rng.integers(0, 2**63 - 1)) * 2 + 1,
+            seed_key=int(rng.integers(0, 2**63 - 1)) * 2 + 1,
+        ))
+    return jobs
+
+
+def serving_pools(levels: int = 8, pool_bits: int = 1 << 28, seed: int = 55,
+                  p=(0.2, 0.5)) -> tuple[list[float], list[np.ndarray]]:
+    """Input pools for the serving stream: one Bernoulli block per p level.
+
+    A job with parameter p reads a slice of the pool whose level is nearest
+    to p (levels are the midpoints of ``levels`` equal bins of [p0, p1]).
+    """
+    ps = [p[0] + (p[1] - p[0]) * (k + 0.5) / levels for k in range(levels)]
+    pools = [bernoulli_bits(pool_bits, pk, seed + k) for k, pk in enumerate(ps)]
+    return ps, pools
+
+
+def pool_slice(job: dict, ps: list[float], pools: list[np.ndarray]) -> np.ndarray:
+    """The packed input of one serving job (a word-aligned slice of a pool)."""
+    k = int(np.argmin([abs(job["p"] - pk) for pk in ps]))
+    pool = pools[k]
+    nw = (job["n_bits"] + 63) // 64
+    total = pool.size
+    off = (job["index"] * 7919 * 64) % max(1, total - nw + 1)
+    words = pool[off: off + nw].copy()
+    r = job["n_bits"] % 64
+    if r:
+        words[-1] &= np.uint64((1 << r) - 1)
+    return words
