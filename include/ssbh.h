@@ -1,0 +1,204 @@
+/*
+ * ssbh.h - sampled sub-block hashing on AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv 2308.02856): a large weakly random bit block A^N is
+ * divided into N_S sub-blocks by seeded random sampling (Sec. III.B step 1),
+ * an over-long sub-block aborts the protocol (Sec. III.B step 2, Sec. III.D),
+ * every sub-block is hashed with a GF(2) Toeplitz matrix (Sec. I, K = T.A';
+ * Sec. III.B step 3) and the outputs are concatenated (Sec. III.B step 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Bit strings: arrays of uint64_t words; bit k is (w[k >> 6] >> (k & 63)) & 1
+ *   (least significant bit first).  Sub-block j of a sampled buffer starts at
+ *   word d_word_off[j] and holds d_len[j] bits; bits past d_len[j] in its last
+ *   word are zero after ssbh_sample and ignored by ssbh_hash_batch.
+ * Toeplitz matrices (the paper fixes no placement of the seed bits; this
+ *   library's convention):  T_j[r][c] = s[j*S + c - r + M - 1]  for
+ *   0 <= r < m_j, 0 <= c < n_j, where s is the seed bit string, S the seed
+ *   stride and M the row cap (M >= every m_j).  S = 0 means one shared seed:
+ *   every T_j is the top-left m_j x n_j corner of one M x max(n_j) matrix.
+ *   S >= max(n_j) + M - 1 gives every sub-block its own independent seed, as
+ *   the paper's security claim requires (Sec. III.B step 3).  With one block
+ *   and M = m this is T[r][c] = s[c - r + m - 1]: row r is the seed window
+ *   that starts at bit m - 1 - r.
+ * Indices are 0-based: the paper's V_i in [1, N_S] is V_i - 1 here.
+ * Pointers named d_* are device memory owned by the caller; the library never
+ *   frees them.  The library owns its scratch memory, sized on demand and
+ *   released by ssbh_destroy.  Every call is asynchronous on the given HIP
+ *   stream (a hipStream_t passed as void *, NULL = the null stream) unless
+ *   stated otherwise.  Calls that share one context must not overlap: they
+ *   share its scratch memory.
+ * Errors: entry points return ssbh_status and never throw.  Argument errors
+ *   that the host can see are returned at once, with a message in
+ *   ssbh_last_error() and nothing enqueued.  Conditions that only the device
+ *   can see (lengths, the abort rule) are written to a caller-owned device
+ *   int32 d_status; every kernel of ssbh_hash_batch does nothing when
+ *   *d_status is nonzero on entry, so an aborted sampling leaves d_out
+ *   untouched.
+ */
+#ifndef SSBH_H
+#define SSBH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssbh_ctx ssbh_ctx;
+
+typedef enum {
+    SSBH_OK = 0,
+    SSBH_PENDING = 1,              /* serving: job not finished yet          */
+    SSBH_E_INVAL = -1,             /* bad argument or inconsistent lengths   */
+    SSBH_E_ABORT_OVERSIZE = -2,    /* some n_j > L_S^UB (Sec. III.B step 2)  */
+    SSBH_E_NOMEM = -3,             /* device memory or HBM budget exhausted  */
+    SSBH_E_DEVICE = -4,            /* a HIP runtime call failed              */
+    SSBH_E_UNKNOWN_JOB = -5,       /* serving: no such job id                */
+    SSBH_E_UNSUPPORTED = -6        /* outside this build's limits            */
+} ssbh_status;
+
+/* Sampling modes (Sec. III.B step 1). */
+enum {
+    SSBH_SAMPLE_IID = 0,      /* V_i drawn on the device from SplitMix64     */
+    SSBH_SAMPLE_PERMUTE = 1,  /* d_assign = permutation pi; contiguous split */
+    SSBH_SAMPLE_EXPLICIT = 2  /* d_assign = V_i given by the caller          */
+};
+
+/* Output-length rules (Sec. III.B step 3). */
+enum {
+    SSBH_OUT_FIXED = 0,       /* m_j = out_a (the paper's l~)                 */
+    SSBH_OUT_RATIO = 1,       /* m_j = floor(n_j * out_a / out_b)             */
+    SSBH_OUT_EXPLICIT = 2     /* m_j = d_out_len[j]                           */
+};
+
+/* Hash kernels. */
+enum {
+    SSBH_K_AUTO = 0,          /* library picks (autotuned)                    */
+    SSBH_K_VALU = 1,          /* bit-sliced AND-XOR + popcount parity         */
+    SSBH_K_MFMA_I8 = 2        /* int8 matrix cores, int32 sums, then mod 2;
+                                 only for a shared seed (seed_stride == 0)    */
+};
+
+/* Limits of this build. */
+#define SSBH_MAX_SUB_LDS 16384u   /* n_sub limit of the i.i.d./explicit modes */
+
+/* ------------------------------------------------------------- context --- */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory that the serving scheduler may hold for admitted jobs
+ * (0 = 80% of the free memory at creation).  Returns SSBH_E_DEVICE when the
+ * device cannot be used. */
+ssbh_status ssbh_create(int device, uint64_t hbm_budget_bytes, ssbh_ctx **out);
+
+/* Wait for the context's own work, stop its serving thread and free its
+ * scratch memory and pending jobs.  NULL is ignored. */
+void ssbh_destroy(ssbh_ctx *ctx);
+
+/* Message of the last error on the calling thread ("" if none).  Valid until
+ * the next call on the same thread. */
+const char *ssbh_last_error(void);
+
+/* Number of compute units of the context's device. */
+int ssbh_num_cus(const ssbh_ctx *ctx);
+
+/* --------------------------------------------------- sampling (a1 - a3) --- */
+
+/* Divide n_bits input bits into n_sub sub-blocks (Sec. III.B step 1) and
+ * apply the abort rule (Sec. III.B step 2, Sec. III.D).
+ *
+ *  d_in          input bits A^N (ceil(n_bits/64) words; bits past n_bits are
+ *                ignored).
+ *  mode          SSBH_SAMPLE_IID: V_i is drawn on the device from the
+ *                SplitMix64 stream with key sample_key (output t is
+ *                mix(key + (t+1)*0x9E3779B97F4A7C15) with Stafford's variant
+ *                13 finaliser); round i uses the low 32 bits of output i/2
+ *                for even i and the high 32 bits for odd i, and
+ *                V_i = floor(u_i * n_sub / 2^32) (exactly uniform when n_sub
+ *                is a power of two, relative bias below n_sub / 2^32
+ *                otherwise).  Sub-block j holds the bits with V_i = j in
+ *                ascending i.  n_sub <= SSBH_MAX_SUB_LDS.
+ *                SSBH_SAMPLE_EXPLICIT: the same, with V_i = d_assign[i]
+ *                (uint32, every value < n_sub, else *d_status = SSBH_E_INVAL).
+ *                SSBH_SAMPLE_PERMUTE: d_assign is a permutation pi of
+ *                0..n_bits-1 (uint32); B[k] = A[pi[k]] and sub-block j is
+ *                B[jL, (j+1)L) with L = n_bits / n_sub (n_sub must divide
+ *                n_bits).  Entries >= n_bits give *d_status = SSBH_E_INVAL.
+ *  l_ub          L_S^UB; 0 disables the abort rule.  If some n_j > l_ub,
+ *                *d_status = SSBH_E_ABORT_OVERSIZE.
+ *  d_sub         output sub-blocks, sub_capacity_words words.  Needs
+ *                ceil(n_bits/64) + n_sub words (IID, EXPLICIT) or
+ *                n_sub * ceil(L/64) words (PERMUTE).
+ *  d_len         output n_j (n_sub uint64).
+ *  d_word_off    output W_j = sum_{k<j} ceil(n_k/64) (n_sub uint64).
+ *  d_status      device int32, overwritten with 0 or an error code.
+ *  stream        hipStream_t.
+ * n_bits = 0 gives n_sub empty sub-blocks. */
+ssbh_status ssbh_sample(ssbh_ctx *ctx, const uint64_t *d_in, uint64_t n_bits,
+                        uint32_t n_sub, uint32_t mode, uint64_t sample_key,
+                        const uint32_t *d_assign, uint64_t l_ub,
+                        uint64_t *d_sub, uint64_t sub_capacity_words,
+                        uint64_t *d_len, uint64_t *d_word_off,
+                        int32_t *d_status, void *stream);
+
+/* ------------------------------------------- hash + concatenate (a4 - a7) --- */
+
+/* Hash every sub-block with its Toeplitz matrix T_j and concatenate the
+ * outputs (Sec. I; Sec. III.B steps 3-4):
+ *     K_j[r] = XOR_{c < n_j} ( s[j*S + c - r + M - 1] AND x_j[c] ),
+ *     K = K_0 || K_1 || ... ,  K_j at bit offset O_j = sum_{k<j} m_k.
+ * n_sub = 1 is the plain single-block hash.
+ *
+ *  d_sub, d_len, d_word_off  sub-blocks as written by ssbh_sample (or built
+ *                by the caller in the same layout); every sub-block must lie
+ *                inside the first sub_capacity_words words of d_sub.
+ *  out_rule, out_a, out_b, d_out_len   output lengths m_j (see SSBH_OUT_*;
+ *                d_out_len is read only for SSBH_OUT_EXPLICIT).
+ *  d_seed, seed_bits   seed bit string s.  Every sub-block with n_j > 0 and
+ *                m_j > 0 needs j*S + n_j + M - 1 <= seed_bits.
+ *  seed_stride   S (0 = shared seed).
+ *  m_cap         M; every m_j must be <= M.
+ *  kernel        SSBH_K_*.
+ *  d_out         output, out_capacity_bits bits (ceil(/64) words); zeroed and
+ *                then written; bits past the total are zero.
+ *  d_out_total_bits  device uint64, receives sum_j m_j.
+ *  d_status      device int32 (in/out): nonzero on entry makes the call a
+ *                no-op on the device; a length, seed or capacity violation
+ *                found on the device sets SSBH_E_INVAL and leaves d_out
+ *                untouched.
+ * The result is bit-identical for every kernel and schedule. */
+ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
+                            uint64_t sub_capacity_words,
+                            const uint64_t *d_len, const uint64_t *d_word_off,
+                            uint32_t n_sub, uint32_t out_rule, uint64_t out_a,
+                            uint64_t out_b, const uint64_t *d_out_len,
+                            const uint64_t *d_seed, uint64_t seed_bits,
+                            uint64_t seed_stride, uint64_t m_cap,
+                            uint32_t kernel, uint64_t *d_out,
+                            uint64_t out_capacity_bits,
+                            uint64_t *d_out_total_bits, int32_t *d_status,
+                            void *stream);
+
+/* Seed bits from a key, on the device: word t of d_seed is output t of the
+ * SplitMix64 stream with key seed_key (the generator described at
+ * ssbh_sample); bits past seed_bits are zero.  Used for the fresh per-job
+ * seeds of the serving loop (a uniform seed, Sec. I). */
+ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
+                               uint64_t *d_seed, uint64_t seed_bits,
+                               void *stream);
+
+/* ------------------------------------------------------------- tuning --- */
+
+/* Force the schedule of the VALU hash kernel for later calls on this
+ * context: r = rows per lane (8, 16 or 32), waves = wavefronts per workgroup
+ * (2, 4 or 8; a workgroup tile is 64*r*waves rows), tile_cols = 32-bit column
+ * words per tile (0 = whole sub-block).  0 for r or waves restores the
+ * library's choice.  The output bits do not depend on the schedule. */
+ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
+                              uint32_t tile_cols);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSBH_H */

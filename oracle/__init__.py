@@ -78,6 +78,8 @@ def _load():
             f = getattr(lib, name)
             f.restype = i32
             f.argtypes = [U64P, u64, U64P, u64, u64, u64, u64, U64P, u64]
+        lib.ssbo_threads.restype = i32
+        lib.ssbo_threads.argtypes = []
         lib.ssbo_hash_batch.restype = ctypes.c_int64
         lib.ssbo_hash_batch.argtypes = [U64P, U64P, U64P, u32, U64P, U64P,
                                         u64, u64, u64, U64P, u64, i32]
@@ -102,6 +104,11 @@ def _u64(a) -> np.ndarray:
 
 def _nw(n_bits: int) -> int:
     return (int(n_bits) + 63) // 64
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().ssbo_threads())
 
 
 # ----------------------------------------------------------------- PRNG ---

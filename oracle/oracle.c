@@ -264,3 +264,11 @@ int64_t ssbo_hash_batch(const uint64_t *sub, const uint64_t *len,
     }
     return (int64_t)total;
 }
+
+/* Threads the OpenMP loops above use (reported with CPU timings). */
+#ifdef _OPENMP
+#include <omp.h>
+int ssbo_threads(void) { return omp_get_max_threads(); }
+#else
+int ssbo_threads(void) { return 1; }
+#endif

@@ -1,0 +1,258 @@
+// C-ABI entry points of the ssbh library: context, errors, argument checks
+// and kernel selection.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "ssbh_internal.hpp"
+
+namespace ssbh {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+ssbh_status DevBuf::reserve(size_t need) {
+    if (need <= bytes) return SSBH_OK;
+    size_t grow = std::max(need, bytes + bytes / 2);
+    grow = (grow + 255) & ~(size_t)255;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+        if (e != hipSuccess) {
+            set_error("hipFree failed: %s", hipGetErrorString(e));
+            return SSBH_E_DEVICE;
+        }
+    }
+    hipError_t e = hipMalloc(&ptr, grow);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        set_error("hipMalloc(%zu) failed: %s", grow, hipGetErrorString(e));
+        return SSBH_E_NOMEM;
+    }
+    bytes = grow;
+    return SSBH_OK;
+}
+
+ssbh_status ensure_dynamic_lds(const void *kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return SSBH_OK;
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, size_t>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &d : done)
+        if (d.first == kernel && d.second >= bytes) return SSBH_OK;
+    hipError_t e = hipFuncSetAttribute(
+        kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("kernel needs %zu bytes of LDS: %s", bytes,
+                  hipGetErrorString(e));
+        return SSBH_E_UNSUPPORTED;
+    }
+    done.emplace_back(kernel, bytes);
+    return SSBH_OK;
+}
+
+void DevBuf::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void Workspace::release() {
+    counts.release();
+    offs.release();
+    part.release();
+    plan.release();
+    tiles.release();
+    counters.release();
+}
+
+// Default VALU schedule: 16 rows per lane, 4 wavefronts (4096 rows per
+// tile); columns are split only when the row tiles alone cannot fill the
+// device several times over.
+static ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q) {
+    ValuSchedule s;
+    if (ctx->forced_valu_r) s.r = ctx->forced_valu_r;
+    if (ctx->forced_valu_waves) s.waves = ctx->forced_valu_waves;
+    const double rows = (double)s.rows();
+    const double row_tiles = (double)q.n_sub * std::ceil((double)q.m_cap / rows);
+    const double target = 16.0 * ctx->num_cus;
+    if (ctx->forced_tile_cols) {
+        s.tile_cols = ctx->forced_tile_cols;
+    } else if (row_tiles < target && q.n_sub) {
+        const double mean_words = 2.0 * (double)q.sub_cap / q.n_sub;
+        const double splits = std::ceil(target / std::max(row_tiles, 1.0));
+        double tc = std::ceil(mean_words / splits / 32.0) * 32.0;
+        tc = std::max(tc, 256.0);
+        if (tc < mean_words) s.tile_cols = (uint32_t)std::min(tc, 4.0e9);
+    }
+    s.chunk_cols = 4096;
+    return s;
+}
+
+ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                        hipStream_t stream) {
+    (void)hipGetLastError();   // clear errors left by earlier calls
+    if (q.kernel == SSBH_K_MFMA_I8) {
+        return launch_hash_mfma(ctx, ws, q, MfmaSchedule{}, stream);
+    }
+    if (q.kernel != SSBH_K_AUTO && q.kernel != SSBH_K_VALU)
+        SSBH_INVAL("unknown kernel %u", q.kernel);
+    return launch_hash_valu(ctx, ws, q, choose_valu(ctx, q), stream);
+}
+
+}  // namespace ssbh
+
+using namespace ssbh;
+
+extern "C" {
+
+const char *ssbh_last_error(void) { return g_err; }
+
+ssbh_status ssbh_create(int device, uint64_t hbm_budget_bytes, ssbh_ctx **out) {
+    clear_error();
+    if (!out) SSBH_INVAL("out is null");
+    *out = nullptr;
+    int count = 0;
+    SSBH_CHECK_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        SSBH_INVAL("device %d out of range (%d devices)", device, count);
+    SSBH_CHECK_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    SSBH_CHECK_HIP(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error("device %d is %s; this library is built for gfx950 only",
+                  device, prop.gcnArchName);
+        return SSBH_E_UNSUPPORTED;
+    }
+    ssbh_ctx *c = new ssbh_ctx();
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    if (!hbm_budget_bytes) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+            hbm_budget_bytes = (uint64_t)(fr * 0.8);
+    }
+    c->hbm_budget = hbm_budget_bytes;
+    *out = c;
+    return SSBH_OK;
+}
+
+void ssbh_serve_shutdown(ssbh_ctx *ctx);   // serve.hip
+
+void ssbh_destroy(ssbh_ctx *ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    ssbh_serve_shutdown(ctx);
+    hipDeviceSynchronize();
+    ctx->ws.release();
+    delete ctx;
+}
+
+int ssbh_num_cus(const ssbh_ctx *ctx) { return ctx ? ctx->num_cus : 0; }
+
+ssbh_status ssbh_sample(ssbh_ctx *ctx, const uint64_t *d_in, uint64_t n_bits,
+                        uint32_t n_sub, uint32_t mode, uint64_t sample_key,
+                        const uint32_t *d_assign, uint64_t l_ub,
+                        uint64_t *d_sub, uint64_t sub_capacity_words,
+                        uint64_t *d_len, uint64_t *d_word_off,
+                        int32_t *d_status, void *stream) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    return launch_sample(ctx, ctx->ws, d_in, n_bits, n_sub, mode, sample_key,
+                         d_assign, l_ub, d_sub, sub_capacity_words, d_len,
+                         d_word_off, d_status, (hipStream_t)stream);
+}
+
+ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
+                            uint64_t sub_capacity_words,
+                            const uint64_t *d_len, const uint64_t *d_word_off,
+                            uint32_t n_sub, uint32_t out_rule, uint64_t out_a,
+                            uint64_t out_b, const uint64_t *d_out_len,
+                            const uint64_t *d_seed, uint64_t seed_bits,
+                            uint64_t seed_stride, uint64_t m_cap,
+                            uint32_t kernel, uint64_t *d_out,
+                            uint64_t out_capacity_bits,
+                            uint64_t *d_out_total_bits, int32_t *d_status,
+                            void *stream) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (!d_len || !d_word_off || !d_status || !d_out_total_bits)
+        SSBH_INVAL("d_len, d_word_off, d_out_total_bits and d_status must be "
+                   "non-null");
+    if (n_sub && !d_sub) SSBH_INVAL("d_sub is null");
+    if (out_capacity_bits && !d_out) SSBH_INVAL("d_out is null");
+    if (out_rule == SSBH_OUT_RATIO) {
+        if (out_b == 0) SSBH_INVAL("out_b must be > 0");
+        if (out_a >= (1ull << 24) || out_b >= (1ull << 24))
+            SSBH_INVAL("ratio terms must be below 2^24");
+    } else if (out_rule == SSBH_OUT_EXPLICIT) {
+        if (n_sub && !d_out_len) SSBH_INVAL("explicit lengths need d_out_len");
+    } else if (out_rule != SSBH_OUT_FIXED) {
+        SSBH_INVAL("unknown out_rule %u", out_rule);
+    }
+    if (m_cap == 0 && out_rule == SSBH_OUT_FIXED && out_a > 0)
+        SSBH_INVAL("m_cap must be >= out_a");
+    if (m_cap >= (1ull << 32)) {
+        set_error("m_cap must be below 2^32");
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (sub_capacity_words >= (1ull << 36)) {
+        set_error("sub_capacity_words must be below 2^36");
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (n_sub > 1 && seed_stride) {
+        const long double last = (long double)(n_sub - 1) * seed_stride;
+        if (last > (long double)seed_bits)
+            SSBH_INVAL("seed too short for %u sub-blocks at stride %llu",
+                       n_sub, (unsigned long long)seed_stride);
+    }
+    if (seed_bits && !d_seed) SSBH_INVAL("d_seed is null");
+    if (kernel == SSBH_K_MFMA_I8 && seed_stride != 0)
+        SSBH_INVAL("the MFMA kernel needs a shared seed (seed_stride = 0)");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    HashRequest q{d_sub, sub_capacity_words, d_len, d_word_off, n_sub,
+                  out_rule, out_a, out_b, d_out_len, d_seed, seed_bits,
+                  seed_stride, m_cap, kernel, d_out, out_capacity_bits,
+                  d_out_total_bits, d_status};
+    return launch_hash(ctx, ctx->ws, q, (hipStream_t)stream);
+}
+
+ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
+                               uint64_t *d_seed, uint64_t seed_bits,
+                               void *stream) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (seed_bits && !d_seed) SSBH_INVAL("d_seed is null");
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    return launch_seed(seed_key, d_seed, seed_bits, (hipStream_t)stream);
+}
+
+// Force the VALU schedule (0 = library choice).
+ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
+                                         uint32_t tile_cols) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    ctx->forced_valu_r = r;
+    ctx->forced_valu_waves = waves;
+    ctx->forced_tile_cols = tile_cols;
+    return SSBH_OK;
+}
+
+}  // extern "C"

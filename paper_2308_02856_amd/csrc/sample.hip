@@ -1,0 +1,445 @@
+// Sampling (Sec. III.B step 1) and the abort rule (Sec. III.B step 2,
+// Sec. III.D) on gfx950.
+//
+// i.i.d. / explicit modes: the input is cut into segments of seg_bits bits,
+// one wavefront per segment.
+//   k_hist     V_i for every bit of the segment (recomputed from the
+//              counter-based generator, never stored), LDS histogram ->
+//              counts[seg][j]; also clears the sub-block buffer.
+//   k_scan_*   column scans of counts over segments -> offs[seg][j] (where the
+//              segment's run of sub-block j starts), n_j, W_j, max n_j, abort.
+//   k_scatter  V_i again; a stable rank inside every 64-bit step from a
+//              ballot-based match of equal V_i; the bits are ORed into an LDS
+//              image of the segment sorted by sub-block (stable), then every
+//              run is copied to its place in sub-block j: whole 64-bit words
+//              by plain stores, the two partial end words by atomic OR (they
+//              are shared with the neighbouring segments' runs).  OR into a
+//              zeroed buffer is order independent, so the result is
+//              bit-identical for every schedule.
+// permutation mode: one wavefront gathers 64 bits B[k] = A[pi[k]] per step
+// and writes one 64-bit word with a ballot.
+#include <algorithm>
+
+#include "ssbh_internal.hpp"
+
+namespace ssbh {
+namespace {
+
+constexpr uint32_t kSegChunk = 64;   // segments per partial-sum chunk
+
+struct SampleArgs {
+    const uint64_t *in;
+    uint64_t n;
+    uint32_t ns;
+    uint32_t vbits;          // ceil(log2(ns))
+    uint64_t key;
+    const uint32_t *assign;  // explicit mode
+    uint64_t seg_bits;       // multiple of 64
+    uint32_t nseg;
+    uint32_t nchunk;
+    uint32_t *counts;        // [nseg][ns]
+    uint32_t *offs;          // [nseg][ns]
+    uint32_t *part;          // [nchunk][ns]
+    uint64_t *sub;
+    uint64_t sub_cap;
+    uint64_t *len;
+    uint64_t *woff;
+    uint64_t l_ub;
+    int32_t *status;
+};
+
+template <bool EXPLICIT>
+__device__ __forceinline__ uint32_t sample_v(const SampleArgs &a, uint64_t i) {
+    if constexpr (EXPLICIT) {
+        return a.assign[i];
+    } else {
+        const uint64_t r = splitmix64_at(a.key, i >> 1);
+        const uint32_t u = (i & 1ull) ? (uint32_t)(r >> 32) : (uint32_t)r;
+        return __umulhi(u, a.ns);   // floor(u * ns / 2^32)
+    }
+}
+
+__global__ void k_init_status(int32_t *status) { *status = 0; }
+
+template <bool EXPLICIT>
+__global__ __launch_bounds__(256) void k_hist(SampleArgs a) {
+    extern __shared__ uint32_t lds[];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    // Clear the sub-block buffer (the scatter ORs partial words into it).
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         k < a.sub_cap; k += stride)
+        a.sub[k] = 0ull;
+
+    const uint32_t seg = blockIdx.x * wpb + w;
+    if (seg >= a.nseg) return;      // per-wave exit, no block barriers below
+    uint32_t *hist = lds + (size_t)w * a.ns;
+    for (uint32_t j = lane; j < a.ns; j += 64) hist[j] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
+    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
+    bool bad = false;
+    for (uint64_t i = i0 + lane; i < i1; i += 64) {
+        const uint32_t v = sample_v<EXPLICIT>(a, i);
+        if (v < a.ns) atomicAdd(&hist[v], 1u);
+        else bad = true;
+    }
+    if (bad) atomicExch(a.status, (int32_t)SSBH_E_INVAL);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): LDS atomics done
+    uint32_t *dst = a.counts + (uint64_t)seg * a.ns;
+    for (uint32_t j = lane; j < a.ns; j += 64) dst[j] = hist[j];
+}
+
+// part[c][j] = sum of counts[seg][j] over the segments of chunk c.
+__global__ __launch_bounds__(64) void k_scan_part(SampleArgs a) {
+    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t c = blockIdx.y;
+    if (j >= a.ns) return;
+    const uint32_t s0 = c * kSegChunk, s1 = min(s0 + kSegChunk, a.nseg);
+    uint32_t sum = 0;
+    for (uint32_t s = s0; s < s1; ++s) sum += a.counts[(uint64_t)s * a.ns + j];
+    a.part[(uint64_t)c * a.ns + j] = sum;
+}
+
+// Exclusive scan of part over chunks; n_j.
+__global__ __launch_bounds__(64) void k_scan_mid(SampleArgs a) {
+    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= a.ns) return;
+    uint64_t run = 0;
+    for (uint32_t c = 0; c < a.nchunk; ++c) {
+        const uint32_t t = a.part[(uint64_t)c * a.ns + j];
+        a.part[(uint64_t)c * a.ns + j] = (uint32_t)run;
+        run += t;
+    }
+    a.len[j] = run;
+}
+
+// offs[seg][j]: where segment seg's run of sub-block j starts in sub-block j.
+__global__ __launch_bounds__(64) void k_scan_offs(SampleArgs a) {
+    const uint32_t j = blockIdx.x * 64 + threadIdx.x;
+    const uint32_t c = blockIdx.y;
+    if (j >= a.ns) return;
+    const uint32_t s0 = c * kSegChunk, s1 = min(s0 + kSegChunk, a.nseg);
+    uint32_t run = a.part[(uint64_t)c * a.ns + j];
+    for (uint32_t s = s0; s < s1; ++s) {
+        a.offs[(uint64_t)s * a.ns + j] = run;
+        run += a.counts[(uint64_t)s * a.ns + j];
+    }
+}
+
+// Word offsets W_j, the capacity check and the abort rule (one block).
+__global__ __launch_bounds__(1024) void k_scan_words(SampleArgs a) {
+    __shared__ uint64_t wsum[16];
+    __shared__ uint64_t carry_s;
+    __shared__ uint64_t maxlen_s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) { carry_s = 0; maxlen_s = 0; }
+    __syncthreads();
+    for (uint32_t base = 0; base < a.ns; base += blockDim.x) {
+        const uint32_t j = base + threadIdx.x;
+        const uint64_t nj = j < a.ns ? a.len[j] : 0ull;
+        const uint64_t v = (nj + 63) / 64;
+        uint64_t incl = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += t;
+        }
+        if (lane == 63) wsum[w] = incl;
+        if (nj) atomicMax((unsigned long long *)&maxlen_s,
+                          (unsigned long long)nj);
+        __syncthreads();
+        uint64_t before = 0;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        const uint64_t carry = carry_s;
+        if (j < a.ns) a.woff[j] = carry + before + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t tot = 0;
+            for (int k = 0; k < nw; ++k) tot += wsum[k];
+            carry_s = carry + tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (*a.status == 0) {
+            if (carry_s > a.sub_cap) *a.status = SSBH_E_INVAL;
+            else if (a.l_ub && maxlen_s > a.l_ub)
+                *a.status = SSBH_E_ABORT_OVERSIZE;
+        }
+    }
+}
+
+// 64 bits of the LDS segment image starting at bit p.
+__device__ __forceinline__ uint64_t stage_bits64(const uint32_t *stage,
+                                                 uint32_t p) {
+    const uint32_t w = p >> 5, s = p & 31;
+    const uint64_t lo = (uint64_t)stage[w] | ((uint64_t)stage[w + 1] << 32);
+    if (s == 0) return lo;
+    return (lo >> s) | ((uint64_t)stage[w + 2] << (64 - s));
+}
+
+template <bool EXPLICIT>
+__global__ __launch_bounds__(64) void k_scatter(SampleArgs a) {
+    extern __shared__ uint32_t lds[];
+    if (*a.status) return;
+    uint32_t *cursor = lds;
+    uint32_t *stage = lds + a.ns;
+    const uint32_t seg = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t nsw = (uint32_t)(a.seg_bits / 32) + 4;
+    const uint32_t *cnt = a.counts + (uint64_t)seg * a.ns;
+
+    // Local exclusive prefix of this segment's counts: where each
+    // sub-block's run starts in the segment image.
+    const uint32_t per = (a.ns + 63) / 64;
+    const uint32_t j0 = min(lane * per, a.ns), j1 = min(j0 + per, a.ns);
+    uint32_t s = 0;
+    for (uint32_t j = j0; j < j1; ++j) s += cnt[j];
+    uint32_t incl = s;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    uint32_t run = incl - s;
+    for (uint32_t j = j0; j < j1; ++j) { cursor[j] = run; run += cnt[j]; }
+    for (uint32_t k = lane; k < nsw; k += 64) stage[k] = 0u;
+    __builtin_amdgcn_wave_barrier();
+
+    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
+    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
+    for (uint64_t base = i0; base < i1; base += 64) {
+        const uint64_t i = base + lane;
+        const bool valid = i < i1;
+        const uint32_t v = valid ? sample_v<EXPLICIT>(a, i) : 0u;
+        const uint64_t word = a.in[base >> 6];
+        const uint32_t bit = valid ? (uint32_t)((word >> lane) & 1ull) : 0u;
+        // Lanes holding the same V_i: intersect the ballots of every bit.
+        uint64_t m = ballot64(valid);
+        for (uint32_t b = 0; b < a.vbits; ++b) {
+            const bool t = (v >> b) & 1u;
+            const uint64_t bal = ballot64(t);
+            m &= t ? bal : ~bal;
+        }
+        if (valid) {
+            const uint32_t basepos = cursor[v];
+            const uint32_t pos = basepos + rank_below(m);
+            if (63 - __clzll((long long)m) == lane)
+                cursor[v] = basepos + (uint32_t)__popcll(m);
+            if (bit) atomicOr(&stage[pos >> 5], 1u << (pos & 31));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+
+    // Copy every run to its sub-block.  After the loop cursor[j] is the end
+    // of run j, so run j starts at cursor[j-1].
+    const uint32_t *off = a.offs + (uint64_t)seg * a.ns;
+    for (uint32_t j = lane; j < a.ns; j += 64) {
+        const uint32_t end = cursor[j];
+        const uint32_t start = j ? cursor[j - 1] : 0u;
+        const uint32_t c = end - start;
+        if (!c) continue;
+        const uint64_t dst = 64ull * a.woff[j] + off[j];
+        const uint64_t d0 = dst >> 6, d1 = (dst + c - 1) >> 6;
+        for (uint64_t d = d0; d <= d1; ++d) {
+            const uint64_t lo = max(dst, d * 64), hi = min(dst + c, d * 64 + 64);
+            const uint32_t nb = (uint32_t)(hi - lo);
+            uint64_t bits = stage_bits64(stage, start + (uint32_t)(lo - dst));
+            if (nb < 64) bits &= (1ull << nb) - 1ull;
+            bits <<= (lo - d * 64);
+            if (nb == 64) a.sub[d] = bits;
+            else if (bits) atomicOr((unsigned long long *)&a.sub[d],
+                                    (unsigned long long)bits);
+        }
+    }
+}
+
+// Permutation mode: B[k] = A[pi[k]], sub-block j = B[jL, (j+1)L).
+__global__ __launch_bounds__(256) void k_perm_gather(
+        const uint64_t *in, uint64_t n, const uint32_t *perm, uint32_t ns,
+        uint64_t L, uint64_t wl, uint64_t *sub, int32_t *status) {
+    if (*status) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t total = (uint64_t)ns * wl;
+    bool bad = false;
+    for (uint64_t w = wave; w < total; w += nwave) {
+        const uint64_t j = w / wl, ww = w - j * wl;
+        const uint64_t c = ww * 64 + lane;
+        bool bit = false;
+        if (c < L) {
+            const uint32_t p = perm[j * L + c];
+            if (p < n) bit = (in[p >> 6] >> (p & 63)) & 1ull;
+            else bad = true;
+        }
+        const uint64_t word = ballot64(bit);
+        if (lane == 0) sub[w] = word;
+    }
+    if (bad) atomicExch(status, (int32_t)SSBH_E_INVAL);
+}
+
+__global__ void k_perm_meta(uint32_t ns, uint64_t L, uint64_t wl,
+                            uint64_t l_ub, uint64_t *len, uint64_t *woff,
+                            int32_t *status) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < ns) { len[j] = L; woff[j] = (uint64_t)j * wl; }
+    if (j == 0 && l_ub && L > l_ub) atomicCAS(status, 0, SSBH_E_ABORT_OVERSIZE);
+}
+
+__global__ void k_seed(uint64_t key, uint64_t *seed, uint64_t bits) {
+    const uint64_t nw = (bits + 63) / 64;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nw;
+         t += stride) {
+        uint64_t v = splitmix64_at(key, t);
+        if (t == nw - 1 && (bits & 63)) v &= (1ull << (bits & 63)) - 1ull;
+        seed[t] = v;
+    }
+}
+
+uint32_t ceil_log2(uint32_t x) {
+    uint32_t b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+}  // namespace
+
+ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
+                        hipStream_t stream) {
+    const uint64_t nw = (seed_bits + 63) / 64;
+    if (!nw) return SSBH_OK;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((nw + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_seed, dim3(blocks), dim3(256), 0, stream, key, d_seed,
+                       seed_bits);
+    SSBH_CHECK_HIP(hipGetLastError());
+    return SSBH_OK;
+}
+
+ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
+                          uint64_t n, uint32_t ns, uint32_t mode, uint64_t key,
+                          const uint32_t *d_assign, uint64_t l_ub,
+                          uint64_t *d_sub, uint64_t sub_cap, uint64_t *d_len,
+                          uint64_t *d_woff, int32_t *d_status,
+                          hipStream_t stream) {
+    if (ns == 0) SSBH_INVAL("n_sub must be >= 1");
+    if (!d_sub || !d_len || !d_woff || !d_status)
+        SSBH_INVAL("d_sub, d_len, d_word_off and d_status must be non-null");
+    if (n && !d_in) SSBH_INVAL("d_in is null");
+    if (n >= (1ull << 32)) {
+        set_error("n_bits must be below 2^32");
+        return SSBH_E_UNSUPPORTED;
+    }
+    (void)hipGetLastError();   // clear errors left by earlier calls
+    hipLaunchKernelGGL(k_init_status, dim3(1), dim3(1), 0, stream, d_status);
+    SSBH_CHECK_HIP(hipGetLastError());
+
+    if (mode == SSBH_SAMPLE_PERMUTE) {
+        if (!d_assign) SSBH_INVAL("permutation mode needs d_assign");
+        if (n % ns) SSBH_INVAL("n_sub (%u) must divide n_bits (%llu)", ns,
+                               (unsigned long long)n);
+        const uint64_t L = n / ns, wl = (L + 63) / 64;
+        if (sub_cap < (uint64_t)ns * wl)
+            SSBH_INVAL("sub_capacity_words %llu < %llu",
+                       (unsigned long long)sub_cap,
+                       (unsigned long long)((uint64_t)ns * wl));
+        hipLaunchKernelGGL(k_perm_meta, dim3((ns + 255) / 256), dim3(256), 0,
+                           stream, ns, L, wl, l_ub, d_len, d_woff, d_status);
+        const uint64_t total = (uint64_t)ns * wl;
+        if (total) {
+            const uint64_t waves = std::min<uint64_t>(total, (uint64_t)ctx->num_cus * 32);
+            hipLaunchKernelGGL(k_perm_gather, dim3((uint32_t)((waves + 3) / 4)),
+                               dim3(256), 0, stream, d_in, n, d_assign, ns, L,
+                               wl, d_sub, d_status);
+        }
+        SSBH_CHECK_HIP(hipGetLastError());
+        return SSBH_OK;
+    }
+    if (mode != SSBH_SAMPLE_IID && mode != SSBH_SAMPLE_EXPLICIT)
+        SSBH_INVAL("unknown sampling mode %u", mode);
+    if (mode == SSBH_SAMPLE_EXPLICIT && n && !d_assign)
+        SSBH_INVAL("explicit mode needs d_assign");
+    if (ns > SSBH_MAX_SUB_LDS) {
+        set_error("n_sub %u exceeds %u for this sampling mode", ns,
+                  SSBH_MAX_SUB_LDS);
+        return SSBH_E_UNSUPPORTED;
+    }
+    const uint64_t need = (n + 63) / 64 + ns;
+    if (sub_cap < need)
+        SSBH_INVAL("sub_capacity_words %llu < ceil(n_bits/64)+n_sub = %llu",
+                   (unsigned long long)sub_cap, (unsigned long long)need);
+
+    SampleArgs a{};
+    a.in = d_in; a.n = n; a.ns = ns; a.vbits = ceil_log2(ns); a.key = key;
+    a.assign = d_assign; a.sub = d_sub; a.sub_cap = sub_cap; a.len = d_len;
+    a.woff = d_woff; a.l_ub = l_ub; a.status = d_status;
+    // Segment size: about 32 bits per sub-block per segment (so runs are a
+    // few words long), at least 2^14 bits, LDS image at most 32 KiB.
+    uint64_t seg = 32ull * ns;
+    seg = std::max<uint64_t>(seg, 1ull << 14);
+    seg = std::min<uint64_t>(seg, 1ull << 18);
+    seg = (seg + 63) / 64 * 64;
+    a.seg_bits = seg;
+    a.nseg = (uint32_t)((n + seg - 1) / seg);
+    a.nchunk = (a.nseg + kSegChunk - 1) / kSegChunk;
+    const size_t mat = (size_t)std::max<uint32_t>(a.nseg, 1) * ns * 4;
+    ssbh_status st;
+    if ((st = ws.counts.reserve(mat)) != SSBH_OK) return st;
+    if ((st = ws.offs.reserve(mat)) != SSBH_OK) return st;
+    if ((st = ws.part.reserve((size_t)std::max<uint32_t>(a.nchunk, 1) * ns * 4)) != SSBH_OK)
+        return st;
+    a.counts = ws.counts.as<uint32_t>();
+    a.offs = ws.offs.as<uint32_t>();
+    a.part = ws.part.as<uint32_t>();
+
+    const bool ex = mode == SSBH_SAMPLE_EXPLICIT;
+    // Histogram: wavefronts per block limited by LDS (4 B per sub-block).
+    int wpb = (int)std::min<uint64_t>(4, std::max<uint64_t>(1, (32768u) / ns));
+    const uint32_t hist_blocks = std::max<uint32_t>(
+        1, std::max<uint32_t>((a.nseg + wpb - 1) / wpb,
+                         (uint32_t)std::min<uint64_t>((sub_cap + 255) / 256, 2048)));
+    const size_t hist_lds = (size_t)wpb * ns * 4;
+    const size_t scat_lds = (size_t)ns * 4 + ((size_t)(seg / 32) + 4) * 4;
+    {
+        const void *kh = ex ? (const void *)k_hist<true> : (const void *)k_hist<false>;
+        const void *ksc = ex ? (const void *)k_scatter<true>
+                             : (const void *)k_scatter<false>;
+        if ((st = ensure_dynamic_lds(kh, hist_lds)) != SSBH_OK) return st;
+        if ((st = ensure_dynamic_lds(ksc, scat_lds)) != SSBH_OK) return st;
+    }
+    if (ex)
+        hipLaunchKernelGGL(k_hist<true>, dim3(hist_blocks), dim3(64 * wpb),
+                           hist_lds, stream, a);
+    else
+        hipLaunchKernelGGL(k_hist<false>, dim3(hist_blocks), dim3(64 * wpb),
+                           hist_lds, stream, a);
+    const uint32_t jb = (ns + 63) / 64;
+    if (a.nseg) {
+        hipLaunchKernelGGL(k_scan_part, dim3(jb, a.nchunk), dim3(64), 0,
+                           stream, a);
+    }
+    hipLaunchKernelGGL(k_scan_mid, dim3(jb), dim3(64), 0, stream, a);
+    if (a.nseg) {
+        hipLaunchKernelGGL(k_scan_offs, dim3(jb, a.nchunk), dim3(64), 0,
+                           stream, a);
+    }
+    hipLaunchKernelGGL(k_scan_words, dim3(1), dim3(1024), 0, stream, a);
+    if (a.nseg) {
+        if (ex)
+            hipLaunchKernelGGL(k_scatter<true>, dim3(a.nseg), dim3(64),
+                               scat_lds, stream, a);
+        else
+            hipLaunchKernelGGL(k_scatter<false>, dim3(a.nseg), dim3(64),
+                               scat_lds, stream, a);
+    }
+    SSBH_CHECK_HIP(hipGetLastError());
+    return SSBH_OK;
+}
+
+}  // namespace ssbh

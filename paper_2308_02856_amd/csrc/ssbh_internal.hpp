@@ -1,0 +1,166 @@
+// Internal declarations of the ssbh library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ssbh.h"
+
+namespace ssbh {
+
+// ------------------------------------------------------------- errors ---
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define SSBH_CHECK_HIP(expr)                                                  \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) {                                               \
+            ::ssbh::set_error("%s failed: %s (%s:%d)", #expr,                 \
+                              hipGetErrorString(e_), __FILE__, __LINE__);     \
+            return SSBH_E_DEVICE;                                             \
+        }                                                                     \
+    } while (0)
+
+#define SSBH_INVAL(...)                                                       \
+    do {                                                                      \
+        ::ssbh::set_error(__VA_ARGS__);                                       \
+        return SSBH_E_INVAL;                                                  \
+    } while (0)
+
+// ------------------------------------------------------ device scratch ---
+
+// A growable device buffer owned by a context.  Growing frees the old
+// allocation (hipFree waits for the device), so pointers handed to kernels
+// stay valid for the work already enqueued.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ssbh_status reserve(size_t need);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Scratch used by one sample / hash pipeline.
+struct Workspace {
+    DevBuf counts;     // sampling: per-segment bucket counts  [segs][n_sub]
+    DevBuf offs;       // sampling: per-segment bucket offsets [segs][n_sub]
+    DevBuf part;       // sampling: per-chunk partial sums
+    DevBuf plan;       // hashing: m_j, O_j, tile offsets (3 * n_sub u64)
+    DevBuf tiles;      // hashing: tile list
+    DevBuf counters;   // hashing: tile count, claim counter
+    void release();
+};
+
+// A VALU hash schedule: rows per lane R, waves per workgroup, column words
+// per tile, column words per LDS chunk.
+struct ValuSchedule {
+    int r = 16;
+    int waves = 4;
+    uint32_t tile_cols = 0;   // 0 = whole sub-block
+    uint32_t chunk_cols = 4096;
+    int rows() const { return r * 64 * waves; }
+};
+
+struct MfmaSchedule {
+    int mt = 4;      // 32-row M tiles per wave
+    int nt = 2;      // 32-sub-block N tiles per wave
+    int waves = 4;
+};
+
+struct ServeState;   // serving scheduler (serve.hip)
+
+}  // namespace ssbh
+
+struct ssbh_ctx {
+    int device = 0;
+    int num_cus = 0;
+    size_t lds_per_block = 0;
+    uint64_t hbm_budget = 0;
+    std::mutex mu;                 // guards the default workspace
+    ssbh::Workspace ws;            // scratch of the synchronous entry points
+    std::vector<std::pair<std::string, std::string>> tune_cache;
+    ssbh::ServeState *serve = nullptr;
+    int forced_valu_r = 0;         // tests / autotuner: force a schedule
+    int forced_valu_waves = 0;
+    uint32_t forced_tile_cols = 0;
+};
+
+namespace ssbh {
+
+// Kernel-launch layers (one per source file).
+ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
+                          uint64_t n_bits, uint32_t n_sub, uint32_t mode,
+                          uint64_t key, const uint32_t *d_assign,
+                          uint64_t l_ub, uint64_t *d_sub, uint64_t sub_cap,
+                          uint64_t *d_len, uint64_t *d_woff, int32_t *d_status,
+                          hipStream_t stream);
+
+struct HashRequest {
+    const uint64_t *sub;
+    uint64_t sub_cap;
+    const uint64_t *len;
+    const uint64_t *woff;
+    uint32_t n_sub;
+    uint32_t out_rule;
+    uint64_t out_a, out_b;
+    const uint64_t *out_len;
+    const uint64_t *seed;
+    uint64_t seed_bits;
+    uint64_t stride;
+    uint64_t m_cap;
+    uint32_t kernel;
+    uint64_t *out;
+    uint64_t out_cap_bits;
+    uint64_t *out_total;
+    int32_t *status;
+};
+
+ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                        hipStream_t stream);
+
+ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,
+                             const HashRequest &q, const ValuSchedule &s,
+                             hipStream_t stream);
+
+ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
+                             const HashRequest &q, const MfmaSchedule &s,
+                             hipStream_t stream);
+
+ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
+                        hipStream_t stream);
+
+// Allow `kernel` to take `bytes` of dynamic LDS (needed above 64 KiB).
+ssbh_status ensure_dynamic_lds(const void *kernel, size_t bytes);
+
+// --------------------------------------------------------- device code ---
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output t of the stream
+// seeded with `key` is mix(key + (t + 1) * golden_gamma).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t key, uint64_t t) {
+    uint64_t z = key + (t + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) {
+    return __builtin_amdgcn_ballot_w64(p);
+}
+
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of `m` strictly below the calling lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+}  // namespace ssbh

@@ -1,0 +1,212 @@
+"""Thin ctypes binding of libssbh.so (argument marshalling only).
+
+Every step of the path runs in the library's HIP kernels; this module turns
+torch tensors into device pointers and the current torch stream into a HIP
+stream, and raises on error codes.  Bit strings are torch.int64 tensors that
+hold the library's uint64 words bit for bit.  Importing this module fails
+loudly when the library has not been built: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssbh.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ssbh.h")
+
+OK, PENDING = 0, 1
+E_INVAL, E_ABORT_OVERSIZE, E_NOMEM, E_DEVICE, E_UNKNOWN_JOB, E_UNSUPPORTED = (
+    -1, -2, -3, -4, -5, -6)
+SAMPLE_IID, SAMPLE_PERMUTE, SAMPLE_EXPLICIT = 0, 1, 2
+OUT_FIXED, OUT_RATIO, OUT_EXPLICIT = 0, 1, 2
+K_AUTO, K_VALU, K_MFMA_I8 = 0, 1, 2
+
+_STATUS_NAMES = {OK: "OK", PENDING: "PENDING", E_INVAL: "E_INVAL",
+                 E_ABORT_OVERSIZE: "E_ABORT_OVERSIZE", E_NOMEM: "E_NOMEM",
+                 E_DEVICE: "E_DEVICE", E_UNKNOWN_JOB: "E_UNKNOWN_JOB",
+                 E_UNSUPPORTED: "E_UNSUPPORTED"}
+
+_lib = None
+_vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+
+
+class SsbhError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def header_functions() -> list[str]:
+    """Names of the functions that include/ssbh.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssbh_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.ssbh_last_error.restype = ctypes.c_char_p
+    L.ssbh_last_error.argtypes = []
+    L.ssbh_create.restype = _i32
+    L.ssbh_create.argtypes = [ctypes.c_int, _u64, ctypes.POINTER(_vp)]
+    L.ssbh_destroy.restype = None
+    L.ssbh_destroy.argtypes = [_vp]
+    L.ssbh_num_cus.restype = ctypes.c_int
+    L.ssbh_num_cus.argtypes = [_vp]
+    L.ssbh_sample.restype = _i32
+    L.ssbh_sample.argtypes = [_vp, _vp, _u64, _u32, _u32, _u64, _vp, _u64,
+                              _vp, _u64, _vp, _vp, _vp, _vp]
+    L.ssbh_hash_batch.restype = _i32
+    L.ssbh_hash_batch.argtypes = [_vp, _vp, _u64, _vp, _vp, _u32, _u32, _u64,
+                                  _u64, _vp, _vp, _u64, _u64, _u64, _u32, _vp,
+                                  _u64, _vp, _vp, _vp]
+    L.ssbh_seed_from_key.restype = _i32
+    L.ssbh_seed_from_key.argtypes = [_vp, _u64, _vp, _u64, _vp]
+    L.ssbh_set_schedule.restype = _i32
+    L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32]
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        msg = lib().ssbh_last_error().decode(errors="replace")
+        raise SsbhError(rc, msg)
+    return rc
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def words(n_bits: int) -> int:
+    return (int(n_bits) + 63) // 64
+
+
+class Context:
+    """A library context on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self.device = int(device)
+        self._h = _vp()
+        _check(lib().ssbh_create(self.device, int(hbm_budget),
+                                 ctypes.byref(self._h)))
+        self.num_cus = lib().ssbh_num_cus(self._h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().ssbh_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self):
+        return torch.device("cuda", self.device)
+
+    # ------------------------------------------------------------ sampling
+
+    def sample(self, inp, n_bits: int, n_sub: int, mode: int = SAMPLE_IID,
+               key: int = 0, assign=None, l_ub: int = 0, sub=None,
+               sub_capacity: int | None = None, length=None, word_off=None,
+               status=None, stream=None):
+        """ssbh_sample; returns (sub, len, word_off, status) device tensors."""
+        dev = self._dev()
+        if sub_capacity is None:
+            if mode == SAMPLE_PERMUTE:
+                sub_capacity = n_sub * words(n_bits // max(n_sub, 1))
+            else:
+                sub_capacity = words(n_bits) + n_sub
+        if sub is None:
+            sub = torch.empty(max(1, sub_capacity), dtype=torch.int64, device=dev)
+        if length is None:
+            length = torch.empty(max(1, n_sub), dtype=torch.int64, device=dev)
+        if word_off is None:
+            word_off = torch.empty(max(1, n_sub), dtype=torch.int64, device=dev)
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+        _check(lib().ssbh_sample(self._h, _ptr(inp), int(n_bits), int(n_sub),
+                                 int(mode), int(key) & (2**64 - 1),
+                                 _ptr(assign), int(l_ub), _ptr(sub),
+                                 int(sub_capacity), _ptr(length),
+                                 _ptr(word_off), _ptr(status),
+                                 _stream(stream)))
+        return sub, length, word_off, status
+
+    # ------------------------------------------------------------- hashing
+
+    def hash_batch(self, sub, sub_capacity: int, length, word_off, n_sub: int,
+                   seed, seed_bits: int, m_cap: int, out_rule: int = OUT_FIXED,
+                   out_a: int = 0, out_b: int = 1, out_len=None,
+                   seed_stride: int = 0, kernel: int = K_AUTO, out=None,
+                   out_capacity_bits: int | None = None, total=None,
+                   status=None, stream=None, reset_status: bool = True):
+        """ssbh_hash_batch; returns (out, total_bits, status) device tensors."""
+        dev = self._dev()
+        if out_capacity_bits is None:
+            if out_rule == OUT_FIXED:
+                out_capacity_bits = int(out_a) * int(n_sub)
+            elif out_rule == OUT_RATIO:
+                out_capacity_bits = (64 * int(sub_capacity) * int(out_a)) // int(out_b)
+            else:
+                out_capacity_bits = int(out_len.sum().item())
+        if out is None:
+            out = torch.empty(max(1, words(out_capacity_bits)), dtype=torch.int64,
+                              device=dev)
+        if total is None:
+            total = torch.zeros(1, dtype=torch.int64, device=dev)
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+        elif reset_status:
+            status.zero_()
+        _check(lib().ssbh_hash_batch(
+            self._h, _ptr(sub), int(sub_capacity), _ptr(length),
+            _ptr(word_off), int(n_sub), int(out_rule), int(out_a), int(out_b),
+            _ptr(out_len), _ptr(seed), int(seed_bits), int(seed_stride),
+            int(m_cap), int(kernel), _ptr(out), int(out_capacity_bits),
+            _ptr(total), _ptr(status), _stream(stream)))
+        return out, total, status
+
+    def seed_from_key(self, key: int, seed_bits: int, out=None, stream=None):
+        if out is None:
+            out = torch.empty(max(1, words(seed_bits)), dtype=torch.int64,
+                              device=self._dev())
+        _check(lib().ssbh_seed_from_key(self._h, int(key) & (2**64 - 1),
+                                        _ptr(out), int(seed_bits),
+                                        _stream(stream)))
+        return out
+
+    def set_schedule(self, r: int = 0, waves: int = 0, tile_cols: int = 0):
+        """Force the VALU schedule (0 = library choice); bits do not change."""
+        _check(lib().ssbh_set_schedule(self._h, int(r), int(waves),
+                                       int(tile_cols)))
+
+
+def status_name(code: int) -> str:
+    return _STATUS_NAMES.get(int(code), str(code))
