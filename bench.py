@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 METRIC = ("input Gbit/s hashed, batched sub-block vs plain single-block; "
           "p50/p99 latency")
 CLOCK_GHZ = 2.4          # MI355X peak engine clock
+LANES_PER_CU_CLK = 128   # 32-bit VALU lanes retired per CU per clock
 BITOPS_PER_LANE_OP = 32  # v_bitop3_b32: 32 AND-XOR bit-products per lane
 
 
@@ -47,8 +48,10 @@ def to_host(t):
 
 
 def alu_peak_tbitops(num_cus: int) -> float:
-    # every CU retires 64 lanes of 32-bit VALU work per clock
-    return num_cus * 64 * CLOCK_GHZ * 1e9 * BITOPS_PER_LANE_OP / 1e12
+    """256 CUs x 128 lanes x 2.4 GHz = 78.6 T 32-bit lane-ops/s (the FP32
+    vector peak of 157.3 TFLOP/s counts an FMA as 2); one v_bitop3_b32 lane-op
+    is 32 AND-XOR bit-products."""
+    return num_cus * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9 * BITOPS_PER_LANE_OP / 1e12
 
 
 def kernel_source_digest() -> str:
@@ -236,6 +239,11 @@ def main() -> int:
     ap.add_argument("--cpu-subblocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
+    ap.add_argument("--mode", default="full",
+                    choices=["full", "hash-batched", "hash-single", "copy"],
+                    help="full = the benchmark line; the others run one "
+                         "kernel family only, for profiler passes")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -245,8 +253,27 @@ def main() -> int:
 
     import torch
     from paper_2308_02856_amd import ssbh
+    if args.mode == "copy":
+        # A plain device copy of known size (calibrates HBM byte counters).
+        nb = args.copy_mib << 20
+        a = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": nb, "bytes_written": nb,
+                          "launches": args.steps}), flush=True)
+        return 0
     ctx = ssbh.Context(0)
+    if args.mode == "hash-single":
+        single = run_single(ctx, ssbh, args)
+        print(json.dumps({"mode": args.mode, "ms": single["ms"]}), flush=True)
+        return 0
     res = run_batched(ctx, ssbh, args)
+    if args.mode == "hash-batched":
+        print(json.dumps({"mode": args.mode, "hash_ms": res["hash_ms"],
+                          "sample_ms": res["sample_ms"]}), flush=True)
+        return 0
     single = None if args.skip_single else run_single(ctx, ssbh, args)
 
     peak = alu_peak_tbitops(ctx.num_cus)

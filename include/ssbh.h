@@ -193,10 +193,18 @@ ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
 /* Force the schedule of the VALU hash kernel for later calls on this
  * context: r = rows per lane (8, 16 or 32), waves = wavefronts per workgroup
  * (2, 4 or 8; a workgroup tile is 64*r*waves rows), tile_cols = 32-bit column
- * words per tile (0 = whole sub-block).  0 for r or waves restores the
- * library's choice.  The output bits do not depend on the schedule. */
+ * words per tile (0 = whole sub-block), chunk_cols = column words staged in
+ * LDS at a time (a multiple of r; 0 = library choice).  0 for r or waves
+ * restores the library's choice.  The output bits do not depend on the
+ * schedule. */
 ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
-                              uint32_t tile_cols);
+                              uint32_t tile_cols, uint32_t chunk_cols);
+
+/* Where the VALU hash kernel reads the 32-bit column words of the sub-blocks
+ * from: 0 = staged in LDS with the seed window, 1 = through the scalar data
+ * cache straight into scalar registers (one s_load_dwordx8 per 8 words),
+ * -1 = library choice.  The output bits do not depend on it. */
+ssbh_status ssbh_set_column_path(ssbh_ctx *ctx, int scalar_x);
 
 #ifdef __cplusplus
 }

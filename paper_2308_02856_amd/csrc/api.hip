@@ -98,7 +98,8 @@ static ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q) {
         tc = std::max(tc, 256.0);
         if (tc < mean_words) s.tile_cols = (uint32_t)std::min(tc, 4.0e9);
     }
-    s.chunk_cols = 4096;
+    s.chunk_cols = ctx->forced_chunk_cols ? ctx->forced_chunk_cols : 4096;
+    if (ctx->forced_scalar_x >= 0) s.scalar_x = ctx->forced_scalar_x != 0;
     return s;
 }
 
@@ -246,12 +247,27 @@ ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
 
 // Force the VALU schedule (0 = library choice).
 ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
-                                         uint32_t tile_cols) {
+                              uint32_t tile_cols, uint32_t chunk_cols) {
     clear_error();
     if (!ctx) SSBH_INVAL("ctx is null");
+    if (r && r != 8 && r != 16 && r != 32) SSBH_INVAL("r must be 8, 16 or 32");
+    if (waves && waves != 2 && waves != 4 && waves != 8)
+        SSBH_INVAL("waves must be 2, 4 or 8");
+    if (chunk_cols && (chunk_cols % 32 || chunk_cols > 16384))
+        SSBH_INVAL("chunk_cols must be a multiple of 32 and at most 16384");
     ctx->forced_valu_r = r;
     ctx->forced_valu_waves = waves;
     ctx->forced_tile_cols = tile_cols;
+    ctx->forced_chunk_cols = chunk_cols;
+    return SSBH_OK;
+}
+
+// Column words through LDS (0), the scalar cache (1) or library choice (-1).
+ssbh_status ssbh_set_column_path(ssbh_ctx *ctx, int scalar_x) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (scalar_x < -1 || scalar_x > 1) SSBH_INVAL("scalar_x must be -1, 0 or 1");
+    ctx->forced_scalar_x = scalar_x;
     return SSBH_OK;
 }
 

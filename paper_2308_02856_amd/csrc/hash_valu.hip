@@ -212,7 +212,65 @@ __device__ __forceinline__ void block_of_steps(uint32_t (&acc)[R],
     }
 }
 
-template <int R, int WAVES>
+// Same step sequence with the column words already in scalar registers.
+template <int R>
+__device__ __forceinline__ void block_of_steps_s(uint32_t (&acc)[R],
+                                                 uint32_t (&sw)[R],
+                                                 uint32_t &raw,
+                                                 const uint32_t *wq,
+                                                 const uint32_t (&xs)[R],
+                                                 uint32_t sh) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const uint32_t nxt = wq[u];
+        sw[u] = __builtin_amdgcn_alignbit(nxt, raw, sh);
+        raw = nxt;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            acc[i] = __builtin_amdgcn_bitop3_b32(sw[(u - i + R) % R], xs[u],
+                                                 acc[i], 0x6a);
+    }
+}
+
+typedef const __attribute__((address_space(4))) uint32_t *const_u32p;
+typedef uint32_t u32x8a __attribute__((ext_vector_type(8), aligned(8)));
+typedef const __attribute__((address_space(4))) u32x8a *const_u32x8p;
+
+// R column words starting at an even word index (sub-blocks start on 64-bit
+// words and blocks on multiples of R words), as wide scalar loads.
+template <int R>
+__device__ __forceinline__ void load_x_fast(uint32_t (&xs)[R], const_u32p Xc,
+                                            uint32_t cw) {
+#pragma unroll
+    for (int q = 0; q < R / 8; ++q) {
+        const u32x8a v = *(const_u32x8p)(Xc + cw + 8 * q);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xs[8 * q + u] = v[u];
+    }
+}
+
+// Column words [cw, cw + R) of a sub-block, through the scalar cache.
+// `fast` blocks lie before the end of the tile and before a partial last
+// word; the others mask words past the tile and the bits past n.
+template <int R>
+__device__ __forceinline__ void load_x_block(uint32_t (&xs)[R], const_u32p Xc,
+                                             uint32_t cw, bool fast,
+                                             uint32_t ck1, uint32_t nw,
+                                             uint32_t tailmask) {
+    if (fast) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) xs[u] = Xc[cw + u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            uint32_t x = (cw + u < ck1) ? Xc[cw + u] : 0u;
+            if (cw + u == nw - 1) x &= tailmask;
+            xs[u] = x;
+        }
+    }
+}
+
+template <int R, int WAVES, bool XS>
 __global__ __launch_bounds__(64 * WAVES) void k_toeplitz_valu(ValuArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t tile_s;
@@ -265,11 +323,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_toeplitz_valu(ValuArgs a) {
                 const int64_t g = lo_w + k;
                 win[k] = (g >= 0 && g < a.seed_w32) ? a.seed32[g] : 0u;
             }
-            for (uint32_t k = threadIdx.x; k < ckend - ck0; k += 64 * WAVES) {
-                const uint32_t cw = ck0 + k;
-                uint32_t x = cw < ck1 ? X[cw] : 0u;
-                if (cw == nw - 1) x &= tailmask;
-                xw[k] = x;
+            if constexpr (!XS) {
+                for (uint32_t k = threadIdx.x; k < ckend - ck0;
+                     k += 64 * WAVES) {
+                    const uint32_t cw = ck0 + k;
+                    uint32_t x = cw < ck1 ? X[cw] : 0u;
+                    if (cw == nw - 1) x &= tailmask;
+                    xw[k] = x;
+                }
             }
             __syncthreads();
             if (active) {
@@ -284,11 +345,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_toeplitz_valu(ValuArgs a) {
                     }
                 }
                 raw = win[qb + (int)ck0];
-                for (uint32_t k = 0; k < nblk; ++k) {
-                    const uint32_t cw = ck0 + k * R;
-                    block_of_steps<R>(acc, sw, raw, win + qb + cw + 1,
-                                      reinterpret_cast<const uint4 *>(xw + k * R),
-                                      sh);
+                if constexpr (XS) {
+                    const const_u32p Xc = (const_u32p)X;
+                    const uint32_t fast_end =
+                        (ck1 < nw || tailmask == ~0u) ? ck1 : nw - 1;
+                    uint32_t k = 0;
+                    for (; k < nblk && ck0 + (k + 1) * R <= fast_end; ++k) {
+                        const uint32_t cw = ck0 + k * R;
+                        uint32_t xs[R];
+                        load_x_fast<R>(xs, Xc, cw);
+                        block_of_steps_s<R>(acc, sw, raw, win + qb + cw + 1,
+                                            xs, sh);
+                    }
+                    for (; k < nblk; ++k) {
+                        const uint32_t cw = ck0 + k * R;
+                        uint32_t xs[R];
+                        load_x_block<R>(xs, Xc, cw, false, ck1, nw, tailmask);
+                        block_of_steps_s<R>(acc, sw, raw, win + qb + cw + 1,
+                                            xs, sh);
+                    }
+                } else {
+                    for (uint32_t k = 0; k < nblk; ++k) {
+                        const uint32_t cw = ck0 + k * R;
+                        block_of_steps<R>(
+                            acc, sw, raw, win + qb + cw + 1,
+                            reinterpret_cast<const uint4 *>(xw + k * R), sh);
+                    }
                 }
             }
             __syncthreads();
@@ -323,11 +405,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_toeplitz_valu(ValuArgs a) {
     }
 }
 
-template <int R, int WAVES>
+template <int R, int WAVES, bool XS>
 ssbh_status run_valu(ssbh_ctx *ctx, const ValuArgs &va, hipStream_t stream) {
     const size_t lds = ((size_t)va.chunk + R +
                         (size_t)WAVES * 64 * R / 32 + va.chunk + 4 * R + 8) * 4;
-    auto kern = k_toeplitz_valu<R, WAVES>;
+    auto kern = k_toeplitz_valu<R, WAVES, XS>;
     ssbh_status st = ensure_dynamic_lds((const void *)kern, lds);
     if (st != SSBH_OK) return st;
     int per_cu = 0;
@@ -424,13 +506,18 @@ ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,
     chunk = (chunk + s.r - 1) / s.r * s.r;
     va.chunk = chunk;
 #define SSBH_VALU_CASE(RR, WW)                                                \
-    if (s.r == RR && s.waves == WW) return run_valu<RR, WW>(ctx, va, stream);
+    if (s.r == RR && s.waves == WW)                                           \
+        return s.scalar_x ? run_valu<RR, WW, true>(ctx, va, stream)           \
+                          : run_valu<RR, WW, false>(ctx, va, stream);
+    SSBH_VALU_CASE(8, 2)
     SSBH_VALU_CASE(8, 4)
-    SSBH_VALU_CASE(16, 4)
-    SSBH_VALU_CASE(32, 4)
+    SSBH_VALU_CASE(8, 8)
     SSBH_VALU_CASE(16, 2)
-    SSBH_VALU_CASE(32, 2)
+    SSBH_VALU_CASE(16, 4)
     SSBH_VALU_CASE(16, 8)
+    SSBH_VALU_CASE(32, 2)
+    SSBH_VALU_CASE(32, 4)
+    SSBH_VALU_CASE(32, 8)
 #undef SSBH_VALU_CASE
     set_error("unsupported VALU schedule R=%d waves=%d", s.r, s.waves);
     return SSBH_E_UNSUPPORTED;

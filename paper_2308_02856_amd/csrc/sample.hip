@@ -182,6 +182,49 @@ __device__ __forceinline__ uint64_t stage_bits64(const uint32_t *stage,
     return (lo >> s) | ((uint64_t)stage[w + 2] << (64 - s));
 }
 
+// Input words for a run of 64 consecutive 64-bit steps: lane l holds word
+// w0 + l (0 past the end); step k of the run reads it with two readlanes.
+__device__ __forceinline__ uint64_t load_word_group(const uint64_t *in,
+                                                    uint64_t w0, uint64_t nw,
+                                                    int lane) {
+    const uint64_t w = w0 + (uint64_t)lane;
+    return w < nw ? in[w] : 0ull;
+}
+
+__device__ __forceinline__ uint64_t word_of_step(uint64_t group, uint32_t k) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)group, (int)k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(group >> 32), (int)k);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Copy every run of the segment image to its sub-block.  After the scatter
+// loop cursor[j] is the end of run j, so run j starts at cursor[j-1].  Whole
+// 64-bit destination words are stored; the partial end words are ORed (they
+// are shared with the neighbouring segments' runs of the same sub-block).
+__device__ __forceinline__ void flush_runs(const SampleArgs &a, uint32_t seg,
+                                           const uint32_t *cursor,
+                                           const uint32_t *stage, int lane) {
+    const uint32_t *off = a.offs + (uint64_t)seg * a.ns;
+    for (uint32_t j = lane; j < a.ns; j += 64) {
+        const uint32_t end = cursor[j];
+        const uint32_t start = j ? cursor[j - 1] : 0u;
+        const uint32_t c = end - start;
+        if (!c) continue;
+        const uint64_t dst = 64ull * a.woff[j] + off[j];
+        const uint64_t d0 = dst >> 6, d1 = (dst + c - 1) >> 6;
+        for (uint64_t d = d0; d <= d1; ++d) {
+            const uint64_t lo = max(dst, d * 64), hi = min(dst + c, d * 64 + 64);
+            const uint32_t nb = (uint32_t)(hi - lo);
+            uint64_t bits = stage_bits64(stage, start + (uint32_t)(lo - dst));
+            if (nb < 64) bits &= (1ull << nb) - 1ull;
+            bits <<= (lo - d * 64);
+            if (nb == 64) a.sub[d] = bits;
+            else if (bits) atomicOr((unsigned long long *)&a.sub[d],
+                                    (unsigned long long)bits);
+        }
+    }
+}
+
 template <bool EXPLICIT>
 __global__ __launch_bounds__(64) void k_scatter(SampleArgs a) {
     extern __shared__ uint32_t lds[];
@@ -211,11 +254,19 @@ __global__ __launch_bounds__(64) void k_scatter(SampleArgs a) {
 
     const uint64_t i0 = (uint64_t)seg * a.seg_bits;
     const uint64_t i1 = min(i0 + a.seg_bits, a.n);
+    const uint64_t nw_in = (a.n + 63) / 64;
+    uint64_t grp = load_word_group(a.in, i0 >> 6, nw_in, lane);
+    uint64_t grp_next = load_word_group(a.in, (i0 >> 6) + 64, nw_in, lane);
     for (uint64_t base = i0; base < i1; base += 64) {
         const uint64_t i = base + lane;
         const bool valid = i < i1;
+        const uint32_t k = (uint32_t)((base - i0) >> 6) & 63u;
+        if (k == 0 && base != i0) {
+            grp = grp_next;
+            grp_next = load_word_group(a.in, (base >> 6) + 64, nw_in, lane);
+        }
         const uint32_t v = valid ? sample_v<EXPLICIT>(a, i) : 0u;
-        const uint64_t word = a.in[base >> 6];
+        const uint64_t word = word_of_step(grp, k);
         const uint32_t bit = valid ? (uint32_t)((word >> lane) & 1ull) : 0u;
         // Lanes holding the same V_i: intersect the ballots of every bit.
         uint64_t m = ballot64(valid);
@@ -236,27 +287,82 @@ __global__ __launch_bounds__(64) void k_scatter(SampleArgs a) {
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_wave_barrier();
 
-    // Copy every run to its sub-block.  After the loop cursor[j] is the end
-    // of run j, so run j starts at cursor[j-1].
-    const uint32_t *off = a.offs + (uint64_t)seg * a.ns;
-    for (uint32_t j = lane; j < a.ns; j += 64) {
-        const uint32_t end = cursor[j];
-        const uint32_t start = j ? cursor[j - 1] : 0u;
-        const uint32_t c = end - start;
-        if (!c) continue;
-        const uint64_t dst = 64ull * a.woff[j] + off[j];
-        const uint64_t d0 = dst >> 6, d1 = (dst + c - 1) >> 6;
-        for (uint64_t d = d0; d <= d1; ++d) {
-            const uint64_t lo = max(dst, d * 64), hi = min(dst + c, d * 64 + 64);
-            const uint32_t nb = (uint32_t)(hi - lo);
-            uint64_t bits = stage_bits64(stage, start + (uint32_t)(lo - dst));
-            if (nb < 64) bits &= (1ull << nb) - 1ull;
-            bits <<= (lo - d * 64);
-            if (nb == 64) a.sub[d] = bits;
-            else if (bits) atomicOr((unsigned long long *)&a.sub[d],
-                                    (unsigned long long)bits);
-        }
+    flush_runs(a, seg, cursor, stage, lane);
+}
+
+// The same scatter with an LDS match table instead of the ballot rounds:
+// every lane ORs its lane bit into mask[V_i]; reading mask[V_i] back gives
+// the lanes of this step that share V_i (LDS instructions of one wavefront
+// execute in order, so the read sees every OR of the instruction before it).
+// The highest lane of each group advances the cursor and clears the entry.
+template <bool EXPLICIT>
+__global__ __launch_bounds__(64) void k_scatter_tab(SampleArgs a) {
+    extern __shared__ __align__(8) uint32_t lds[];
+    if (*a.status) return;
+    uint64_t *mask = reinterpret_cast<uint64_t *>(lds);
+    uint32_t *cursor = lds + 2 * a.ns;
+    uint32_t *stage = cursor + a.ns;
+    const uint32_t seg = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t nsw = (uint32_t)(a.seg_bits / 32) + 4;
+    const uint32_t *cnt = a.counts + (uint64_t)seg * a.ns;
+
+    const uint32_t per = (a.ns + 63) / 64;
+    const uint32_t j0 = min(lane * per, a.ns), j1 = min(j0 + per, a.ns);
+    uint32_t s = 0;
+    for (uint32_t j = j0; j < j1; ++j) s += cnt[j];
+    uint32_t incl = s;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
     }
+    uint32_t run = incl - s;
+    for (uint32_t j = j0; j < j1; ++j) {
+        cursor[j] = run;
+        run += cnt[j];
+        mask[j] = 0ull;
+    }
+    for (uint32_t k = lane; k < nsw; k += 64) stage[k] = 0u;
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+
+    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
+    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
+    const uint64_t me = 1ull << lane;
+    const uint64_t nw_in = (a.n + 63) / 64;
+    uint64_t grp = load_word_group(a.in, i0 >> 6, nw_in, lane);
+    uint64_t grp_next = load_word_group(a.in, (i0 >> 6) + 64, nw_in, lane);
+    uint32_t v_next = (i0 + lane < i1) ? sample_v<EXPLICIT>(a, i0 + lane) : 0u;
+    for (uint64_t base = i0; base < i1; base += 64) {
+        const uint64_t i = base + lane;
+        const bool valid = i < i1;
+        const uint32_t v = v_next;
+        const uint32_t k = (uint32_t)((base - i0) >> 6) & 63u;
+        if (k == 0 && base != i0) {
+            grp = grp_next;
+            grp_next = load_word_group(a.in, (base >> 6) + 64, nw_in, lane);
+        }
+        const uint64_t word = word_of_step(grp, k);
+        if (valid) atomicOr((unsigned long long *)&mask[v], (unsigned long long)me);
+        // Next step's draw overlaps the LDS round trip.
+        const uint64_t in = i + 64;
+        v_next = (in < i1) ? sample_v<EXPLICIT>(a, in) : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            const uint64_t m = mask[v];
+            const uint32_t basepos = cursor[v];
+            const uint32_t pos = basepos + rank_below(m);
+            if (63 - __clzll((long long)m) == lane) {
+                cursor[v] = basepos + (uint32_t)__popcll(m);
+                mask[v] = 0ull;
+            }
+            if ((word >> lane) & 1ull) atomicOr(&stage[pos >> 5], 1u << (pos & 31));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    flush_runs(a, seg, cursor, stage, lane);
 }
 
 // Permutation mode: B[k] = A[pi[k]], sub-block j = B[jL, (j+1)L).
@@ -406,12 +512,20 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
                          (uint32_t)std::min<uint64_t>((sub_cap + 255) / 256, 2048)));
     const size_t hist_lds = (size_t)wpb * ns * 4;
     const size_t scat_lds = (size_t)ns * 4 + ((size_t)(seg / 32) + 4) * 4;
+    const size_t tab_lds = scat_lds + (size_t)ns * 8;
+    const bool use_tab = tab_lds <= 48 * 1024;
     {
         const void *kh = ex ? (const void *)k_hist<true> : (const void *)k_hist<false>;
         const void *ksc = ex ? (const void *)k_scatter<true>
                              : (const void *)k_scatter<false>;
         if ((st = ensure_dynamic_lds(kh, hist_lds)) != SSBH_OK) return st;
-        if ((st = ensure_dynamic_lds(ksc, scat_lds)) != SSBH_OK) return st;
+        const void *kt = ex ? (const void *)k_scatter_tab<true>
+                            : (const void *)k_scatter_tab<false>;
+        if (use_tab) {
+            if ((st = ensure_dynamic_lds(kt, tab_lds)) != SSBH_OK) return st;
+        } else if ((st = ensure_dynamic_lds(ksc, scat_lds)) != SSBH_OK) {
+            return st;
+        }
     }
     if (ex)
         hipLaunchKernelGGL(k_hist<true>, dim3(hist_blocks), dim3(64 * wpb),
@@ -431,7 +545,13 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     }
     hipLaunchKernelGGL(k_scan_words, dim3(1), dim3(1024), 0, stream, a);
     if (a.nseg) {
-        if (ex)
+        if (use_tab && ex)
+            hipLaunchKernelGGL(k_scatter_tab<true>, dim3(a.nseg), dim3(64),
+                               tab_lds, stream, a);
+        else if (use_tab)
+            hipLaunchKernelGGL(k_scatter_tab<false>, dim3(a.nseg), dim3(64),
+                               tab_lds, stream, a);
+        else if (ex)
             hipLaunchKernelGGL(k_scatter<true>, dim3(a.nseg), dim3(64),
                                scat_lds, stream, a);
         else

@@ -64,6 +64,7 @@ struct ValuSchedule {
     int waves = 4;
     uint32_t tile_cols = 0;   // 0 = whole sub-block
     uint32_t chunk_cols = 4096;
+    bool scalar_x = false;    // column words through the scalar cache
     int rows() const { return r * 64 * waves; }
 };
 
@@ -89,6 +90,8 @@ struct ssbh_ctx {
     int forced_valu_r = 0;         // tests / autotuner: force a schedule
     int forced_valu_waves = 0;
     uint32_t forced_tile_cols = 0;
+    uint32_t forced_chunk_cols = 0;
+    int forced_scalar_x = -1;      // -1 = library choice
 };
 
 namespace ssbh {

@@ -73,7 +73,9 @@ def lib() -> ctypes.CDLL:
     L.ssbh_seed_from_key.restype = _i32
     L.ssbh_seed_from_key.argtypes = [_vp, _u64, _vp, _u64, _vp]
     L.ssbh_set_schedule.restype = _i32
-    L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32]
+    L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32, _u32]
+    L.ssbh_set_column_path.restype = _i32
+    L.ssbh_set_column_path.argtypes = [_vp, ctypes.c_int]
     _lib = L
     return L
 
@@ -202,10 +204,15 @@ class Context:
                                         _stream(stream)))
         return out
 
-    def set_schedule(self, r: int = 0, waves: int = 0, tile_cols: int = 0):
+    def set_schedule(self, r: int = 0, waves: int = 0, tile_cols: int = 0,
+                     chunk_cols: int = 0):
         """Force the VALU schedule (0 = library choice); bits do not change."""
         _check(lib().ssbh_set_schedule(self._h, int(r), int(waves),
-                                       int(tile_cols)))
+                                       int(tile_cols), int(chunk_cols)))
+
+    def set_column_path(self, scalar_x: int = -1):
+        """Column words via LDS (0), scalar loads (1) or library choice (-1)."""
+        _check(lib().ssbh_set_column_path(self._h, int(scalar_x)))
 
 
 def status_name(code: int) -> str:
