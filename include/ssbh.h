@@ -188,6 +188,65 @@ ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
                                uint64_t *d_seed, uint64_t seed_bits,
                                void *stream);
 
+/* ------------------------------------------------------------ serving --- */
+
+/* One extraction job (the whole method of Sec. III.B on one input block):
+ * i.i.d. sampling into n_sub sub-blocks with the abort threshold l_ub,
+ * a fresh uniform seed drawn on the device from seed_key, a Toeplitz hash of
+ * every sub-block with its OWN seed window (independent hash functions, Sec.
+ * III.B step 3) and the concatenation of the outputs.
+ *
+ * Sizes fixed from the job's parameters (so the result is a function of the
+ * job alone):  n_cap = l_ub (if l_ub = 0 the library uses
+ * l_ub = ceil(n/n_sub + 8*sqrt(n/n_sub)) + 64);  m_cap = the output rule
+ * applied to n_cap;  seed stride S = n_cap + m_cap - 1;  seed length
+ * n_sub * S bits (word t of the seed is output t of the SplitMix64 stream
+ * keyed by seed_key, as in ssbh_seed_from_key). */
+typedef struct {
+    const uint64_t *in;      /* input bits A^N                               */
+    int in_on_device;        /* 1: `in` is device memory, already written
+                                when ssbh_submit is called, valid until
+                                ssbh_poll returns a terminal status;
+                                0: host memory (pinned for an overlapped
+                                copy), copied at admission                   */
+    uint64_t n_bits;         /* N < 2^32                                     */
+    uint32_t n_sub;          /* N_S <= SSBH_MAX_SUB_LDS                      */
+    uint64_t sample_key;     /* key of the V_i draws                         */
+    uint64_t l_ub;           /* L_S^UB (0 = library default above)           */
+    uint32_t out_rule;       /* SSBH_OUT_FIXED or SSBH_OUT_RATIO             */
+    uint64_t out_a, out_b;
+    uint64_t seed_key;       /* key of the job's fresh seed                  */
+    uint64_t *out;           /* result buffer: >= ssbh_job_out_words words   */
+    int out_on_device;       /* 1: `out` is device memory; 0: host memory
+                                (pinned for an overlapped copy)              */
+} ssbh_job;
+
+typedef struct {
+    int32_t status;          /* SSBH_OK, SSBH_E_ABORT_OVERSIZE, ...          */
+    uint64_t out_bits;       /* total output length sum_j m_j               */
+    uint64_t device_bytes;   /* HBM the job held while admitted              */
+    double t_submit, t_admit, t_done;   /* seconds, host steady clock        */
+} ssbh_result;
+
+/* Words the `out` buffer of a job must hold: ceil((floor(n*a/b) + 64)/64)
+ * for the ratio rule, ceil((n_sub*a + 64)/64) for the fixed rule. */
+uint64_t ssbh_job_out_words(const ssbh_job *job);
+
+/* Queue a job; never blocks on the device.  Jobs are admitted in FIFO order
+ * as soon as a stream slot and enough of the context's HBM budget are free
+ * (continuous batching: admitted jobs run concurrently on separate streams).
+ * SSBH_E_NOMEM: the job alone exceeds the budget; SSBH_E_INVAL: bad job. */
+ssbh_status ssbh_submit(ssbh_ctx *ctx, const ssbh_job *job, uint64_t *job_id);
+
+/* SSBH_PENDING while queued or running; otherwise the job's terminal status
+ * (also in res->status), its output already written to job->out, and the id
+ * is released.  SSBH_E_UNKNOWN_JOB for an unknown or released id. */
+ssbh_status ssbh_poll(ssbh_ctx *ctx, uint64_t job_id, ssbh_result *res);
+
+/* Counters of the serving scheduler: jobs queued, running, finished. */
+ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
+                              uint64_t *running, uint64_t *finished);
+
 /* ------------------------------------------------------------- tuning --- */
 
 /* Force the schedule of the VALU hash kernel for later calls on this
@@ -199,6 +258,12 @@ ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
  * schedule. */
 ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
                               uint32_t tile_cols, uint32_t chunk_cols);
+
+/* Force the schedule of the int8 matrix-core kernel: mt = 32-row tiles per
+ * wavefront, nt = 32-sub-block tiles per wavefront, wm = wavefronts per
+ * workgroup (supported: (8,2,4), (4,4,4), (4,2,4), (8,1,4)); 0s restore the
+ * library's choice.  The output bits do not depend on it. */
+ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm);
 
 /* Where the VALU hash kernel reads the 32-bit column words of the sub-blocks
  * from: 0 = staged in LDS with the seed window, 1 = through the scalar data

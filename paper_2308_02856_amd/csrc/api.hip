@@ -24,6 +24,11 @@ void clear_error() { g_err[0] = 0; }
 
 ssbh_status DevBuf::reserve(size_t need) {
     if (need <= bytes) return SSBH_OK;
+    if (external) {
+        set_error("scratch lent by the serving arena is too small (%zu < %zu)",
+                  bytes, need);
+        return SSBH_E_NOMEM;
+    }
     size_t grow = std::max(need, bytes + bytes / 2);
     grow = (grow + 255) & ~(size_t)255;
     if (ptr) {
@@ -65,7 +70,7 @@ ssbh_status ensure_dynamic_lds(const void *kernel, size_t bytes) {
 }
 
 void DevBuf::release() {
-    if (ptr) hipFree(ptr);
+    if (ptr && !external) hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
 }
@@ -82,7 +87,7 @@ void Workspace::release() {
 // Default VALU schedule: 16 rows per lane, 4 wavefronts (4096 rows per
 // tile); columns are split only when the row tiles alone cannot fill the
 // device several times over.
-static ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q) {
+ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q) {
     ValuSchedule s;
     if (ctx->forced_valu_r) s.r = ctx->forced_valu_r;
     if (ctx->forced_valu_waves) s.waves = ctx->forced_valu_waves;
@@ -107,7 +112,13 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                         hipStream_t stream) {
     (void)hipGetLastError();   // clear errors left by earlier calls
     if (q.kernel == SSBH_K_MFMA_I8) {
-        return launch_hash_mfma(ctx, ws, q, MfmaSchedule{}, stream);
+        MfmaSchedule ms;
+        if (ctx->forced_mfma[0]) {
+            ms.mt = ctx->forced_mfma[0];
+            ms.nt = ctx->forced_mfma[1];
+            ms.wm = ctx->forced_mfma[2];
+        }
+        return launch_hash_mfma(ctx, ws, q, ms, stream);
     }
     if (q.kernel != SSBH_K_AUTO && q.kernel != SSBH_K_VALU)
         SSBH_INVAL("unknown kernel %u", q.kernel);
@@ -259,6 +270,15 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
     ctx->forced_valu_waves = waves;
     ctx->forced_tile_cols = tile_cols;
     ctx->forced_chunk_cols = chunk_cols;
+    return SSBH_OK;
+}
+
+ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    ctx->forced_mfma[0] = mt;
+    ctx->forced_mfma[1] = nt;
+    ctx->forced_mfma[2] = wm;
     return SSBH_OK;
 }
 

@@ -1,10 +1,315 @@
-// Shared-seed contraction on int8 matrix cores - placeholder.
+// Shared-seed contraction on the int8 matrix cores of gfx950.
+//
+// With one seed shared by all sub-blocks (stride S = 0), every T_j is the
+// top-left corner of one M x n_max Toeplitz matrix T[r][c] = s[c - r + M - 1]
+// (Sec. I), so hashing a group of sub-blocks is one dense product
+//     K = (T . [x_j0 ... x_j0+B-1]) mod 2
+// over 0/1 values.  v_mfma_i32_32x32x32_i8 multiplies 0/1 bytes and sums in
+// int32; only the low bit of each sum is kept (int32 wrap-around keeps the
+// parity exact for any length).  Columns past n_j are zero and rows past m_j
+// are dropped, so uneven sizes share one launch.
+//
+// Operands are built in registers from bit-packed data; T never exists in
+// memory.  A-operand lane l (row i = l%32, k = 16*(l/32) + byte) needs 16
+// consecutive seed bits; rows 32 apart at columns 32 apart need the same bits,
+// so a wave that owns MT row tiles makes ONE new A operand per K step and
+// rotates the others (diagonal constancy).  B-operand lane l (sub-block
+// l%32) takes 16 data bits of its sub-block.  Bits become 0/1 bytes with one
+// multiply per nibble: (nib * 0x204081) & 0x01010101.
+#include <algorithm>
+
 #include "ssbh_internal.hpp"
 
 namespace ssbh {
-ssbh_status launch_hash_mfma(ssbh_ctx *, Workspace &, const HashRequest &,
-                             const MfmaSchedule &, hipStream_t) {
-    set_error("MFMA kernel not built");
+
+ssbh_status plan_only(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                      hipStream_t stream);
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kKC = 2048;          // columns staged per chunk
+constexpr int kKCW = kKC / 32;     // 32-bit words per sub-block per chunk
+
+struct MfmaArgs {
+    const uint32_t *sub32;
+    const uint64_t *len, *woff, *mlen, *ooff;
+    const uint32_t *seed32;
+    int64_t seed_w32;
+    uint64_t mcap;
+    uint32_t ns;
+    uint32_t m_tiles;
+    uint32_t *out32;
+    const int32_t *status;
+};
+
+// Bits base .. base+15 of b -> 16 bytes of 0/1 (byte t = bit base+t).
+__device__ __forceinline__ v4i expand16(uint32_t b, uint32_t base = 0) {
+    v4i r;
+    r.x = (int)((__builtin_amdgcn_ubfe(b, base, 4) * 0x204081u) & 0x01010101u);
+    r.y = (int)((__builtin_amdgcn_ubfe(b, base + 4, 4) * 0x204081u) & 0x01010101u);
+    r.z = (int)((__builtin_amdgcn_ubfe(b, base + 8, 4) * 0x204081u) & 0x01010101u);
+    r.w = (int)((__builtin_amdgcn_ubfe(b, base + 12, 4) * 0x204081u) & 0x01010101u);
+    return r;
+}
+
+// Workgroup tile: BM = 32*MT*WM rows x BN = 32*NT sub-blocks; every wave
+// owns MT row tiles and all NT sub-block tiles.
+template <int MT, int NT, int WM>
+struct MfmaTile {
+    static constexpr int BM = 32 * MT * WM;
+    static constexpr int BN = 32 * NT;
+    static constexpr int NTH = 64 * WM;
+    static constexpr int XS = kKCW + 1;                 // padded row stride
+    static constexpr int WINW = (BM + kKC) / 32 + MT + 6;
+    static constexpr int PFX = BN * kKCW / NTH;         // words per thread
+    static constexpr int PFW = (WINW + NTH - 1) / NTH;  // window words/thread
+};
+
+template <int MT, int NT, int WM>
+__global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
+    using TT = MfmaTile<MT, NT, WM>;
+    constexpr int BM = TT::BM, BN = TT::BN, NTH = TT::NTH, XS = TT::XS;
+    constexpr int WINW = TT::WINW, PFX = TT::PFX, PFW = TT::PFW;
+    static_assert(BN * kKCW % NTH == 0, "staging must divide evenly");
+    __shared__ uint32_t xs[BN * XS];
+    __shared__ uint32_t win[WINW];
+    __shared__ uint64_t woff_s[BN];
+    __shared__ uint32_t nw_s[BN], tail_s[BN];
+    __shared__ uint64_t nmax_s, mmax_s;
+    if (*a.status) return;
+
+    const uint32_t mt = blockIdx.x % a.m_tiles;
+    const uint32_t grp = blockIdx.x / a.m_tiles;
+    const int64_t R0 = (int64_t)mt * BM;
+    const uint32_t J0 = grp * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, li = lane & 31;
+
+    if (threadIdx.x == 0) { nmax_s = 0; mmax_s = 0; }
+    __syncthreads();
+    for (int t = threadIdx.x; t < BN; t += NTH) {
+        const uint32_t j = J0 + t;
+        uint64_t n = 0, m = 0, wo = 0;
+        if (j < a.ns) { n = a.len[j]; m = a.mlen[j]; wo = a.woff[j]; }
+        woff_s[t] = wo;
+        nw_s[t] = (uint32_t)((n + 31) / 32);
+        tail_s[t] = (n & 31) ? ((1u << (n & 31)) - 1u) : ~0u;
+        if (n) atomicMax((unsigned long long *)&nmax_s, (unsigned long long)n);
+        if (m) atomicMax((unsigned long long *)&mmax_s, (unsigned long long)m);
+    }
+    __syncthreads();
+    const uint64_t nmax = nmax_s, mmax = mmax_s;
+    if (nmax == 0 || (uint64_t)R0 >= mmax) return;   // uniform
+    const uint32_t nwords = (uint32_t)((nmax + 31) / 32);
+    const int64_t R0w = R0 + (int64_t)wave * 32 * MT;   // wave's first row
+
+    // Register prefetch of one chunk: column words and seed window.
+    uint32_t pfx[PFX], pfw[PFW];
+    auto window_lo = [&](uint32_t cw0) -> int64_t {
+        // Lowest seed bit of the chunk: column 32*cw0, row R0+BM-1; the first
+        // chunk also needs MT-1 earlier A operands.
+        const int64_t lo = 32 * (int64_t)cw0 - (R0 + BM - 1) + (int64_t)a.mcap -
+                           1 - (cw0 == 0 ? 32 * (MT - 1) : 0);
+        return lo >> 5;
+    };
+    auto prefetch = [&](uint32_t cw0) {
+#pragma unroll
+        for (int i = 0; i < PFX; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            const int jl = t / kKCW, w = t - jl * kKCW;
+            const uint32_t cw = cw0 + w;
+            uint32_t x = 0u;
+            if (cw < nw_s[jl]) {
+                x = a.sub32[2 * woff_s[jl] + cw];
+                if (cw == nw_s[jl] - 1) x &= tail_s[jl];
+            }
+            pfx[i] = x;
+        }
+        const int64_t lo_w = window_lo(cw0);
+#pragma unroll
+        for (int i = 0; i < PFW; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            const int64_t g = lo_w + t;
+            pfw[i] = (t < WINW && g >= 0 && g < a.seed_w32) ? a.seed32[g] : 0u;
+        }
+    };
+
+    v16i acc[MT][NT];
+#pragma unroll
+    for (int p = 0; p < MT; ++p)
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[p][q][r] = 0;
+    // Ring of tile-0 A operands: slot (s mod MT) holds step s; tile p at
+    // step s uses step s - p.
+    v4i ring[MT];
+
+    prefetch(0);
+    for (uint32_t cw0 = 0; cw0 < nwords; cw0 += kKCW) {
+#pragma unroll
+        for (int i = 0; i < PFX; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            const int jl = t / kKCW, w = t - jl * kKCW;
+            xs[jl * XS + w] = pfx[i];
+        }
+#pragma unroll
+        for (int i = 0; i < PFW; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            if (t < WINW) win[t] = pfw[i];
+        }
+        const int64_t lo_w = window_lo(cw0);
+        __syncthreads();
+        if (cw0 + kKCW < nwords) prefetch(cw0 + kKCW);
+
+        // This lane's seed bit for (its row at tile 0, column 32*cw0 + 16h).
+        const int64_t e = 32 * (int64_t)cw0 + 16 * h - (R0w + li) +
+                          (int64_t)a.mcap - 1 - (lo_w << 5);
+        const int qa = (int)(e >> 5);
+        const uint32_t sha = (uint32_t)(e & 31);
+        if (cw0 == 0) {
+            // Steps -1 .. -(MT-1) of tile 0 (slots MT-1 .. 1).
+#pragma unroll
+            for (int d = 1; d < MT; ++d) {
+                const int qq = qa - d;
+                ring[MT - d] = expand16(
+                    __builtin_amdgcn_alignbit(win[qq + 1], win[qq], sha));
+            }
+        }
+        // Steps of this chunk, rounded up to a multiple of MT (the staged
+        // column words past the sub-blocks are zero).
+        const uint32_t steps =
+            (min((uint32_t)kKCW, nwords - cw0) + MT - 1) / MT * MT;
+        // Software pipeline: the operands of step s+1 are built while the
+        // matrix cores run step s.
+        v4i a_next, b_next[NT];
+        const uint32_t hb = 16u * (uint32_t)h;
+        auto build = [&](uint32_t s, v4i &an, v4i (&bn)[NT]) {
+            const int qq = qa + (int)s;
+            an = expand16(__builtin_amdgcn_alignbit(win[qq + 1], win[qq], sha));
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                bn[q] = expand16(xs[(32 * q + li) * XS + s], hb);
+        };
+        build(0, a_next, b_next);
+        for (uint32_t s0 = 0; s0 < steps; s0 += MT) {
+#pragma unroll
+            for (int u = 0; u < MT; ++u) {
+                const uint32_t s = s0 + u;
+                ring[u] = a_next;
+                v4i bcur[NT];
+#pragma unroll
+                for (int q = 0; q < NT; ++q) bcur[q] = b_next[q];
+                // Step s+1 <= kKCW stays inside the padded LDS arrays; its
+                // operands are unused after the last step.
+                build(s + 1, a_next, b_next);
+#pragma unroll
+                for (int p = 0; p < MT; ++p)
+#pragma unroll
+                    for (int q = 0; q < NT; ++q)
+                        acc[p][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            ring[(u - p + MT) % MT], bcur[q], acc[p][q], 0, 0, 0);
+                // Interleave: LDS reads first, then one matrix op per three
+                // vector ops.
+                __builtin_amdgcn_sched_group_barrier(0x100, 1 + NT, 0);
+#pragma unroll
+                for (int k = 0; k < MT * NT; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Parity and output.  Lane l holds rows 8(r/4) + 4h + (r%4) of column
+    // l%32; the partner lane l^32 holds the other 16 rows.
+#pragma unroll
+    for (int p = 0; p < MT; ++p) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            uint32_t mine = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                mine |= ((uint32_t)acc[p][q][r] & 1u)
+                        << (8 * (r / 4) + 4 * h + (r % 4));
+            const uint32_t word = mine | (uint32_t)__shfl_xor((int)mine, 32, 64);
+            const uint32_t j = J0 + 32 * q + li;
+            if (h == 0 && j < a.ns) {
+                const int64_t rs = R0w + 32 * p;
+                const int64_t nvalid = (int64_t)a.mlen[j] - rs;
+                if (nvalid > 0) {
+                    uint32_t v = word;
+                    if (nvalid < 32) v &= (1u << nvalid) - 1u;
+                    const uint64_t pos = a.ooff[j] + (uint64_t)rs;
+                    const uint64_t wq = pos >> 5;
+                    const uint32_t sh = (uint32_t)(pos & 31);
+                    if (sh == 0 && nvalid >= 32) {
+                        a.out32[wq] = v;          // this chunk owns the word
+                    } else if (v) {
+                        atomicXor(a.out32 + wq, v << sh);
+                        if (sh && (v >> (32 - sh)))
+                            atomicXor(a.out32 + wq + 1, v >> (32 - sh));
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int MT, int NT, int WM>
+ssbh_status run_mfma(ssbh_ctx *ctx, const MfmaArgs &ma, hipStream_t stream) {
+    using TT = MfmaTile<MT, NT, WM>;
+    MfmaArgs m = ma;
+    m.m_tiles = (uint32_t)((ma.mcap + TT::BM - 1) / TT::BM);
+    const uint64_t groups = (ma.ns + TT::BN - 1) / TT::BN;
+    const uint64_t grid = (uint64_t)m.m_tiles * groups;
+    if (grid == 0) return SSBH_OK;
+    if (grid >= (1ull << 31)) {
+        set_error("MFMA grid too large");
+        return SSBH_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL((k_toeplitz_mfma<MT, NT, WM>), dim3((uint32_t)grid),
+                       dim3(64 * WM), 0, stream, m);
+    SSBH_CHECK_HIP(hipGetLastError());
+    (void)ctx;
+    return SSBH_OK;
+}
+
+}  // namespace
+
+ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
+                             const HashRequest &q, const MfmaSchedule &s,
+                             hipStream_t stream) {
+    if (q.stride != 0) {
+        set_error("the MFMA kernel needs a shared seed (seed_stride = 0)");
+        return SSBH_E_INVAL;
+    }
+    ssbh_status st = plan_only(ctx, ws, q, stream);
+    if (st != SSBH_OK || !q.n_sub) return st;
+    MfmaArgs ma{};
+    uint64_t *plan = ws.plan.as<uint64_t>();
+    ma.sub32 = reinterpret_cast<const uint32_t *>(q.sub);
+    ma.len = q.len; ma.woff = q.woff; ma.mlen = plan; ma.ooff = plan + q.n_sub;
+    ma.seed32 = reinterpret_cast<const uint32_t *>(q.seed);
+    ma.seed_w32 = (int64_t)(2 * ((q.seed_bits + 63) / 64));
+    ma.mcap = q.m_cap;
+    ma.ns = q.n_sub;
+    ma.out32 = reinterpret_cast<uint32_t *>(q.out);
+    ma.status = q.status;
+#define SSBH_MFMA_CASE(A, B, C)                                               \
+    if (s.mt == A && s.nt == B && s.wm == C)                                  \
+        return run_mfma<A, B, C>(ctx, ma, stream);
+    SSBH_MFMA_CASE(8, 2, 4)
+    SSBH_MFMA_CASE(4, 4, 4)
+    SSBH_MFMA_CASE(4, 2, 4)
+    SSBH_MFMA_CASE(8, 1, 4)
+#undef SSBH_MFMA_CASE
+    set_error("unsupported MFMA schedule");
     return SSBH_E_UNSUPPORTED;
 }
+
 }  // namespace ssbh

@@ -440,12 +440,15 @@ static uint64_t tile_bound(uint64_t ns, uint64_t mcap, uint64_t sub_cap,
 
 ssbh_status plan_and_fill(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                           uint32_t rows, uint32_t tile_cols,
-                          hipStream_t stream, Tile **tiles_out) {
+                          hipStream_t stream, Tile **tiles_out,
+                          bool want_tiles = true) {
     const uint64_t ns = q.n_sub;
     // tile_cols = 0 means one column range per sub-block; the bound then
     // uses the longest possible sub-block.
     const uint64_t tc_b = tile_cols ? tile_cols : (2 * q.sub_cap + 1);
-    const uint64_t bound = tile_bound(ns, q.m_cap, q.sub_cap, rows, tc_b);
+    const uint64_t bound =
+        want_tiles ? tile_bound(ns, q.m_cap, q.sub_cap, rows, tc_b) : 1;
+    if (!want_tiles) rows = 1u << 31;   // tile counts are not used
     if (bound > (1ull << 28)) {
         set_error("tile list too large (%llu tiles); use a smaller m_cap or "
                   "sub_capacity_words", (unsigned long long)bound);
@@ -453,7 +456,8 @@ ssbh_status plan_and_fill(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     }
     ssbh_status st;
     if ((st = ws.plan.reserve((size_t)ns * 3 * 8 + 64)) != SSBH_OK) return st;
-    if ((st = ws.tiles.reserve((size_t)bound * sizeof(Tile) + 64)) != SSBH_OK)
+    if ((st = ws.tiles.reserve(want_tiles ? (size_t)bound * sizeof(Tile) + 64
+                                          : 64)) != SSBH_OK)
         return st;
     if ((st = ws.counters.reserve(64)) != SSBH_OK) return st;
     PlanArgs pa{};
@@ -461,7 +465,8 @@ ssbh_status plan_and_fill(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     pa.ra = q.out_a; pa.rb = q.out_b ? q.out_b : 1; pa.out_len = q.out_len;
     pa.seed_bits = q.seed_bits; pa.stride = q.stride; pa.mcap = q.m_cap;
     pa.sub_cap = q.sub_cap; pa.out_cap = q.out_cap_bits;
-    pa.rows = rows; pa.tile_cols = tile_cols; pa.tile_cap = bound;
+    pa.rows = rows; pa.tile_cols = tile_cols;
+    pa.tile_cap = want_tiles ? bound : ~0ull;
     uint64_t *plan = ws.plan.as<uint64_t>();
     pa.mlen = plan; pa.ooff = plan + ns; pa.toff = plan + 2 * ns;
     pa.counters = ws.counters.as<uint64_t>();
@@ -473,13 +478,35 @@ ssbh_status plan_and_fill(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, stream,
                            q.out, ow, q.status);
     }
-    if (ns) {
+    if (ns && want_tiles) {
         hipLaunchKernelGGL(k_expand, dim3((uint32_t)((ns + 3) / 4)), dim3(256),
                            0, stream, pa, ws.tiles.as<Tile>());
     }
     SSBH_CHECK_HIP(hipGetLastError());
     *tiles_out = ws.tiles.as<Tile>();
     return SSBH_OK;
+}
+
+ScratchSizes hash_scratch(const ssbh_ctx *ctx, const HashRequest &q) {
+    ScratchSizes z;
+    z.plan = (size_t)q.n_sub * 3 * 8 + 64;
+    z.counters = 64;
+    if (q.kernel == SSBH_K_MFMA_I8) {
+        z.tiles = 64;
+        return z;
+    }
+    const ValuSchedule s = choose_valu(ctx, q);
+    const uint64_t tc_b = s.tile_cols ? s.tile_cols : (2 * q.sub_cap + 1);
+    z.tiles = (size_t)tile_bound(q.n_sub, q.m_cap, q.sub_cap, s.rows(), tc_b) *
+                  sizeof(Tile) + 64;
+    return z;
+}
+
+// Lengths, offsets, checks and the zeroed output, without a tile list.
+ssbh_status plan_only(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                      hipStream_t stream) {
+    Tile *unused = nullptr;
+    return plan_and_fill(ctx, ws, q, 1, 0, stream, &unused, false);
 }
 
 ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,

@@ -417,6 +417,27 @@ uint32_t ceil_log2(uint32_t x) {
 
 }  // namespace
 
+// Segment size: about 32 bits per sub-block per segment (so runs are a few
+// words long), at least 2^14 bits, LDS image at most 32 KiB.
+static uint64_t segment_bits(uint32_t ns) {
+    uint64_t seg = 32ull * ns;
+    seg = std::max<uint64_t>(seg, 1ull << 14);
+    seg = std::min<uint64_t>(seg, 1ull << 18);
+    return (seg + 63) / 64 * 64;
+}
+
+ScratchSizes sample_scratch(uint64_t n, uint32_t ns, uint32_t mode) {
+    ScratchSizes z;
+    if (mode == SSBH_SAMPLE_PERMUTE || ns == 0) return z;
+    const uint64_t seg = segment_bits(ns);
+    const uint64_t nseg = (n + seg - 1) / seg;
+    const uint64_t nchunk = (nseg + kSegChunk - 1) / kSegChunk;
+    z.counts = (size_t)std::max<uint64_t>(nseg, 1) * ns * 4;
+    z.offs = z.counts;
+    z.part = (size_t)std::max<uint64_t>(nchunk, 1) * ns * 4;
+    return z;
+}
+
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
                         hipStream_t stream) {
     const uint64_t nw = (seed_bits + 63) / 64;
@@ -485,21 +506,15 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     a.in = d_in; a.n = n; a.ns = ns; a.vbits = ceil_log2(ns); a.key = key;
     a.assign = d_assign; a.sub = d_sub; a.sub_cap = sub_cap; a.len = d_len;
     a.woff = d_woff; a.l_ub = l_ub; a.status = d_status;
-    // Segment size: about 32 bits per sub-block per segment (so runs are a
-    // few words long), at least 2^14 bits, LDS image at most 32 KiB.
-    uint64_t seg = 32ull * ns;
-    seg = std::max<uint64_t>(seg, 1ull << 14);
-    seg = std::min<uint64_t>(seg, 1ull << 18);
-    seg = (seg + 63) / 64 * 64;
+    const uint64_t seg = segment_bits(ns);
     a.seg_bits = seg;
     a.nseg = (uint32_t)((n + seg - 1) / seg);
     a.nchunk = (a.nseg + kSegChunk - 1) / kSegChunk;
-    const size_t mat = (size_t)std::max<uint32_t>(a.nseg, 1) * ns * 4;
+    const ScratchSizes sz = sample_scratch(n, ns, mode);
     ssbh_status st;
-    if ((st = ws.counts.reserve(mat)) != SSBH_OK) return st;
-    if ((st = ws.offs.reserve(mat)) != SSBH_OK) return st;
-    if ((st = ws.part.reserve((size_t)std::max<uint32_t>(a.nchunk, 1) * ns * 4)) != SSBH_OK)
-        return st;
+    if ((st = ws.counts.reserve(sz.counts)) != SSBH_OK) return st;
+    if ((st = ws.offs.reserve(sz.offs)) != SSBH_OK) return st;
+    if ((st = ws.part.reserve(sz.part)) != SSBH_OK) return st;
     a.counts = ws.counts.as<uint32_t>();
     a.offs = ws.offs.as<uint32_t>();
     a.part = ws.part.as<uint32_t>();

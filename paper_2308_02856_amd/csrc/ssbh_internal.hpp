@@ -41,6 +41,7 @@ void clear_error();
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool external = false;   // memory lent by the serving arena: never grown
     ssbh_status reserve(size_t need);
     void release();
     template <class T> T *as() const { return static_cast<T *>(ptr); }
@@ -69,9 +70,9 @@ struct ValuSchedule {
 };
 
 struct MfmaSchedule {
-    int mt = 4;      // 32-row M tiles per wave
-    int nt = 2;      // 32-sub-block N tiles per wave
-    int waves = 4;
+    int mt = 8;      // 32-row tiles per wave
+    int nt = 2;      // 32-sub-block tiles per wave (all waves share them)
+    int wm = 4;      // waves per workgroup, along rows
 };
 
 struct ServeState;   // serving scheduler (serve.hip)
@@ -92,6 +93,7 @@ struct ssbh_ctx {
     uint32_t forced_tile_cols = 0;
     uint32_t forced_chunk_cols = 0;
     int forced_scalar_x = -1;      // -1 = library choice
+    int forced_mfma[3] = {0, 0, 0};
 };
 
 namespace ssbh {
@@ -137,6 +139,18 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
 
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
                         hipStream_t stream);
+
+// Scratch each launch layer will reserve for the given request (bytes per
+// Workspace buffer), so callers can lend pre-sized memory.
+struct ScratchSizes {
+    size_t counts = 0, offs = 0, part = 0, plan = 0, tiles = 0, counters = 0;
+    size_t total() const {
+        return counts + offs + part + plan + tiles + counters;
+    }
+};
+ScratchSizes sample_scratch(uint64_t n_bits, uint32_t n_sub, uint32_t mode);
+ScratchSizes hash_scratch(const ssbh_ctx *ctx, const HashRequest &q);
+ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q);
 
 // Allow `kernel` to take `bytes` of dynamic LDS (needed above 64 KiB).
 ssbh_status ensure_dynamic_lds(const void *kernel, size_t bytes);

@@ -35,6 +35,23 @@ _lib = None
 _vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
 
 
+class Job(ctypes.Structure):
+    """ssbh_job (include/ssbh.h)."""
+    _fields_ = [("inp", ctypes.c_void_p), ("in_on_device", ctypes.c_int),
+                ("n_bits", ctypes.c_uint64), ("n_sub", ctypes.c_uint32),
+                ("sample_key", ctypes.c_uint64), ("l_ub", ctypes.c_uint64),
+                ("out_rule", ctypes.c_uint32), ("out_a", ctypes.c_uint64),
+                ("out_b", ctypes.c_uint64), ("seed_key", ctypes.c_uint64),
+                ("out", ctypes.c_void_p), ("out_on_device", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    """ssbh_result (include/ssbh.h)."""
+    _fields_ = [("status", ctypes.c_int32), ("out_bits", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class SsbhError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
@@ -74,8 +91,20 @@ def lib() -> ctypes.CDLL:
     L.ssbh_seed_from_key.argtypes = [_vp, _u64, _vp, _u64, _vp]
     L.ssbh_set_schedule.restype = _i32
     L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32, _u32]
+    L.ssbh_set_mfma_schedule.restype = _i32
+    L.ssbh_set_mfma_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int]
     L.ssbh_set_column_path.restype = _i32
     L.ssbh_set_column_path.argtypes = [_vp, ctypes.c_int]
+    L.ssbh_job_out_words.restype = _u64
+    L.ssbh_job_out_words.argtypes = [ctypes.POINTER(Job)]
+    L.ssbh_submit.restype = _i32
+    L.ssbh_submit.argtypes = [_vp, ctypes.POINTER(Job), ctypes.POINTER(_u64)]
+    L.ssbh_poll.restype = _i32
+    L.ssbh_poll.argtypes = [_vp, _u64, ctypes.POINTER(Result)]
+    L.ssbh_serve_counts.restype = _i32
+    L.ssbh_serve_counts.argtypes = [_vp, ctypes.POINTER(_u64),
+                                    ctypes.POINTER(_u64), ctypes.POINTER(_u64)]
     _lib = L
     return L
 
@@ -204,11 +233,54 @@ class Context:
                                         _stream(stream)))
         return out
 
+    # ------------------------------------------------------------- serving
+
+    def make_job(self, inp, n_bits: int, n_sub: int, sample_key: int,
+                 seed_key: int, out_rule: int = OUT_RATIO, out_a: int = 2,
+                 out_b: int = 5, l_ub: int = 0, out=None) -> tuple:
+        """An ssbh_job over a device input; allocates the device output."""
+        j = Job(inp=_ptr(inp), in_on_device=1, n_bits=int(n_bits),
+                n_sub=int(n_sub), sample_key=int(sample_key) & (2**64 - 1),
+                l_ub=int(l_ub), out_rule=int(out_rule), out_a=int(out_a),
+                out_b=int(out_b), seed_key=int(seed_key) & (2**64 - 1),
+                out=None, out_on_device=1)
+        nw = int(lib().ssbh_job_out_words(ctypes.byref(j)))
+        if out is None:
+            out = torch.empty(max(1, nw), dtype=torch.int64, device=self._dev())
+        j.out = _ptr(out)
+        return j, out
+
+    def submit(self, job: Job) -> int:
+        """ssbh_submit: queue a job (its input must already be on the GPU)."""
+        jid = _u64()
+        _check(lib().ssbh_submit(self._h, ctypes.byref(job), ctypes.byref(jid)))
+        return int(jid.value)
+
+    def poll(self, job_id: int):
+        """None while pending; else the Result (terminal status included)."""
+        r = Result()
+        rc = lib().ssbh_poll(self._h, int(job_id), ctypes.byref(r))
+        if rc == PENDING:
+            return None
+        if rc == E_UNKNOWN_JOB or rc == E_INVAL:
+            _check(rc)
+        return r
+
+    def serve_counts(self):
+        p, r, f = _u64(), _u64(), _u64()
+        _check(lib().ssbh_serve_counts(self._h, ctypes.byref(p),
+                                       ctypes.byref(r), ctypes.byref(f)))
+        return int(p.value), int(r.value), int(f.value)
+
     def set_schedule(self, r: int = 0, waves: int = 0, tile_cols: int = 0,
                      chunk_cols: int = 0):
         """Force the VALU schedule (0 = library choice); bits do not change."""
         _check(lib().ssbh_set_schedule(self._h, int(r), int(waves),
                                        int(tile_cols), int(chunk_cols)))
+
+    def set_mfma_schedule(self, mt: int = 0, nt: int = 0, wm: int = 0):
+        """Force the matrix-core schedule (0s = library choice)."""
+        _check(lib().ssbh_set_mfma_schedule(self._h, int(mt), int(nt), int(wm)))
 
     def set_column_path(self, scalar_x: int = -1):
         """Column words via LDS (0), scalar loads (1) or library choice (-1)."""
