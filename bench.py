@@ -6,9 +6,12 @@ N = 2^28 Bernoulli(0.3) bits into 2048 sub-blocks (with the abort check),
 then the Toeplitz hash of every sub-block (floor(0.4 n_j) output bits, one
 shared seed of max n_j + max m_j - 1 bits) and the concatenation.  `value` is
 input Gbit/s of that step with the input resident in HBM.  The same line
-reports the plain single-block hash (n = 2^24 -> m = 2^23, same kernel) that
-the method is compared with, the roofline of the dominant kernel (timed with
-HIP events on its own stream) and the CPU oracle timed on a bounded sample.
+reports the plain single-block hash (n = 2^24 -> m = 2^23) that the method is
+compared with, the contraction workload (2^30 bits, 8192 equal sub-blocks,
+int8 matrix cores against the bit-sliced kernel), the small workload through a
+captured HIP graph, the serving stream (p50/p99 latency, sustained Gbit/s),
+the roofline of the dominant kernel (timed with HIP events on its stream) and
+the CPU oracle timed on a bounded sample.
 """
 
 from __future__ import annotations
@@ -19,6 +22,7 @@ import json
 import math
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -32,6 +36,10 @@ METRIC = ("input Gbit/s hashed, batched sub-block vs plain single-block; "
 CLOCK_GHZ = 2.4          # MI355X peak engine clock
 LANES_PER_CU_CLK = 128   # 32-bit VALU lanes retired per CU per clock
 BITOPS_PER_LANE_OP = 32  # v_bitop3_b32: 32 AND-XOR bit-products per lane
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak (TOP/s)
+
+KERNEL_SOURCES = {"k_toeplitz_valu": "hash_valu.hip",
+                  "k_toeplitz_mfma": "hash_mfma.hip"}
 
 
 def log(msg: str) -> None:
@@ -54,9 +62,9 @@ def alu_peak_tbitops(num_cus: int) -> float:
     return num_cus * LANES_PER_CU_CLK * CLOCK_GHZ * 1e9 * BITOPS_PER_LANE_OP / 1e12
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in ("hash_valu.hip", "ssbh_internal.hpp"):
+    for f in (KERNEL_SOURCES[kernel], "ssbh_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2308_02856_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -68,12 +76,13 @@ def load_traffic(kernel: str, workload: str):
     if not os.path.exists(path):
         return None
     try:
-        data = json.load(open(path))
+        with open(path) as fh:
+            data = json.load(fh)
         rec = data.get(f"{kernel}:{workload}")
-        if not rec or rec.get("source_digest") != kernel_source_digest():
+        if not rec or rec.get("source_digest") != kernel_source_digest(kernel):
             return None
         return rec.get("hbm_bytes_per_launch")
-    except Exception:
+    except (OSError, ValueError):
         return None
 
 
@@ -113,6 +122,15 @@ def run_batched(ctx, ssbh, args):
     out = torch.empty((out_cap + 63) // 64, dtype=torch.int64, device="cuda")
     tot = torch.zeros(1, dtype=torch.int64, device="cuda")
     work = int((lens * mlen).sum())
+    kernel = {"auto": ssbh.K_AUTO, "valu": ssbh.K_VALU,
+              "mfma": ssbh.K_MFMA_I8}[args.kernel]
+    tune_report = ""
+    if kernel == ssbh.K_AUTO and not args.no_tune:
+        log("batched: autotuning the hash kernel (untimed)")
+        tune_report = ctx.tune(sub, sub_cap, ln, wo, ns, seed, seed_bits, cap,
+                               out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
+                               out_b=c["out_b"], out=out,
+                               out_capacity_bits=out_cap, total=tot, status=st)
 
     def sample():
         ctx.sample(d_in, n, ns, ssbh.SAMPLE_IID, key=key, l_ub=l_ub, sub=sub,
@@ -122,7 +140,7 @@ def run_batched(ctx, ssbh, args):
         ctx.hash_batch(sub, sub_cap, ln, wo, ns, seed, seed_bits, cap,
                        out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
                        out_b=c["out_b"], out=out, out_capacity_bits=out_cap,
-                       total=tot, status=st, reset_status=False)
+                       total=tot, status=st, reset_status=False, kernel=kernel)
 
     for _ in range(args.warmup):
         sample()
@@ -140,11 +158,13 @@ def run_batched(ctx, ssbh, args):
         raise RuntimeError(f"device status {ssbh.status_name(status)}")
     ms_step = (t1 - t0) * 1e3 / args.steps
     hash_ms = time_events(hash_, max(3, args.steps))
+    schedule = ctx.last_schedule()
     samp_ms = time_events(sample, max(3, args.steps))
     res = dict(n=n, ns=ns, lens=lens, mlen=mlen, cap=cap, seed_bits=seed_bits,
                work=work, ms_step=ms_step,
                hash_ms=float(np.mean(hash_ms)), sample_ms=float(np.mean(samp_ms)),
-               a=a, out=out, sub=sub, wo=wo, seed=seed, key=key, c=c)
+               a=a, out=out, sub=sub, wo=wo, seed=seed, key=key, c=c,
+               schedule=schedule, tune_report=tune_report)
     return res
 
 
@@ -177,17 +197,226 @@ def run_single(ctx, ssbh, args):
     return dict(n=n, m=m, ms=float(np.mean(ms)), work=n * m)
 
 
+# -------------------------------------------------------------- contraction
+
+def run_contraction(ctx, ssbh, args, peak_alu):
+    """2^30 uniform bits, permutation split into 8192 sub-blocks of 2^17 bits,
+    2^16 output bits each from one shared seed: the gather, then the hash on
+    the int8 matrix cores and on the bit-sliced VALU kernel (same bits)."""
+    import torch
+    from workloads import config, permutation_device, uniform_bits
+    c = config("contraction")
+    n, ns, L, m = c["n_bits"], c["n_sub"], c["sub_bits"], c["out_a"]
+    log(f"contraction: {n} bits, permutation split into {ns} x {L}")
+    d_in = to_dev(uniform_bits(n, c["input_seed"]))
+    perm = permutation_device(n, c["perm_seed"])
+    seed_bits = L + m - 1
+    seed = to_dev(uniform_bits(seed_bits, c["seed_seed"]))
+    sub_cap = ns * (L // 64)
+    sub = torch.empty(sub_cap, dtype=torch.int64, device="cuda")
+    ln = torch.empty(ns, dtype=torch.int64, device="cuda")
+    wo = torch.empty(ns, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.empty(ns * m // 64, dtype=torch.int64, device="cuda")
+    outv = torch.empty_like(out)
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def sample():
+        ctx.sample(d_in, n, ns, ssbh.SAMPLE_PERMUTE, assign=perm, sub=sub,
+                   sub_capacity=sub_cap, length=ln, word_off=wo, status=st)
+
+    def hash_(kern, o):
+        ctx.hash_batch(sub, sub_cap, ln, wo, ns, seed, seed_bits, m,
+                       out_rule=ssbh.OUT_FIXED, out_a=m, out=o,
+                       out_capacity_bits=ns * m, total=tot, status=st,
+                       reset_status=False, kernel=kern)
+
+    sample()
+    hash_(ssbh.K_MFMA_I8, out)
+    hash_(ssbh.K_VALU, outv)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out, outv)) and int(st.item()) == 0
+    g_ms = float(np.mean(time_events(sample, 3)))
+    mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
+    va_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
+    prods = L * m * ns
+    del d_in, perm, sub, out, outv
+    torch.cuda.empty_cache()
+    return {
+        "workload": "contraction", "n_bits": n, "n_sub": ns, "sub_bits": L,
+        "m_bits": m, "gather_ms": round(g_ms, 3),
+        "mfma_ms": round(mf_ms, 3), "valu_ms": round(va_ms, 3),
+        "gbps_step_mfma": round(n / ((g_ms + mf_ms) * 1e-3) / 1e9, 3),
+        "gbps_hash_mfma": round(n / (mf_ms * 1e-3) / 1e9, 3),
+        "gbps_hash_valu": round(n / (va_ms * 1e-3) / 1e9, 3),
+        "mfma_int8_tops": round(2 * prods / (mf_ms * 1e-3) / 1e12, 1),
+        "mfma_frac": round(2 * prods / (mf_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+        "valu_frac": round(prods / (va_ms * 1e-3) / 1e12 / peak_alu, 4),
+        "mfma_equals_valu": same,
+    }
+
+
+# -------------------------------------------------------------------- small
+
+def run_small(ctx, ssbh, args):
+    """The small workload (2^18 bits, permutation split into 8 x 2^15 bits,
+    2^14 output bits each from independent seeds): eager calls against one
+    replay of the captured HIP graph, per pass."""
+    import torch
+    from workloads import config, permutation, uniform_bits
+    c = config("small")
+    n, ns, L, m = c["n_bits"], c["n_sub"], c["sub_bits"], c["out_a"]
+    stride = L + m - 1
+    seed_bits = ns * stride
+    d_in = to_dev(uniform_bits(n, c["input_seed"]))
+    perm = torch.from_numpy(permutation(n, c["perm_seed"]).view(np.int32)).cuda()
+    seed = to_dev(uniform_bits(seed_bits, c["seed_seed"]))
+    sub_cap = ns * (L // 64)
+    sub = torch.empty(sub_cap, dtype=torch.int64, device="cuda")
+    ln = torch.empty(ns, dtype=torch.int64, device="cuda")
+    wo = torch.empty(ns, dtype=torch.int64, device="cuda")
+    out = torch.empty(ns * m // 64, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def eager():
+        ctx.sample(d_in, n, ns, ssbh.SAMPLE_PERMUTE, assign=perm, sub=sub,
+                   sub_capacity=sub_cap, length=ln, word_off=wo, status=st)
+        ctx.hash_batch(sub, sub_cap, ln, wo, ns, seed, seed_bits, m,
+                       out_rule=ssbh.OUT_FIXED, out_a=m, out=out,
+                       out_capacity_bits=ns * m, total=tot, status=st,
+                       reset_status=False, seed_stride=stride,
+                       kernel=ssbh.K_VALU)
+
+    pipe = ctx.pipeline(d_in=d_in, n_bits=n, n_sub=ns,
+                        mode=ssbh.SAMPLE_PERMUTE, d_assign=perm, d_sub=sub,
+                        sub_capacity_words=sub_cap, d_len=ln, d_word_off=wo,
+                        out_rule=ssbh.OUT_FIXED, out_a=m, out_b=1, d_seed=seed,
+                        seed_bits=seed_bits, seed_stride=stride, m_cap=m,
+                        kernel=ssbh.K_VALU, d_out=out,
+                        out_capacity_bits=ns * m, d_out_total_bits=tot,
+                        d_status=st)
+    eager()
+    torch.cuda.synchronize()
+    ref = out.clone()
+    pipe.launch()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out, ref)) and int(st.item()) == 0
+    reps = 200
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    e_ms = timed(eager)
+    g_ms = timed(pipe.launch)
+    pipe.close()
+    return {"workload": "small", "n_bits": n, "n_sub": ns,
+            "eager_ms": round(e_ms, 4), "graph_ms": round(g_ms, 4),
+            "gbps_graph": round(n / (g_ms * 1e-3) / 1e9, 3),
+            "graph_equals_eager": same}
+
+
+# ------------------------------------------------------------------ serving
+
+def run_serving(ssbh, args):
+    """Poisson stream of whole-method jobs (i.i.d. sampling with the abort
+    threshold, independent seeds from the job's key, hash, concatenation),
+    admitted FIFO under an HBM budget; latency = submit -> results ready."""
+    import torch
+    from workloads import CONFIGS, serving_jobs, serving_pools
+    cfg = CONFIGS["serving"]
+    total = args.serve_jobs + args.serve_warmup
+    jobs = serving_jobs(total, seed=cfg["stream_seed"], rate_hz=cfg["rate_hz"],
+                        log2_n=cfg["log2_n"], log2_sub=cfg["log2_sub"],
+                        q=cfg["q"], p=cfg["p"])
+    log(f"serving: input pools and {total} jobs")
+    ps, pools = serving_pools(levels=4, pool_bits=1 << 28, p=cfg["p"])
+    d_pools = [to_dev(pl) for pl in pools]
+    del pools
+    ctx = ssbh.Context(0, hbm_budget=args.serve_budget_mib << 20)
+    made = []
+    for jb in jobs:
+        k = int(np.argmin([abs(jb["p"] - pk) for pk in ps]))
+        nw = (jb["n_bits"] + 63) // 64
+        off = (jb["index"] * 7919) % max(1, d_pools[k].numel() - nw + 1)
+        job, out = ctx.make_job(d_pools[k][off:off + nw], jb["n_bits"],
+                                jb["n_sub"], jb["sample_key"], jb["seed_key"],
+                                ssbh.OUT_RATIO, jb["ratio_num"],
+                                jb["ratio_den"])
+        made.append((jb, job, out))
+    torch.cuda.synchronize()
+    ids = [None] * len(made)
+    log(f"serving: submitting {total} jobs at {cfg['rate_hz']:.0f}/s")
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, (jb, job, _) in enumerate(made):
+            delay = t_start + jb["arrival_s"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = ctx.submit(job)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    results = {}
+    nxt = 0
+    pending = []
+    deadline = time.perf_counter() + jobs[-1]["arrival_s"] + 120.0
+    while len(results) < len(made):
+        while nxt < len(made) and ids[nxt] is not None:
+            pending.append(nxt)
+            nxt += 1
+        still = []
+        for i in pending:
+            r = ctx.poll(ids[i])
+            if r is None:
+                still.append(i)
+            else:
+                results[i] = r
+        pending = still
+        if time.perf_counter() > deadline:
+            raise RuntimeError("serving stream did not drain")
+        time.sleep(0.0005)
+    th.join()
+    ctx.close()
+    meas = range(args.serve_warmup, len(made))
+    lat = np.array([(results[i].t_done - results[i].t_submit) * 1e3
+                    for i in meas])
+    t0 = min(results[i].t_submit for i in meas)
+    t1 = max(results[i].t_done for i in meas)
+    bits = sum(made[i][0]["n_bits"] for i in meas)
+    offered = bits / (jobs[-1]["arrival_s"] - jobs[args.serve_warmup]["arrival_s"])
+    return {"workload": "serving", "jobs": len(meas),
+            "warmup_jobs": args.serve_warmup, "rate_hz": cfg["rate_hz"],
+            "budget_mib": args.serve_budget_mib,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "sustained_gbps": round(bits / (t1 - t0) / 1e9, 3),
+            "offered_gbps": round(offered / 1e9, 3),
+            "ok": sum(1 for i in meas if results[i].status == 0),
+            "aborted": sum(1 for i in meas if results[i].status == -2),
+            "errors": sum(1 for i in meas if results[i].status not in (0, -2))}
+
+
+# -------------------------------------------------------------- cpu oracle
+
 def spot_check(res, n_rows: int = 24) -> bool:
     """A few output rows of the batched step against the oracle."""
     import oracle
-    lens, mlen = res["lens"], res["mlen"]
+    mlen = res["mlen"]
     osub, oln, owo, _ = res["oracle_sampled"]
     seed = to_host(res["seed"])
     got = to_host(res["out"])
     ooff = np.concatenate([[0], np.cumsum(mlen)[:-1]])
     rng = np.random.default_rng(1)
     for _ in range(n_rows):
-        j = int(rng.integers(0, len(lens)))
+        j = int(rng.integers(0, len(mlen)))
         r = int(rng.integers(0, int(mlen[j])))
         want = oracle.toeplitz_rowwin(osub[int(owo[j]):], int(oln[j]), seed,
                                       res["seed_bits"], 0, res["cap"], r)
@@ -236,13 +465,23 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--single-steps", type=int, default=2)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
+                    help="hash kernel of the batched step (auto = tuned)")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-subblocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
+    ap.add_argument("--skip-contraction", action="store_true")
+    ap.add_argument("--skip-small", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-budget-mib", type=int, default=4096)
     ap.add_argument("--mode", default="full",
-                    choices=["full", "hash-batched", "hash-single", "copy"],
+                    choices=["full", "hash-batched", "hash-single", "copy",
+                             "contraction", "small", "serving"],
                     help="full = the benchmark line; the others run one "
-                         "kernel family only, for profiler passes")
+                         "part only, for profiler passes")
     ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -264,20 +503,45 @@ def main() -> int:
         print(json.dumps({"mode": "copy", "bytes_read": nb, "bytes_written": nb,
                           "launches": args.steps}), flush=True)
         return 0
+    if args.mode == "serving":
+        print(json.dumps(run_serving(ssbh, args)), flush=True)
+        return 0
     ctx = ssbh.Context(0)
+    peak = alu_peak_tbitops(ctx.num_cus)
     if args.mode == "hash-single":
         single = run_single(ctx, ssbh, args)
         print(json.dumps({"mode": args.mode, "ms": single["ms"]}), flush=True)
         return 0
+    if args.mode == "contraction":
+        print(json.dumps(run_contraction(ctx, ssbh, args, peak)), flush=True)
+        return 0
+    if args.mode == "small":
+        print(json.dumps(run_small(ctx, ssbh, args)), flush=True)
+        return 0
     res = run_batched(ctx, ssbh, args)
     if args.mode == "hash-batched":
         print(json.dumps({"mode": args.mode, "hash_ms": res["hash_ms"],
-                          "sample_ms": res["sample_ms"]}), flush=True)
+                          "sample_ms": res["sample_ms"],
+                          "schedule": res["schedule"]}), flush=True)
         return 0
     single = None if args.skip_single else run_single(ctx, ssbh, args)
 
-    peak = alu_peak_tbitops(ctx.num_cus)
-    achieved = res["work"] / (res["hash_ms"] * 1e-3) / 1e12
+    if res["schedule"].startswith("mfma"):
+        kern = "k_toeplitz_mfma"
+        achieved = 2 * res["work"] / (res["hash_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": kern, "schedule": res["schedule"],
+                "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
+                "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
+                "traffic": load_traffic(kern, "batched")}
+        dtype = "i8"
+    else:
+        kern = "k_toeplitz_valu"
+        achieved = res["work"] / (res["hash_ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": kern, "schedule": res["schedule"],
+                "achieved": round(achieved, 2), "peak": round(peak, 2),
+                "unit": "Tbit-op/s", "frac": round(achieved / peak, 4),
+                "traffic": load_traffic(kern, "batched")}
+        dtype = "u32"
     line = {
         "metric": METRIC,
         "value": round(res["n"] / (res["ms_step"] * 1e-3) / 1e9, 4),
@@ -289,34 +553,42 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "batched", "n_bits": res["n"],
                    "n_sub": res["ns"], "p": res["c"]["p"],
                    "sampling": "iid", "out_len": "floor(2*n_j/5)",
                    "seed": "shared", "seed_bits": res["seed_bits"],
-                   "bit_products": res["work"]},
+                   "bit_products": res["work"],
+                   "hash_kernel": res["schedule"]},
         "hash_only_gbps": round(res["n"] / (res["hash_ms"] * 1e-3) / 1e9, 4),
         "hash_ms": round(res["hash_ms"], 4),
         "sample_ms": round(res["sample_ms"], 4),
-        "roofline": {"bound": "alu", "kernel": "k_toeplitz_valu",
-                     "achieved": round(achieved, 2), "peak": round(peak, 2),
-                     "unit": "Tbit-op/s", "frac": round(achieved / peak, 4),
-                     "traffic": load_traffic("k_toeplitz_valu", "batched")},
+        "bit_products_per_s": float(f"{res['work'] / (res['hash_ms'] * 1e-3):.4g}"),
+        "roofline": roof,
+        "tuning": res["tune_report"].strip().splitlines(),
     }
     if single is not None:
         sg = single["n"] / (single["ms"] * 1e-3) / 1e9
         line["single_block"] = {
             "workload": "single", "n_bits": single["n"], "m_bits": single["m"],
             "gbps": round(sg, 5), "ms": round(single["ms"], 3),
-            "roofline_frac": round(single["work"] / (single["ms"] * 1e-3) / 1e12
-                                   / peak, 4)}
+            "alu_frac": round(single["work"] / (single["ms"] * 1e-3) / 1e12
+                              / peak, 4)}
         line["speedup_vs_single_block"] = round(line["value"] / sg, 2)
+    if not args.skip_contraction:
+        line["contraction"] = run_contraction(ctx, ssbh, args, peak)
+    if not args.skip_small:
+        line["small"] = run_small(ctx, ssbh, args)
+    ctx.close()
+    if not args.skip_serving:
+        line["serving"] = run_serving(ssbh, args)
+        line["p50_ms"] = line["serving"]["p50_ms"]
+        line["p99_ms"] = line["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(res, args.cpu_subblocks)
         line["spot_check_vs_oracle"] = spot_check(res)
     print(json.dumps(line), flush=True)
-    ctx.close()
     return 0
 
 

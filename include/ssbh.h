@@ -188,6 +188,40 @@ ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,
                                uint64_t *d_seed, uint64_t seed_bits,
                                void *stream);
 
+/* ------------------------------------------------------ graph pipeline --- */
+
+/* The whole hot path (ssbh_sample then ssbh_hash_batch) on fixed buffers,
+ * captured once into a HIP graph and replayed with one launch.  The fields
+ * mean what the arguments of the two calls mean; d_in = NULL skips the
+ * sampling step (hash-only pipeline over d_sub/d_len/d_word_off as given).
+ * Inputs may change between launches; sizes and pointers may not. */
+typedef struct {
+    const uint64_t *d_in; uint64_t n_bits; uint32_t n_sub; uint32_t mode;
+    uint64_t sample_key; const uint32_t *d_assign; uint64_t l_ub;
+    uint64_t *d_sub; uint64_t sub_capacity_words;
+    uint64_t *d_len; uint64_t *d_word_off;
+    uint32_t out_rule; uint64_t out_a, out_b; const uint64_t *d_out_len;
+    const uint64_t *d_seed; uint64_t seed_bits; uint64_t seed_stride;
+    uint64_t m_cap; uint32_t kernel;
+    uint64_t *d_out; uint64_t out_capacity_bits; uint64_t *d_out_total_bits;
+    int32_t *d_status;
+} ssbh_pipeline_desc;
+
+typedef struct ssbh_pipeline ssbh_pipeline;
+
+/* Build the pipeline: allocates its own scratch memory (so replays never
+ * share scratch with other calls), runs the path once eagerly on a private
+ * stream (one-time kernel set-up; the outputs are written), then captures it.
+ * Blocks until done. */
+ssbh_status ssbh_pipeline_create(ssbh_ctx *ctx, const ssbh_pipeline_desc *desc,
+                                 ssbh_pipeline **out);
+
+/* Enqueue one replay of the captured path on `stream` (hipStream_t). */
+ssbh_status ssbh_pipeline_launch(ssbh_pipeline *pipe, void *stream);
+
+/* Free the graph and its scratch (waits for the pipeline's replays). */
+void ssbh_pipeline_destroy(ssbh_pipeline *pipe);
+
 /* ------------------------------------------------------------ serving --- */
 
 /* One extraction job (the whole method of Sec. III.B on one input block):
@@ -248,6 +282,35 @@ ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
                               uint64_t *running, uint64_t *finished);
 
 /* ------------------------------------------------------------- tuning --- */
+
+/* Autotuner: run ssbh_hash_batch on the given (real) arguments once per
+ * candidate kernel and schedule (bit-sliced VALU schedules; int8 matrix-core
+ * schedules when the seed is shared), `reps` timed runs each with HIP events,
+ * and remember the fastest for the shape bucket of these arguments (seed
+ * sharing, log2 of n_sub, m_cap and mean sub-block words).  Later calls with
+ * kernel = SSBH_K_AUTO in the same bucket use it; without a tuned entry AUTO
+ * picks the matrix cores for a shared seed and n_sub >= 64, else the VALU
+ * kernel.  Blocks until the stream is idle; d_out holds a valid result
+ * afterwards.  If report is non-null, a text table of the timings is written
+ * (truncated to report_len bytes). */
+ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,
+                      uint64_t sub_capacity_words, const uint64_t *d_len,
+                      const uint64_t *d_word_off, uint32_t n_sub,
+                      uint32_t out_rule, uint64_t out_a, uint64_t out_b,
+                      const uint64_t *d_out_len, const uint64_t *d_seed,
+                      uint64_t seed_bits, uint64_t seed_stride, uint64_t m_cap,
+                      uint64_t *d_out, uint64_t out_capacity_bits,
+                      uint64_t *d_out_total_bits, int32_t *d_status,
+                      uint32_t reps, char *report, uint64_t report_len,
+                      void *stream);
+
+/* The tuned choices, one "bucket=choice" line each (truncated to len). */
+ssbh_status ssbh_tune_table(ssbh_ctx *ctx, char *buf, uint64_t len);
+
+/* The kernel and schedule that the last ssbh_hash_batch or ssbh_tune call on
+ * this context launched, as "valu:R:waves:chunk_cols:tile_cols" or
+ * "mfma:MT:NT:WM" (empty before the first call; truncated to len). */
+ssbh_status ssbh_last_schedule(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* Force the schedule of the VALU hash kernel for later calls on this
  * context: r = rows per lane (8, 16 or 32), waves = wavefronts per workgroup

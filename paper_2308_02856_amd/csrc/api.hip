@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "ssbh_internal.hpp"
 
@@ -108,9 +109,51 @@ ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q) {
     return s;
 }
 
+// Shape bucket of a hash request (used by the autotuner's table).
+std::string tune_bucket(const HashRequest &q) {
+    auto lg = [](double v) { return v <= 1 ? 0 : (int)std::floor(std::log2(v)); };
+    const double mean_words = q.n_sub ? 2.0 * (double)q.sub_cap / q.n_sub : 0;
+    char b[96];
+    snprintf(b, sizeof b, "%s/ns%d/m%d/w%d", q.stride ? "indep" : "shared",
+             lg(q.n_sub), lg((double)q.m_cap), lg(mean_words));
+    return b;
+}
+
 ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                         hipStream_t stream) {
     (void)hipGetLastError();   // clear errors left by earlier calls
+    if (q.kernel == SSBH_K_AUTO) {
+        HashRequest r = q;
+        std::string choice;
+        {
+            const std::string key = tune_bucket(q);
+            for (auto &kv : ctx->tune_cache)
+                if (kv.first == key) choice = kv.second;
+        }
+        if (!choice.empty()) {
+            int a = 0, b = 0, c = 0;
+            unsigned d = 0, e = 0;
+            if (sscanf(choice.c_str(), "mfma:%d:%d:%d", &a, &b, &c) == 3 &&
+                q.stride == 0) {
+                MfmaSchedule ms;
+                ms.mt = a; ms.nt = b; ms.wm = c;
+                r.kernel = SSBH_K_MFMA_I8;
+                return launch_hash_mfma(ctx, ws, r, ms, stream);
+            }
+            if (sscanf(choice.c_str(), "valu:%d:%d:%u:%u", &a, &b, &d, &e) == 4) {
+                ValuSchedule vs = choose_valu(ctx, q);
+                vs.r = a; vs.waves = b; vs.chunk_cols = d; vs.tile_cols = e;
+                r.kernel = SSBH_K_VALU;
+                return launch_hash_valu(ctx, ws, r, vs, stream);
+            }
+        }
+        if (q.stride == 0 && q.n_sub >= 64 && !ctx->forced_valu_r) {
+            r.kernel = SSBH_K_MFMA_I8;
+            return launch_hash(ctx, ws, r, stream);
+        }
+        r.kernel = SSBH_K_VALU;
+        return launch_hash_valu(ctx, ws, r, choose_valu(ctx, r), stream);
+    }
     if (q.kernel == SSBH_K_MFMA_I8) {
         MfmaSchedule ms;
         if (ctx->forced_mfma[0]) {
@@ -120,8 +163,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         }
         return launch_hash_mfma(ctx, ws, q, ms, stream);
     }
-    if (q.kernel != SSBH_K_AUTO && q.kernel != SSBH_K_VALU)
-        SSBH_INVAL("unknown kernel %u", q.kernel);
+    if (q.kernel != SSBH_K_VALU) SSBH_INVAL("unknown kernel %u", q.kernel);
     return launch_hash_valu(ctx, ws, q, choose_valu(ctx, q), stream);
 }
 

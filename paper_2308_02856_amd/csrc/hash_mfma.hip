@@ -18,6 +18,8 @@
 // multiply per nibble: (nib * 0x204081) & 0x01010101.
 #include <algorithm>
 
+#include <stdio.h>
+
 #include "ssbh_internal.hpp"
 
 namespace ssbh {
@@ -289,7 +291,10 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
         return SSBH_E_INVAL;
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
-    if (st != SSBH_OK || !q.n_sub) return st;
+    if (st != SSBH_OK) return st;
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "mfma:%d:%d:%d",
+             s.mt, s.nt, s.wm);
+    if (!q.n_sub) return st;
     MfmaArgs ma{};
     uint64_t *plan = ws.plan.as<uint64_t>();
     ma.sub32 = reinterpret_cast<const uint32_t *>(q.sub);

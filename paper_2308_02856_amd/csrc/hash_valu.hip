@@ -25,6 +25,8 @@
 // order independent, so every schedule gives the same bits.
 #include <algorithm>
 
+#include <stdio.h>
+
 #include "ssbh_internal.hpp"
 
 namespace ssbh {
@@ -516,6 +518,8 @@ ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,
     ssbh_status st = plan_and_fill(ctx, ws, q, (uint32_t)s.rows(),
                                    s.tile_cols, stream, &tiles);
     if (st != SSBH_OK) return st;
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "valu:%d:%d:%u:%u",
+             s.r, s.waves, s.chunk_cols, s.tile_cols);
     if (!q.n_sub) return SSBH_OK;
     ValuArgs va{};
     va.sub32 = reinterpret_cast<const uint32_t *>(q.sub);

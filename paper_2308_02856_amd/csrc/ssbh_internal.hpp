@@ -55,6 +55,7 @@ struct Workspace {
     DevBuf plan;       // hashing: m_j, O_j, tile offsets (3 * n_sub u64)
     DevBuf tiles;      // hashing: tile list
     DevBuf counters;   // hashing: tile count, claim counter
+    char last_schedule[48] = "";   // kernel and schedule of the last hash
     void release();
 };
 
@@ -151,6 +152,7 @@ struct ScratchSizes {
 ScratchSizes sample_scratch(uint64_t n_bits, uint32_t n_sub, uint32_t mode);
 ScratchSizes hash_scratch(const ssbh_ctx *ctx, const HashRequest &q);
 ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q);
+std::string tune_bucket(const HashRequest &q);
 
 // Allow `kernel` to take `bytes` of dynamic LDS (needed above 64 KiB).
 ssbh_status ensure_dynamic_lds(const void *kernel, size_t bytes);

@@ -52,6 +52,24 @@ class Result(ctypes.Structure):
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
+class PipelineDesc(ctypes.Structure):
+    """ssbh_pipeline_desc (include/ssbh.h)."""
+    _fields_ = [("d_in", ctypes.c_void_p), ("n_bits", ctypes.c_uint64),
+                ("n_sub", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("sample_key", ctypes.c_uint64), ("d_assign", ctypes.c_void_p),
+                ("l_ub", ctypes.c_uint64), ("d_sub", ctypes.c_void_p),
+                ("sub_capacity_words", ctypes.c_uint64),
+                ("d_len", ctypes.c_void_p), ("d_word_off", ctypes.c_void_p),
+                ("out_rule", ctypes.c_uint32), ("out_a", ctypes.c_uint64),
+                ("out_b", ctypes.c_uint64), ("d_out_len", ctypes.c_void_p),
+                ("d_seed", ctypes.c_void_p), ("seed_bits", ctypes.c_uint64),
+                ("seed_stride", ctypes.c_uint64), ("m_cap", ctypes.c_uint64),
+                ("kernel", ctypes.c_uint32), ("d_out", ctypes.c_void_p),
+                ("out_capacity_bits", ctypes.c_uint64),
+                ("d_out_total_bits", ctypes.c_void_p),
+                ("d_status", ctypes.c_void_p)]
+
+
 class SsbhError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
@@ -91,6 +109,21 @@ def lib() -> ctypes.CDLL:
     L.ssbh_seed_from_key.argtypes = [_vp, _u64, _vp, _u64, _vp]
     L.ssbh_set_schedule.restype = _i32
     L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32, _u32]
+    L.ssbh_pipeline_create.restype = _i32
+    L.ssbh_pipeline_create.argtypes = [_vp, ctypes.POINTER(PipelineDesc),
+                                       ctypes.POINTER(_vp)]
+    L.ssbh_pipeline_launch.restype = _i32
+    L.ssbh_pipeline_launch.argtypes = [_vp, _vp]
+    L.ssbh_pipeline_destroy.restype = None
+    L.ssbh_pipeline_destroy.argtypes = [_vp]
+    L.ssbh_tune.restype = _i32
+    L.ssbh_tune.argtypes = [_vp, _vp, _u64, _vp, _vp, _u32, _u32, _u64, _u64,
+                            _vp, _vp, _u64, _u64, _u64, _vp, _u64, _vp, _vp,
+                            _u32, ctypes.c_char_p, _u64, _vp]
+    L.ssbh_tune_table.restype = _i32
+    L.ssbh_tune_table.argtypes = [_vp, ctypes.c_char_p, _u64]
+    L.ssbh_last_schedule.restype = _i32
+    L.ssbh_last_schedule.argtypes = [_vp, ctypes.c_char_p, _u64]
     L.ssbh_set_mfma_schedule.restype = _i32
     L.ssbh_set_mfma_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int]
@@ -233,6 +266,48 @@ class Context:
                                         _stream(stream)))
         return out
 
+    def tune(self, sub, sub_capacity: int, length, word_off, n_sub: int,
+             seed, seed_bits: int, m_cap: int, out_rule: int = OUT_FIXED,
+             out_a: int = 0, out_b: int = 1, out_len=None, seed_stride: int = 0,
+             out=None, out_capacity_bits: int | None = None, total=None,
+             status=None, reps: int = 2, stream=None) -> str:
+        """ssbh_tune on these arguments; returns the timing table."""
+        dev = self._dev()
+        if out_capacity_bits is None:
+            out_capacity_bits = (int(out_a) * int(n_sub) if out_rule == OUT_FIXED
+                                 else (64 * int(sub_capacity) * int(out_a)) // int(out_b))
+        if out is None:
+            out = torch.empty(max(1, words(out_capacity_bits)), dtype=torch.int64,
+                              device=dev)
+        if total is None:
+            total = torch.zeros(1, dtype=torch.int64, device=dev)
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().ssbh_tune(
+            self._h, _ptr(sub), int(sub_capacity), _ptr(length), _ptr(word_off),
+            int(n_sub), int(out_rule), int(out_a), int(out_b), _ptr(out_len),
+            _ptr(seed), int(seed_bits), int(seed_stride), int(m_cap), _ptr(out),
+            int(out_capacity_bits), _ptr(total), _ptr(status), int(reps), buf,
+            4096, _stream(stream)))
+        return buf.value.decode()
+
+    def tune_table(self) -> str:
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib().ssbh_tune_table(self._h, buf, 8192))
+        return buf.value.decode()
+
+    def last_schedule(self) -> str:
+        """Kernel and schedule of the last synchronous hash launch."""
+        buf = ctypes.create_string_buffer(64)
+        _check(lib().ssbh_last_schedule(self._h, buf, 64))
+        return buf.value.decode()
+
+    def pipeline(self, **kw) -> "Pipeline":
+        """A captured sample -> hash graph; keyword names as in ssbh_pipeline_desc
+        (tensors for the d_* fields)."""
+        return Pipeline(self, **kw)
+
     # ------------------------------------------------------------- serving
 
     def make_job(self, inp, n_bits: int, n_sub: int, sample_key: int,
@@ -285,6 +360,40 @@ class Context:
     def set_column_path(self, scalar_x: int = -1):
         """Column words via LDS (0), scalar loads (1) or library choice (-1)."""
         _check(lib().ssbh_set_column_path(self._h, int(scalar_x)))
+
+
+class Pipeline:
+    """ssbh_pipeline: the hot path captured into a HIP graph."""
+
+    def __init__(self, ctx: Context, **kw):
+        self.ctx = ctx
+        self._keep = dict(kw)          # tensors must outlive the graph
+        d = PipelineDesc()
+        for name, _ in PipelineDesc._fields_:
+            if name not in kw:
+                continue
+            v = kw[name]
+            if isinstance(v, torch.Tensor):
+                setattr(d, name, _ptr(v))
+            else:
+                setattr(d, name, v)
+        self._h = _vp()
+        _check(lib().ssbh_pipeline_create(ctx.handle, ctypes.byref(d),
+                                          ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(lib().ssbh_pipeline_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().ssbh_pipeline_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status_name(code: int) -> str:

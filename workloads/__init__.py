@@ -14,6 +14,7 @@ from .gen import (  # noqa: F401
     bernoulli_bits,
     uniform_bits,
     permutation,
+    permutation_device,
     assignment,
     unpack_bits,
     pack_bits,
