@@ -309,7 +309,8 @@ ssbh_status ssbh_tune_table(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* The kernel and schedule that the last ssbh_hash_batch or ssbh_tune call on
  * this context launched, as "valu:R:waves:chunk_cols:tile_cols" or
- * "mfma:MT:NT:WM" (empty before the first call; truncated to len). */
+ * "mfma:MT:NT:WM:ksplit" (ksplit 0 = automatic; empty before the first call;
+ * truncated to len). */
 ssbh_status ssbh_last_schedule(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* Force the schedule of the VALU hash kernel for later calls on this
@@ -325,8 +326,11 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
 /* Force the schedule of the int8 matrix-core kernel: mt = 32-row tiles per
  * wavefront, nt = 32-sub-block tiles per wavefront, wm = wavefronts per
  * workgroup (supported: (8,2,4), (4,4,4), (4,2,4), (8,1,4)); 0s restore the
- * library's choice.  The output bits do not depend on it. */
-ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm);
+ * library's choice.  ksplit = K splits per tile (1 .. 64; 0 = chosen so that
+ * the tiles fill every compute unit in whole rounds).  The output bits do not
+ * depend on any of them. */
+ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm,
+                                   int ksplit);
 
 /* Where the VALU hash kernel reads the 32-bit column words of the sub-blocks
  * from: 0 = staged in LDS with the seed window, 1 = through the scalar data

@@ -131,12 +131,12 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                 if (kv.first == key) choice = kv.second;
         }
         if (!choice.empty()) {
-            int a = 0, b = 0, c = 0;
+            int a = 0, b = 0, c = 0, k = 0;
             unsigned d = 0, e = 0;
-            if (sscanf(choice.c_str(), "mfma:%d:%d:%d", &a, &b, &c) == 3 &&
+            if (sscanf(choice.c_str(), "mfma:%d:%d:%d:%d", &a, &b, &c, &k) == 4 &&
                 q.stride == 0) {
                 MfmaSchedule ms;
-                ms.mt = a; ms.nt = b; ms.wm = c;
+                ms.mt = a; ms.nt = b; ms.wm = c; ms.ksplit = k;
                 r.kernel = SSBH_K_MFMA_I8;
                 return launch_hash_mfma(ctx, ws, r, ms, stream);
             }
@@ -161,6 +161,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             ms.nt = ctx->forced_mfma[1];
             ms.wm = ctx->forced_mfma[2];
         }
+        ms.ksplit = ctx->forced_mfma[3];
         return launch_hash_mfma(ctx, ws, q, ms, stream);
     }
     if (q.kernel != SSBH_K_VALU) SSBH_INVAL("unknown kernel %u", q.kernel);
@@ -315,12 +316,16 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
     return SSBH_OK;
 }
 
-ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm) {
+ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm,
+                                   int ksplit) {
     clear_error();
     if (!ctx) SSBH_INVAL("ctx is null");
+    if (ksplit < 0 || ksplit > 64) SSBH_INVAL("ksplit must be 0 .. 64");
+    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->forced_mfma[0] = mt;
     ctx->forced_mfma[1] = nt;
     ctx->forced_mfma[2] = wm;
+    ctx->forced_mfma[3] = ksplit;
     return SSBH_OK;
 }
 

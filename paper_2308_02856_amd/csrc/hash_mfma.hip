@@ -9,6 +9,15 @@
 // parity exact for any length).  Columns past n_j are zero and rows past m_j
 // are dropped, so uneven sizes share one launch.
 //
+// Work split: a workgroup owns BM rows x BN sub-blocks and a range of K
+// chunks (split-K; partial parities merge by XOR, which is exact).  Block
+// indices are remapped so that the row tiles and K splits of one sub-block
+// group run on one XCD (blocks are dispatched to the 8 XCDs round-robin), so
+// the group's column words are fetched into one L2 only.  The epilogue
+// assembles each sub-block's BM output bits in LDS and stores whole 32-bit
+// words; only the two end words of a segment (shared with the neighbouring
+// row tile or sub-block) and split-K partials go through atomic XOR.
+//
 // Operands are built in registers from bit-packed data; T never exists in
 // memory.  A-operand lane l (row i = l%32, k = 16*(l/32) + byte) needs 16
 // consecutive seed bits; rows 32 apart at columns 32 apart need the same bits,
@@ -17,6 +26,7 @@
 // l%32) takes 16 data bits of its sub-block.  Bits become 0/1 bytes with one
 // multiply per nibble: (nib * 0x204081) & 0x01010101.
 #include <algorithm>
+#include <cmath>
 
 #include <stdio.h>
 
@@ -43,6 +53,7 @@ struct MfmaArgs {
     uint64_t mcap;
     uint32_t ns;
     uint32_t m_tiles;
+    uint32_t ksplit;         // K splits per tile (1 = the tile owns all K)
     uint32_t *out32;
     const int32_t *status;
 };
@@ -68,23 +79,38 @@ struct MfmaTile {
     static constexpr int WINW = (BM + kKC) / 32 + MT + 6;
     static constexpr int PFX = BN * kKCW / NTH;         // words per thread
     static constexpr int PFW = (WINW + NTH - 1) / NTH;  // window words/thread
+    static constexpr int OBW = BM / 32 + 1;             // epilogue words/col
 };
 
-template <int MT, int NT, int WM>
-__global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
+// Block b runs logical tile t: XCD x = b mod 8 takes the x-th contiguous
+// range of logical tiles (a bijection for any grid size).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t g) {
+    const uint32_t per = g >> 3, rem = g & 7u, x = b & 7u;
+    const uint32_t start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return start + (b >> 3);
+}
+
+template <int MT, int NT, int WM, int OCC>
+__global__ __launch_bounds__(64 * WM) __attribute__((amdgpu_waves_per_eu(OCC)))
+void k_toeplitz_mfma(MfmaArgs a) {
     using TT = MfmaTile<MT, NT, WM>;
     constexpr int BM = TT::BM, BN = TT::BN, NTH = TT::NTH, XS = TT::XS;
     constexpr int WINW = TT::WINW, PFX = TT::PFX, PFW = TT::PFW;
+    constexpr int OBW = TT::OBW;
     static_assert(BN * kKCW % NTH == 0, "staging must divide evenly");
+    static_assert(OBW <= XS, "epilogue image must fit the staging area");
     __shared__ uint32_t xs[BN * XS];
     __shared__ uint32_t win[WINW];
-    __shared__ uint64_t woff_s[BN];
+    __shared__ uint64_t woff_s[BN], mlen_s[BN], ooff_s[BN];
     __shared__ uint32_t nw_s[BN], tail_s[BN];
     __shared__ uint64_t nmax_s, mmax_s;
     if (*a.status) return;
 
-    const uint32_t mt = blockIdx.x % a.m_tiles;
-    const uint32_t grp = blockIdx.x / a.m_tiles;
+    const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t mt = t % a.m_tiles;
+    const uint32_t rest = t / a.m_tiles;
+    const uint32_t ks = rest % a.ksplit;
+    const uint32_t grp = rest / a.ksplit;
     const int64_t R0 = (int64_t)mt * BM;
     const uint32_t J0 = grp * BN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -92,13 +118,17 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
 
     if (threadIdx.x == 0) { nmax_s = 0; mmax_s = 0; }
     __syncthreads();
-    for (int t = threadIdx.x; t < BN; t += NTH) {
-        const uint32_t j = J0 + t;
-        uint64_t n = 0, m = 0, wo = 0;
-        if (j < a.ns) { n = a.len[j]; m = a.mlen[j]; wo = a.woff[j]; }
-        woff_s[t] = wo;
-        nw_s[t] = (uint32_t)((n + 31) / 32);
-        tail_s[t] = (n & 31) ? ((1u << (n & 31)) - 1u) : ~0u;
+    for (int jl = threadIdx.x; jl < BN; jl += NTH) {
+        const uint32_t j = J0 + jl;
+        uint64_t n = 0, m = 0, wo = 0, oo = 0;
+        if (j < a.ns) {
+            n = a.len[j]; m = a.mlen[j]; wo = a.woff[j]; oo = a.ooff[j];
+        }
+        woff_s[jl] = wo;
+        mlen_s[jl] = m;
+        ooff_s[jl] = oo;
+        nw_s[jl] = (uint32_t)((n + 31) / 32);
+        tail_s[jl] = (n & 31) ? ((1u << (n & 31)) - 1u) : ~0u;
         if (n) atomicMax((unsigned long long *)&nmax_s, (unsigned long long)n);
         if (m) atomicMax((unsigned long long *)&mmax_s, (unsigned long long)m);
     }
@@ -106,15 +136,22 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
     const uint64_t nmax = nmax_s, mmax = mmax_s;
     if (nmax == 0 || (uint64_t)R0 >= mmax) return;   // uniform
     const uint32_t nwords = (uint32_t)((nmax + 31) / 32);
+    // This split's column words: whole chunks [c_lo, c_hi).
+    const uint32_t nchunks = (nwords + kKCW - 1) / kKCW;
+    const uint32_t c_lo = (uint32_t)((uint64_t)ks * nchunks / a.ksplit);
+    const uint32_t c_hi = (uint32_t)((uint64_t)(ks + 1) * nchunks / a.ksplit);
+    if (c_lo >= c_hi) return;                          // uniform
+    const uint32_t cw_begin = c_lo * kKCW;
+    const uint32_t cw_end = min(c_hi * (uint32_t)kKCW, nwords);
     const int64_t R0w = R0 + (int64_t)wave * 32 * MT;   // wave's first row
 
     // Register prefetch of one chunk: column words and seed window.
     uint32_t pfx[PFX], pfw[PFW];
     auto window_lo = [&](uint32_t cw0) -> int64_t {
         // Lowest seed bit of the chunk: column 32*cw0, row R0+BM-1; the first
-        // chunk also needs MT-1 earlier A operands.
+        // chunk of the split also needs MT-1 earlier A operands.
         const int64_t lo = 32 * (int64_t)cw0 - (R0 + BM - 1) + (int64_t)a.mcap -
-                           1 - (cw0 == 0 ? 32 * (MT - 1) : 0);
+                           1 - (cw0 == cw_begin ? 32 * (MT - 1) : 0);
         return lo >> 5;
     };
     auto prefetch = [&](uint32_t cw0) {
@@ -150,8 +187,8 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
     // step s uses step s - p.
     v4i ring[MT];
 
-    prefetch(0);
-    for (uint32_t cw0 = 0; cw0 < nwords; cw0 += kKCW) {
+    prefetch(cw_begin);
+    for (uint32_t cw0 = cw_begin; cw0 < cw_end; cw0 += kKCW) {
 #pragma unroll
         for (int i = 0; i < PFX; ++i) {
             const int t = threadIdx.x + i * NTH;
@@ -165,14 +202,14 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
         }
         const int64_t lo_w = window_lo(cw0);
         __syncthreads();
-        if (cw0 + kKCW < nwords) prefetch(cw0 + kKCW);
+        if (cw0 + kKCW < cw_end) prefetch(cw0 + kKCW);
 
         // This lane's seed bit for (its row at tile 0, column 32*cw0 + 16h).
         const int64_t e = 32 * (int64_t)cw0 + 16 * h - (R0w + li) +
                           (int64_t)a.mcap - 1 - (lo_w << 5);
         const int qa = (int)(e >> 5);
         const uint32_t sha = (uint32_t)(e & 31);
-        if (cw0 == 0) {
+        if (cw0 == cw_begin) {
             // Steps -1 .. -(MT-1) of tile 0 (slots MT-1 .. 1).
 #pragma unroll
             for (int d = 1; d < MT; ++d) {
@@ -181,10 +218,11 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
                     __builtin_amdgcn_alignbit(win[qq + 1], win[qq], sha));
             }
         }
-        // Steps of this chunk, rounded up to a multiple of MT (the staged
-        // column words past the sub-blocks are zero).
+        // Steps of this chunk, rounded up to a multiple of MT (only the last
+        // chunk of a sub-block group can be short; its staged column words
+        // past the sub-blocks are zero).
         const uint32_t steps =
-            (min((uint32_t)kKCW, nwords - cw0) + MT - 1) / MT * MT;
+            (min((uint32_t)kKCW, cw_end - cw0) + MT - 1) / MT * MT;
         // Software pipeline: the operands of step s+1 are built while the
         // matrix cores run step s.
         v4i a_next, b_next[NT];
@@ -227,8 +265,10 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
         __syncthreads();
     }
 
-    // Parity and output.  Lane l holds rows 8(r/4) + 4h + (r%4) of column
-    // l%32; the partner lane l^32 holds the other 16 rows.
+    // Parity.  Lane l holds rows 8(r/4) + 4h + (r%4) of column l%32; the
+    // partner lane l^32 holds the other 16 rows.  Each 32-row word goes to
+    // the LDS image ob[sub-block][row word] (rows past m_j cleared).
+    uint32_t *ob = xs;
 #pragma unroll
     for (int p = 0; p < MT; ++p) {
 #pragma unroll
@@ -239,45 +279,76 @@ __global__ __launch_bounds__(64 * WM) void k_toeplitz_mfma(MfmaArgs a) {
                 mine |= ((uint32_t)acc[p][q][r] & 1u)
                         << (8 * (r / 4) + 4 * h + (r % 4));
             const uint32_t word = mine | (uint32_t)__shfl_xor((int)mine, 32, 64);
-            const uint32_t j = J0 + 32 * q + li;
-            if (h == 0 && j < a.ns) {
-                const int64_t rs = R0w + 32 * p;
-                const int64_t nvalid = (int64_t)a.mlen[j] - rs;
-                if (nvalid > 0) {
-                    uint32_t v = word;
-                    if (nvalid < 32) v &= (1u << nvalid) - 1u;
-                    const uint64_t pos = a.ooff[j] + (uint64_t)rs;
-                    const uint64_t wq = pos >> 5;
-                    const uint32_t sh = (uint32_t)(pos & 31);
-                    if (sh == 0 && nvalid >= 32) {
-                        a.out32[wq] = v;          // this chunk owns the word
-                    } else if (v) {
-                        atomicXor(a.out32 + wq, v << sh);
-                        if (sh && (v >> (32 - sh)))
-                            atomicXor(a.out32 + wq + 1, v >> (32 - sh));
-                    }
-                }
-            }
+            const int jl = 32 * q + li;
+            const int64_t nvalid = (int64_t)mlen_s[jl] - (R0w + 32 * p);
+            uint32_t v = nvalid > 0 ? word : 0u;
+            if (nvalid > 0 && nvalid < 32) v &= (1u << nvalid) - 1u;
+            if (h == 0) ob[jl * OBW + wave * MT + p] = v;
         }
+    }
+    for (int jl = threadIdx.x; jl < BN; jl += NTH) ob[jl * OBW + OBW - 1] = 0u;
+    __syncthreads();
+    // Output words: sub-block j's rows R0 .. R0+nb-1 land at bits P .. P+nb-1
+    // with P = O_j + R0.  Words wholly inside that range belong to this
+    // workgroup alone (when it owns all of K) and are stored; the others are
+    // merged with atomic XOR into the zeroed output.
+    const bool owner = a.ksplit == 1;
+    for (int idx = threadIdx.x; idx < BN * OBW; idx += NTH) {
+        const int jl = idx / OBW, k = idx - jl * OBW;
+        const uint64_t m = mlen_s[jl];
+        if (m <= (uint64_t)R0) continue;
+        const uint64_t nb = min(m - (uint64_t)R0, (uint64_t)BM);
+        const uint64_t P = ooff_s[jl] + (uint64_t)R0;
+        const uint32_t sh = (uint32_t)(P & 31);
+        const uint64_t wq0 = P >> 5;
+        if ((uint64_t)k > ((P + nb - 1) >> 5) - wq0) continue;
+        const uint32_t *row = ob + jl * OBW;
+        uint32_t val = row[k];
+        if (sh) val = (val << sh) | (k ? row[k - 1] >> (32 - sh) : 0u);
+        const uint64_t wstart = 32 * (wq0 + (uint64_t)k);
+        if (owner && wstart >= P && wstart + 32 <= P + nb)
+            a.out32[wq0 + k] = val;
+        else if (val)
+            atomicXor(a.out32 + wq0 + k, val);
     }
 }
 
-template <int MT, int NT, int WM>
-ssbh_status run_mfma(ssbh_ctx *ctx, const MfmaArgs &ma, hipStream_t stream) {
+// K splits per tile: enough tiles in flight to fill every CU in whole
+// rounds (a short last round idles most of the chip), at least 8 K chunks
+// per split.
+uint32_t choose_ksplit(uint64_t tiles, uint64_t slots, uint64_t nchunks) {
+    uint32_t best = 1;
+    double best_eff = 0.0;
+    for (uint32_t k = 1; k <= 4; ++k) {
+        if (k > 1 && nchunks < 8ull * k) break;
+        const double r = (double)(tiles * k) / (double)slots;
+        const double eff = r / std::ceil(r) * (1.0 - 0.015 * (k - 1));
+        if (eff > best_eff + 1e-9) { best_eff = eff; best = k; }
+    }
+    return best;
+}
+
+template <int MT, int NT, int WM, int OCC>
+ssbh_status run_mfma(ssbh_ctx *ctx, const MfmaArgs &ma, uint32_t ksplit,
+                     uint64_t ncap, hipStream_t stream) {
     using TT = MfmaTile<MT, NT, WM>;
     MfmaArgs m = ma;
     m.m_tiles = (uint32_t)((ma.mcap + TT::BM - 1) / TT::BM);
     const uint64_t groups = (ma.ns + TT::BN - 1) / TT::BN;
-    const uint64_t grid = (uint64_t)m.m_tiles * groups;
-    if (grid == 0) return SSBH_OK;
+    const uint64_t tiles = (uint64_t)m.m_tiles * groups;
+    if (tiles == 0) return SSBH_OK;
+    const uint64_t nchunks = (ncap + 32ull * kKCW - 1) / (32ull * kKCW);
+    m.ksplit = ksplit ? ksplit
+                      : choose_ksplit(tiles, (uint64_t)ctx->num_cus * OCC,
+                                      nchunks);
+    const uint64_t grid = tiles * m.ksplit;
     if (grid >= (1ull << 31)) {
         set_error("MFMA grid too large");
         return SSBH_E_UNSUPPORTED;
     }
-    hipLaunchKernelGGL((k_toeplitz_mfma<MT, NT, WM>), dim3((uint32_t)grid),
+    hipLaunchKernelGGL((k_toeplitz_mfma<MT, NT, WM, OCC>), dim3((uint32_t)grid),
                        dim3(64 * WM), 0, stream, m);
     SSBH_CHECK_HIP(hipGetLastError());
-    (void)ctx;
     return SSBH_OK;
 }
 
@@ -292,8 +363,8 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
-    snprintf(ws.last_schedule, sizeof ws.last_schedule, "mfma:%d:%d:%d",
-             s.mt, s.nt, s.wm);
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "mfma:%d:%d:%d:%d",
+             s.mt, s.nt, s.wm, s.ksplit);
     if (!q.n_sub) return st;
     MfmaArgs ma{};
     uint64_t *plan = ws.plan.as<uint64_t>();
@@ -305,13 +376,20 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
     ma.ns = q.n_sub;
     ma.out32 = reinterpret_cast<uint32_t *>(q.out);
     ma.status = q.status;
-#define SSBH_MFMA_CASE(A, B, C)                                               \
+    if (s.ksplit < 0 || s.ksplit > 64) {
+        set_error("ksplit must be 0 (automatic) .. 64");
+        return SSBH_E_INVAL;
+    }
+    // Mean sub-block length from the buffer capacity: the split count only
+    // needs an estimate of the K chunks per tile.
+    const uint64_t ncap = 64ull * q.sub_cap / q.n_sub + 64;
+#define SSBH_MFMA_CASE(A, B, C, O)                                            \
     if (s.mt == A && s.nt == B && s.wm == C)                                  \
-        return run_mfma<A, B, C>(ctx, ma, stream);
-    SSBH_MFMA_CASE(8, 2, 4)
-    SSBH_MFMA_CASE(4, 4, 4)
-    SSBH_MFMA_CASE(4, 2, 4)
-    SSBH_MFMA_CASE(8, 1, 4)
+        return run_mfma<A, B, C, O>(ctx, ma, (uint32_t)s.ksplit, ncap, stream);
+    SSBH_MFMA_CASE(8, 2, 4, 1)
+    SSBH_MFMA_CASE(4, 4, 4, 1)
+    SSBH_MFMA_CASE(4, 2, 4, 2)
+    SSBH_MFMA_CASE(8, 1, 4, 1)
 #undef SSBH_MFMA_CASE
     set_error("unsupported MFMA schedule");
     return SSBH_E_UNSUPPORTED;

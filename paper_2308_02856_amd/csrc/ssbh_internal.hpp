@@ -74,6 +74,7 @@ struct MfmaSchedule {
     int mt = 8;      // 32-row tiles per wave
     int nt = 2;      // 32-sub-block tiles per wave (all waves share them)
     int wm = 4;      // waves per workgroup, along rows
+    int ksplit = 0;  // K splits per tile (0 = fill the chip in whole rounds)
 };
 
 struct ServeState;   // serving scheduler (serve.hip)
@@ -94,7 +95,7 @@ struct ssbh_ctx {
     uint32_t forced_tile_cols = 0;
     uint32_t forced_chunk_cols = 0;
     int forced_scalar_x = -1;      // -1 = library choice
-    int forced_mfma[3] = {0, 0, 0};
+    int forced_mfma[4] = {0, 0, 0, 0};
 };
 
 namespace ssbh {

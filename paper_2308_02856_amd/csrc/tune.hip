@@ -45,15 +45,18 @@ std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
         c.push_back(k);
     }
     if (q.stride == 0) {
-        const int ms[][3] = {{8, 2, 4}, {8, 1, 4}, {4, 4, 4}};
+        // ksplit 0 = the launcher's whole-rounds choice.
+        const int ms[][4] = {{8, 2, 4, 0}, {8, 2, 4, 1}, {4, 2, 4, 0},
+                             {8, 1, 4, 0}, {4, 4, 4, 0}};
         for (auto &x : ms) {
             Candidate k;
             k.mfma = true;
             k.m.mt = x[0];
             k.m.nt = x[1];
             k.m.wm = x[2];
+            k.m.ksplit = x[3];
             char b[64];
-            snprintf(b, sizeof b, "mfma:%d:%d:%d", x[0], x[1], x[2]);
+            snprintf(b, sizeof b, "mfma:%d:%d:%d:%d", x[0], x[1], x[2], x[3]);
             k.name = b;
             c.push_back(k);
         }

@@ -126,7 +126,7 @@ def lib() -> ctypes.CDLL:
     L.ssbh_last_schedule.argtypes = [_vp, ctypes.c_char_p, _u64]
     L.ssbh_set_mfma_schedule.restype = _i32
     L.ssbh_set_mfma_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int]
+                                         ctypes.c_int, ctypes.c_int]
     L.ssbh_set_column_path.restype = _i32
     L.ssbh_set_column_path.argtypes = [_vp, ctypes.c_int]
     L.ssbh_job_out_words.restype = _u64
@@ -353,9 +353,11 @@ class Context:
         _check(lib().ssbh_set_schedule(self._h, int(r), int(waves),
                                        int(tile_cols), int(chunk_cols)))
 
-    def set_mfma_schedule(self, mt: int = 0, nt: int = 0, wm: int = 0):
+    def set_mfma_schedule(self, mt: int = 0, nt: int = 0, wm: int = 0,
+                          ksplit: int = 0):
         """Force the matrix-core schedule (0s = library choice)."""
-        _check(lib().ssbh_set_mfma_schedule(self._h, int(mt), int(nt), int(wm)))
+        _check(lib().ssbh_set_mfma_schedule(self._h, int(mt), int(nt), int(wm),
+                                            int(ksplit)))
 
     def set_column_path(self, scalar_x: int = -1):
         """Column words via LDS (0), scalar loads (1) or library choice (-1)."""

@@ -140,3 +140,67 @@ def test_contraction_shape_sampled_rows(ctx, S, orc):
         want = orc.toeplitz_rowwin(a[j * (n // 64):(j + 1) * (n // 64)], n,
                                    seed, seed_bits, 0, m, r)
         assert bit(g_mfma, j * m + r) == want, (j, r)
+
+
+SCHEDULES = [(8, 2, 4), (4, 4, 4), (4, 2, 4), (8, 1, 4)]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("ksplit", [0, 1, 2, 3, 5])
+def test_every_schedule_and_k_split(ctx, S, orc, sched, ksplit):
+    """Every matrix-core schedule and K split (partial parities merged by
+    XOR) gives the oracle's bits: uneven i.i.d. sub-blocks of ~2^14 bits
+    (several K chunks of 2048 columns, ragged ends), output segments at
+    arbitrary bit offsets, m_j spanning several 32-row words and row tiles."""
+    import torch
+    N, ns = (1 << 20) + 4321, 70
+    a = bernoulli_bits(N, 0.4, 808)
+    key = 0x77AA
+    sub, ln, wo, st = ctx.sample(to_dev(a), N, ns, S.SAMPLE_IID, key=key)
+    osub, oln, owo, _ = orc.sample(a, N, ns, orc.SAMPLE_IID, key=key)
+    om = orc.out_lengths(oln, orc.OUT_RATIO, 3, 7)
+    cap = int(om.max())
+    seed_bits = int(oln.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 809)
+    want, wtot = orc.hash_batch(osub, oln, owo, om, seed, seed_bits, 0, cap)
+    ctx.set_mfma_schedule(*sched, ksplit)
+    try:
+        out, tot, st2 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns,
+                                       to_dev(seed), seed_bits, cap,
+                                       out_rule=S.OUT_RATIO, out_a=3, out_b=7,
+                                       kernel=S.K_MFMA_I8)
+        torch.cuda.synchronize()
+        used = ctx.last_schedule()
+    finally:
+        ctx.set_mfma_schedule(0, 0, 0, 0)
+    assert int(st2.item()) == 0 and int(tot.item()) == wtot
+    assert used == "mfma:%d:%d:%d:%d" % (*sched, ksplit)
+    got = to_host(out)[: want.size]
+    assert np.array_equal(got, want), first_diff(got, want)
+
+
+def test_k_split_beyond_chunks_is_exact(ctx, S, orc):
+    """More K splits than K chunks: empty splits contribute nothing."""
+    import torch
+    n, ns, m = 3000, 40, 2500          # 2 chunks of 2048 columns
+    N = n * ns
+    a = uniform_bits(N, 91)
+    perm = permutation(N, 92)
+    sub, ln, wo, st = ctx.sample(to_dev(a), N, ns, S.SAMPLE_PERMUTE,
+                                 assign=to_dev_u32(perm))
+    seed_bits = n + m - 1
+    seed = uniform_bits(seed_bits, 93)
+    ctx.set_mfma_schedule(8, 2, 4, 7)
+    try:
+        out, tot, st2 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns,
+                                       to_dev(seed), seed_bits, m,
+                                       out_rule=S.OUT_FIXED, out_a=m,
+                                       kernel=S.K_MFMA_I8)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_mfma_schedule(0, 0, 0, 0)
+    osub, oln, owo, _ = orc.sample(a, N, ns, orc.SAMPLE_PERMUTE, assign=perm)
+    want, _ = orc.hash_batch(osub, oln, owo, np.full(ns, m, np.uint64), seed,
+                             seed_bits, 0, m)
+    assert int(st2.item()) == 0
+    assert np.array_equal(to_host(out)[: want.size], want)
