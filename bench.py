@@ -70,8 +70,9 @@ def kernel_source_digest(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed PMC counters, if still current."""
+def load_traffic(kernel: str, workload: str, schedule: str):
+    """HBM bytes per launch from committed PMC counters, if they were taken
+    on the same kernel source and schedule."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -80,6 +81,8 @@ def load_traffic(kernel: str, workload: str):
             data = json.load(fh)
         rec = data.get(f"{kernel}:{workload}")
         if not rec or rec.get("source_digest") != kernel_source_digest(kernel):
+            return None
+        if rec.get("schedule") != schedule:
             return None
         return rec.get("hbm_bytes_per_launch")
     except (OSError, ValueError):
@@ -238,6 +241,7 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     same = bool(torch.equal(out, outv)) and int(st.item()) == 0
     g_ms = float(np.mean(time_events(sample, 3)))
     mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
+    mfma_sched = ctx.last_schedule()
     va_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
     prods = L * m * ns
     del d_in, perm, sub, out, outv
@@ -253,6 +257,8 @@ def run_contraction(ctx, ssbh, args, peak_alu):
         "mfma_frac": round(2 * prods / (mf_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
         "valu_frac": round(prods / (va_ms * 1e-3) / 1e12 / peak_alu, 4),
         "mfma_equals_valu": same,
+        "mfma_traffic": load_traffic("k_toeplitz_mfma", "contraction",
+                                     mfma_sched),
     }
 
 
@@ -390,6 +396,18 @@ def run_serving(ssbh, args):
     t0 = min(results[i].t_submit for i in meas)
     t1 = max(results[i].t_done for i in meas)
     bits = sum(made[i][0]["n_bits"] for i in meas)
+    # Busy fraction: time with at least one admitted, unfinished job.
+    spans = sorted((results[i].t_admit, results[i].t_done) for i in meas)
+    busy, cur0, cur1 = 0.0, spans[0][0], spans[0][1]
+    for a0, a1 in spans[1:]:
+        if a0 > cur1:
+            busy += cur1 - cur0
+            cur0, cur1 = a0, a1
+        else:
+            cur1 = max(cur1, a1)
+    busy += cur1 - cur0
+    queued = np.array([(results[i].t_admit - results[i].t_submit) * 1e3
+                       for i in meas])
     offered = bits / (jobs[-1]["arrival_s"] - jobs[args.serve_warmup]["arrival_s"])
     return {"workload": "serving", "jobs": len(meas),
             "warmup_jobs": args.serve_warmup, "rate_hz": cfg["rate_hz"],
@@ -397,8 +415,10 @@ def run_serving(ssbh, args):
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3),
+            "p99_queue_ms": round(float(np.percentile(queued, 99)), 3),
             "sustained_gbps": round(bits / (t1 - t0) / 1e9, 3),
             "offered_gbps": round(offered / 1e9, 3),
+            "busy_frac": round(busy / (t1 - t0), 4),
             "ok": sum(1 for i in meas if results[i].status == 0),
             "aborted": sum(1 for i in meas if results[i].status == -2),
             "errors": sum(1 for i in meas if results[i].status not in (0, -2))}
@@ -447,15 +467,29 @@ def cpu_baseline(res, k_sub: int):
     oracle.hash_batch(osub[:hi], oln[:k], owo[:k], om[:k], seed,
                       res["seed_bits"], 0, res["cap"], level=1)
     t3 = time.perf_counter()
+    cores = oracle.threads()
+    # The same hash sample on one thread (the sampling is serial anyway).
+    k1 = max(1, k // 8)
+    hi1 = int(owo[k1 - 1] + (oln[k1 - 1] + 63) // 64)
+    log(f"cpu baseline: oracle hash of {k1} sub-blocks on one thread")
+    oracle.set_threads(1)
+    t4 = time.perf_counter()
+    oracle.hash_batch(osub[:hi1], oln[:k1], owo[:k1], om[:k1], seed,
+                      res["seed_bits"], 0, res["cap"], level=1)
+    t5 = time.perf_counter()
+    oracle.set_threads(cores)
     t_full = (t1 - t0) + (t3 - t2) * ns / k
+    t_one = (t1 - t0) + (t5 - t4) * ns / k1
     return {
         "value": round(n / t_full / 1e9, 6),
         "unit": "Gbit/s",
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"oracle sampling of all {n} bits ({t1 - t0:.2f} s) + "
-                   f"row-window hash of {k}/{ns} sub-blocks ({t3 - t2:.2f} s), "
-                   "hash time scaled by ns/k"),
+        "value_1thread": round(n / t_one / 1e9, 6),
+        "sample": (f"oracle sampling of all {n} bits ({t1 - t0:.2f} s, one "
+                   f"thread) + row-window hash of {k}/{ns} sub-blocks "
+                   f"({t3 - t2:.2f} s on {cores} threads; {k1} sub-blocks "
+                   f"{t5 - t4:.2f} s on one), hash time scaled to all {ns}"),
     }
 
 
@@ -474,9 +508,9 @@ def main() -> int:
     ap.add_argument("--skip-contraction", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=2000)
-    ap.add_argument("--serve-warmup", type=int, default=100)
-    ap.add_argument("--serve-budget-mib", type=int, default=4096)
+    ap.add_argument("--serve-jobs", type=int, default=3000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-budget-mib", type=int, default=512)
     ap.add_argument("--mode", default="full",
                     choices=["full", "hash-batched", "hash-single", "copy",
                              "contraction", "small", "serving"],
@@ -532,7 +566,7 @@ def main() -> int:
         roof = {"bound": "mfma", "kernel": kern, "schedule": res["schedule"],
                 "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
                 "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
-                "traffic": load_traffic(kern, "batched")}
+                "traffic": load_traffic(kern, "batched", res["schedule"])}
         dtype = "i8"
     else:
         kern = "k_toeplitz_valu"
@@ -540,7 +574,7 @@ def main() -> int:
         roof = {"bound": "alu", "kernel": kern, "schedule": res["schedule"],
                 "achieved": round(achieved, 2), "peak": round(peak, 2),
                 "unit": "Tbit-op/s", "frac": round(achieved / peak, 4),
-                "traffic": load_traffic(kern, "batched")}
+                "traffic": load_traffic(kern, "batched", res["schedule"])}
         dtype = "u32"
     line = {
         "metric": METRIC,

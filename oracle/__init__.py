@@ -80,6 +80,8 @@ def _load():
             f.argtypes = [U64P, u64, U64P, u64, u64, u64, u64, U64P, u64]
         lib.ssbo_threads.restype = i32
         lib.ssbo_threads.argtypes = []
+        lib.ssbo_set_threads.restype = None
+        lib.ssbo_set_threads.argtypes = [i32]
         lib.ssbo_hash_batch.restype = ctypes.c_int64
         lib.ssbo_hash_batch.argtypes = [U64P, U64P, U64P, u32, U64P, U64P,
                                         u64, u64, u64, U64P, u64, i32]
@@ -109,6 +111,11 @@ def _nw(n_bits: int) -> int:
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().ssbo_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of the oracle's parallel loops."""
+    _load().ssbo_set_threads(int(n))
 
 
 # ----------------------------------------------------------------- PRNG ---

@@ -269,6 +269,8 @@ int64_t ssbo_hash_batch(const uint64_t *sub, const uint64_t *len,
 #ifdef _OPENMP
 #include <omp.h>
 int ssbo_threads(void) { return omp_get_max_threads(); }
+void ssbo_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 #else
 int ssbo_threads(void) { return 1; }
+void ssbo_set_threads(int n) { (void)n; }
 #endif
