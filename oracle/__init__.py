@@ -14,6 +14,7 @@ sub-block length threshold L_S^UB, per-sub-block extraction and concatenation
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -64,6 +65,9 @@ def _load():
         lib.ssbo_partition.restype = i32
         lib.ssbo_partition.argtypes = [U64P, u64, U32P, u32, U64P, u64, U64P,
                                        U64P]
+        lib.ssbo_sift.restype = i32
+        lib.ssbo_sift.argtypes = [U64P, U64P, U64P, U64P, u32, U64P, u64,
+                                  U64P, U64P]
         lib.ssbo_permute_split.restype = i32
         lib.ssbo_permute_split.argtypes = [U64P, u64, U32P, u32, U64P, U64P,
                                            U64P]
@@ -180,20 +184,90 @@ def permute_split(a, n: int, perm, n_sub: int):
     return sub[: wl * n_sub], ln, wo
 
 
+def sift(sub, keep_sub, ln, wo, n_sub: int):
+    """Sec. III.B step 2 inside every sub-block: keep the bits of sub-block j
+    whose flag (sub-block j of the keep string, divided by the same V) is 1.
+    Returns (sub', len', word_off')."""
+    sub, keep_sub, ln, wo = _u64(sub), _u64(keep_sub), _u64(ln), _u64(wo)
+    cap = max(1, int(sub.size))
+    out = np.zeros(cap, dtype=np.uint64)
+    oln = np.zeros(max(1, n_sub), dtype=np.uint64)
+    owo = np.zeros(max(1, n_sub), dtype=np.uint64)
+    if keep_sub.size < sub.size:
+        keep_sub = np.concatenate([keep_sub, np.zeros(sub.size - keep_sub.size,
+                                                      dtype=np.uint64)])
+    rc = _load().ssbo_sift(_p64(sub), _p64(keep_sub), _p64(ln), _p64(wo),
+                           n_sub, _p64(out), cap, _p64(oln), _p64(owo))
+    if rc:
+        raise ValueError("sift output too small")
+    used = int(owo[n_sub - 1] + (oln[n_sub - 1] + 63) // 64) if n_sub else 0
+    return out[:used], oln[:n_sub], owo[:n_sub]
+
+
 def sample(a, n: int, n_sub: int, mode: int, key: int = 0, assign=None,
-           l_ub: int = 0):
-    """Sampling step with the abort rule: returns (sub, len, word_off, abort)."""
+           l_ub: int = 0, keep=None):
+    """Sampling (Sec. III.B step 1), optional sifting with the keep flags
+    `keep` (step 2; i.i.d. and explicit modes) and the abort rule: returns
+    (sub, len, word_off, abort)."""
     if mode == SAMPLE_IID:
         v = assign_iid(n, n_sub, key)
         sub, ln, wo = partition(a, n, v, n_sub)
     elif mode == SAMPLE_EXPLICIT:
+        v = assign
         sub, ln, wo = partition(a, n, assign, n_sub)
     elif mode == SAMPLE_PERMUTE:
+        if keep is not None:
+            raise ValueError("sifting is defined for i.i.d. / explicit V")
         sub, ln, wo = permute_split(a, n, assign, n_sub)
     else:
         raise ValueError(mode)
+    if keep is not None:
+        ksub, kln, kwo = partition(keep, n, v, n_sub)
+        sub, ln, wo = sift(sub, ksub, ln, wo, n_sub)
     abort = bool(l_ub) and n_sub > 0 and int(ln.max()) > int(l_ub)
     return sub, ln, wo, abort
+
+
+# ------------------------------------------------ abort threshold (III.D) ---
+
+def _rel_entropy(x: float, p: float) -> float:
+    """H(x, p) = x ln(x/p) + (1-x) ln((1-x)/(1-p)), with 0 ln 0 = 0.
+
+    Written as x ln(1 + d/p) + (1-x) ln(1 - d/(1-p)) with d = x - p and
+    log1p: near x = p the two logarithms are +-d-sized and cancel to a
+    d^2-sized result, which plain logs of the ratios lose to rounding."""
+    d = x - p
+    h = 0.0
+    if x > 0.0:
+        h += x * math.log1p(d / p)
+    if x < 1.0:
+        h += (1.0 - x) * math.log1p(-d / (1.0 - p))
+    return h
+
+
+def ub_tail(n: int, p: float, l_ub: int) -> float:
+    """Sec. III.D bound on the chance that one sub-block (Binomial(n, p)
+    length, p = p_sift) is longer than l_ub:
+    1 - Phi(sqrt(2 n H(l_ub/n, p))) for l_ub >= n p, else 1."""
+    n, l_ub = int(n), int(l_ub)
+    if l_ub >= n:
+        return 0.0
+    x = l_ub / n
+    if x < p:
+        return 1.0
+    z = math.sqrt(2.0 * n * _rel_entropy(x, p))
+    return 0.5 * math.erfc(z / math.sqrt(2.0))
+
+
+def ub_threshold(n: int, p: float, n_sub: int, eps: float) -> int:
+    """Smallest integer L_S^UB with n_sub * ub_tail(n, p, L) <= eps (a union
+    bound over the sub-blocks; the bound falls as L grows), found by trying
+    L = ceil(n p), ceil(n p) + 1, ... in turn; L = n always qualifies."""
+    n = int(n)
+    L = int(math.ceil(n * p))
+    while L < n and n_sub * ub_tail(n, p, L) > eps:
+        L += 1
+    return L
 
 
 def out_lengths(ln, rule: int, a: int, b: int = 1) -> np.ndarray:

@@ -126,6 +126,41 @@ int ssbo_partition(const uint64_t *a, uint64_t n, const uint32_t *v,
     return 0;
 }
 
+/* Sifting inside every sub-block (Sec. III.B step 2): sub-block j of the
+ * data and sub-block j of the keep flags (both divided by the same V) are
+ * walked together, and only the bits whose flag is 1 are kept, in order.
+ * Output sub-block j starts at word out_off[j] = sum_{k<j} ceil(out_len[k]/64).
+ * Returns 0, or -1 when the output buffer is too small. */
+int ssbo_sift(const uint64_t *sub, const uint64_t *keep_sub,
+              const uint64_t *len, const uint64_t *word_off, uint32_t n_sub,
+              uint64_t *out, uint64_t out_cap_words, uint64_t *out_len,
+              uint64_t *out_off) {
+    for (uint32_t j = 0; j < n_sub; ++j) {
+        uint64_t c = 0;
+        for (uint64_t k = 0; k < len[j]; ++k)
+            c += get_bit(keep_sub, 64ull * word_off[j] + k);
+        out_len[j] = c;
+    }
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < n_sub; ++j) {
+        out_off[j] = acc;
+        acc += (out_len[j] + 63) / 64;
+    }
+    if (acc > out_cap_words) return -1;
+    memset(out, 0, sizeof(uint64_t) * acc);
+    for (uint32_t j = 0; j < n_sub; ++j) {
+        uint64_t pos = 0;
+        for (uint64_t k = 0; k < len[j]; ++k) {
+            const uint64_t b = 64ull * word_off[j] + k;
+            if (get_bit(keep_sub, b)) {
+                put_bit(out, 64ull * out_off[j] + pos, get_bit(sub, b));
+                pos += 1;
+            }
+        }
+    }
+    return 0;
+}
+
 /* Permutation then contiguous split: B[k] = A[perm[k]], sub-block j is
  * B[jL, (j+1)L) with L = n / n_sub, starting at word j*ceil(L/64).
  * Returns -1 when n_sub does not divide n or perm is out of range. */

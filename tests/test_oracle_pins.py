@@ -9,6 +9,7 @@ SplitMix64 outputs, by numpy boolean selection / fancy indexing (library
 routines), by the bijection property and by the abort rule of Sec. III.B.
 """
 
+import math
 import os
 
 import numpy as np
@@ -411,3 +412,85 @@ def test_toeplitz_ignores_input_bits_past_n(orc):
         for r in (0, m - 1):
             assert (orc.toeplitz_rowwin(dirty, n, s, n + m - 1, 0, m, r)
                     == orc.toeplitz_row(x, n, s, 0, m, r))
+
+
+# ------------------------------------------------ sifting (Sec. III.B step 2)
+
+@pytest.mark.parametrize("n,ns,pk", [(5000, 7, 0.6), (64 * 40, 3, 0.9),
+                                     (1000, 1, 0.5), (777, 16, 0.0),
+                                     (4096, 8, 1.0)])
+def test_sift_equals_selection_by_v_and_keep(orc, n, ns, pk):
+    """Sampling then sifting inside each sub-block == selecting, from the raw
+    string, the rounds with V_i = j and keep_i = 1 (in ascending i)."""
+    a = uniform_bits(n, n + 1)
+    keep = bernoulli_bits(n, pk, n + 2) if 0.0 < pk < 1.0 else (
+        uniform_bits(n, 1) & np.uint64(0) if pk == 0.0 else
+        pack_bits(np.ones(n, dtype=np.uint8)))
+    key = 0xABC + n
+    sub, ln, wo, abort = orc.sample(a, n, ns, orc.SAMPLE_IID, key=key,
+                                    keep=keep)
+    v = orc.assign_iid(n, ns, key)
+    abits, kbits = unpack_bits(a, n), unpack_bits(keep, n)
+    assert int(ln.sum()) == int(kbits.sum())
+    for j in range(ns):
+        want = abits[(v == j) & (kbits == 1)]
+        assert int(ln[j]) == want.size
+        got = unpack_bits(sub[int(wo[j]):], int(ln[j])) if want.size else want
+        assert np.array_equal(got, want), j
+
+
+def test_sift_explicit_mode_and_permute_rejected(orc):
+    n, ns = 3000, 5
+    a = uniform_bits(n, 3)
+    keep = bernoulli_bits(n, 0.7, 4)
+    v = assignment(n, ns, 5)
+    sub, ln, wo, _ = orc.sample(a, n, ns, orc.SAMPLE_EXPLICIT, assign=v,
+                                keep=keep)
+    abits, kbits = unpack_bits(a, n), unpack_bits(keep, n)
+    for j in range(ns):
+        want = abits[(v == j) & (kbits == 1)]
+        assert np.array_equal(unpack_bits(sub[int(wo[j]):], int(ln[j])), want)
+    with pytest.raises(ValueError):
+        orc.sample(a, n, ns, orc.SAMPLE_PERMUTE, assign=permutation(n, 6),
+                   keep=keep)
+
+
+# ------------------------------------------- abort threshold (Sec. III.D) ---
+
+def test_ub_tail_bounds_the_exact_binomial_tail(orc):
+    """The Sec. III.D bound is an upper bound on P(Binomial(n, p) > L)."""
+    from scipy.stats import binom
+    for n in (100, 1000, 10 ** 5, 2 ** 28):
+        for p in (1 / 2048, 0.01, 0.05, 0.3, 0.5):
+            mu, sd = n * p, math.sqrt(n * p * (1 - p))
+            for k in (0, 1, 2, 4, 7):
+                L = int(math.ceil(mu + k * sd))
+                if L >= n:
+                    continue
+                exact = float(binom.sf(L, n, p))
+                bound = orc.ub_tail(n, p, L)
+                assert exact <= bound * (1 + 1e-9) + 1e-300, (n, p, L)
+                assert bound <= 1.0
+
+
+def test_ub_tail_special_values(orc):
+    assert orc.ub_tail(1000, 0.25, 250) == pytest.approx(0.5)   # H = 0
+    assert orc.ub_tail(1000, 0.25, 1000) == 0.0                 # L = n
+    assert orc.ub_tail(1000, 0.25, 100) == 1.0                  # below mean
+    # Monotone: a larger threshold never has a larger bound.
+    vals = [orc.ub_tail(10 ** 6, 0.01, L) for L in range(10000, 10600, 37)]
+    assert all(b <= a for a, b in zip(vals, vals[1:]))
+
+
+@pytest.mark.parametrize("n,p,ns,eps", [(2 ** 28, 1 / 2048, 2048, 1e-8),
+                                        (2 ** 24, 0.3 / 128, 128, 1e-6),
+                                        (10 ** 5, 0.05, 20, 1e-10),
+                                        (200, 0.5, 2, 1e-30)])
+def test_ub_threshold_is_the_smallest_valid_threshold(orc, n, p, ns, eps):
+    from scipy.stats import binom
+    L = orc.ub_threshold(n, p, ns, eps)
+    assert ns * orc.ub_tail(n, p, L) <= eps
+    if L > math.ceil(n * p):
+        assert ns * orc.ub_tail(n, p, L - 1) > eps
+    # The union bound with the exact tail holds as well.
+    assert ns * float(binom.sf(L, n, p)) <= eps
