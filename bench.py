@@ -19,7 +19,6 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import threading
@@ -63,10 +62,11 @@ def alu_peak_tbitops(num_cus: int) -> float:
 
 
 def kernel_source_digest(kernel: str) -> str:
+    """Digest of the source file that holds the kernel's body."""
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCES[kernel], "ssbh_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2308_02856_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2308_02856_amd", "csrc",
+                           KERNEL_SOURCES[kernel]), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -119,7 +119,9 @@ def run_batched(ctx, ssbh, args):
     cap = int(mlen.max())
     seed_bits = int(lens.max()) + cap - 1
     seed = to_dev(uniform_bits(seed_bits, c["seed_seed"]))
-    l_ub = int(n / ns + 6 * math.sqrt(n / ns))
+    # Abort threshold from the Sec. III.D tail bound: every round is kept,
+    # so a sub-block's length is Binomial(N, 1/N_S); abort chance <= 1e-8.
+    l_ub, _ = ssbh.ub_threshold(n, 1.0 / ns, ns, 1e-8)
     sub_cap = sub.numel()
     out_cap = int(mlen.sum())
     out = torch.empty((out_cap + 63) // 64, dtype=torch.int64, device="cuda")
@@ -163,11 +165,29 @@ def run_batched(ctx, ssbh, args):
     hash_ms = time_events(hash_, max(3, args.steps))
     schedule = ctx.last_schedule()
     samp_ms = time_events(sample, max(3, args.steps))
+    # Sampling with sifting flags (Sec. III.B step 2): 96 % of rounds kept.
+    keep = to_dev(bernoulli_bits(n, 0.96, c["input_seed"] + 1000))
+    sub2 = torch.empty_like(sub)
+    ln2, wo2 = torch.empty_like(ln), torch.empty_like(wo)
+    st2 = torch.zeros_like(st)
+    l_ub2, _ = ssbh.ub_threshold(n, 0.96 / ns, ns, 1e-8)
+
+    def sample_sifted():
+        ctx.sample_sifted(d_in, keep, n, ns, ssbh.SAMPLE_IID, key=key,
+                          l_ub=l_ub2, sub=sub2, sub_capacity=sub_cap,
+                          length=ln2, word_off=wo2, status=st2)
+
+    sample_sifted()
+    sift_ms = time_events(sample_sifted, 3)
+    if int(st2.item()) != 0:
+        raise RuntimeError("sifted sampling status nonzero")
+    del keep, sub2
     res = dict(n=n, ns=ns, lens=lens, mlen=mlen, cap=cap, seed_bits=seed_bits,
                work=work, ms_step=ms_step,
                hash_ms=float(np.mean(hash_ms)), sample_ms=float(np.mean(samp_ms)),
                a=a, out=out, sub=sub, wo=wo, seed=seed, key=key, c=c,
-               schedule=schedule, tune_report=tune_report)
+               schedule=schedule, tune_report=tune_report, l_ub=l_ub,
+               sift_ms=float(np.mean(sift_ms)), l_ub_sifted=l_ub2)
     return res
 
 
@@ -594,10 +614,12 @@ def main() -> int:
                    "sampling": "iid", "out_len": "floor(2*n_j/5)",
                    "seed": "shared", "seed_bits": res["seed_bits"],
                    "bit_products": res["work"],
+                   "l_ub": res["l_ub"], "abort_eps": 1e-8,
                    "hash_kernel": res["schedule"]},
         "hash_only_gbps": round(res["n"] / (res["hash_ms"] * 1e-3) / 1e9, 4),
         "hash_ms": round(res["hash_ms"], 4),
         "sample_ms": round(res["sample_ms"], 4),
+        "sifted_sample_ms": round(res["sift_ms"], 4),
         "bit_products_per_s": float(f"{res['work'] / (res['hash_ms'] * 1e-3):.4g}"),
         "roofline": roof,
         "tuning": res["tune_report"].strip().splitlines(),

@@ -142,6 +142,39 @@ ssbh_status ssbh_sample(ssbh_ctx *ctx, const uint64_t *d_in, uint64_t n_bits,
                         uint64_t *d_len, uint64_t *d_word_off,
                         int32_t *d_status, void *stream);
 
+/* Sampling followed by sifting inside every sub-block (Sec. III.B steps 1-2)
+ * and the abort rule.  d_keep holds one flag per round (n_bits bits, same
+ * layout as d_in); sub-block j is the list of bits A_i with V_i = j and
+ * keep_i = 1, in ascending i, which is what sifting each sampled sub-block
+ * gives, since V_i is drawn for every round whether kept or not.  n_j and the
+ * abort rule count kept bits only.  Modes SSBH_SAMPLE_IID and
+ * SSBH_SAMPLE_EXPLICIT (SSBH_SAMPLE_PERMUTE gives SSBH_E_INVAL); every other
+ * argument, the capacity rule and the error behaviour are those of
+ * ssbh_sample. */
+ssbh_status ssbh_sample_sifted(ssbh_ctx *ctx, const uint64_t *d_in,
+                               const uint64_t *d_keep, uint64_t n_bits,
+                               uint32_t n_sub, uint32_t mode,
+                               uint64_t sample_key, const uint32_t *d_assign,
+                               uint64_t l_ub, uint64_t *d_sub,
+                               uint64_t sub_capacity_words, uint64_t *d_len,
+                               uint64_t *d_word_off, int32_t *d_status,
+                               void *stream);
+
+/* Abort threshold L_S^UB (Sec. III.D), computed on the host.  A sifted
+ * sub-block's length is Binomial(n_rounds, p_sift) (p_sift = chance that a
+ * round is kept AND lands in that sub-block); the binomial tail bound of
+ * Sec. III.D gives P(length > L) <= 1 - Phi(sqrt(2 n H(L/n, p))) for
+ * L >= n p, with H(x, p) = x ln(x/p) + (1-x) ln((1-x)/(1-p)).  A union bound
+ * over the n_sub sub-blocks (the reading taken for the formula's undefined
+ * m) gives eps(L) = n_sub * (1 - Phi(...)).
+ *  *l_ub    receives the smallest integer L >= ceil(n p) with eps(L) <= eps
+ *           (n_rounds if none is smaller: no sub-block can be longer);
+ *  *eps_at  (may be NULL) receives eps(*l_ub).
+ * Errors: SSBH_E_INVAL for p_sift outside (0, 1), eps <= 0, n_sub = 0,
+ * n_rounds = 0 or a null l_ub. */
+ssbh_status ssbh_ub_threshold(uint64_t n_rounds, double p_sift, uint32_t n_sub,
+                              double eps, uint64_t *l_ub, double *eps_at);
+
 /* ------------------------------------------- hash + concatenate (a4 - a7) --- */
 
 /* Hash every sub-block with its Toeplitz matrix T_j and concatenate the
@@ -205,6 +238,8 @@ typedef struct {
     uint64_t m_cap; uint32_t kernel;
     uint64_t *d_out; uint64_t out_capacity_bits; uint64_t *d_out_total_bits;
     int32_t *d_status;
+    const uint64_t *d_keep;  /* sifting flags as in ssbh_sample_sifted, or
+                                NULL (no sifting)                           */
 } ssbh_pipeline_desc;
 
 typedef struct ssbh_pipeline ssbh_pipeline;

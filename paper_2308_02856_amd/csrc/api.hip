@@ -229,9 +229,29 @@ ssbh_status ssbh_sample(ssbh_ctx *ctx, const uint64_t *d_in, uint64_t n_bits,
     if (!ctx) SSBH_INVAL("ctx is null");
     std::lock_guard<std::mutex> lk(ctx->mu);
     SSBH_CHECK_HIP(hipSetDevice(ctx->device));
-    return launch_sample(ctx, ctx->ws, d_in, n_bits, n_sub, mode, sample_key,
-                         d_assign, l_ub, d_sub, sub_capacity_words, d_len,
-                         d_word_off, d_status, (hipStream_t)stream);
+    return launch_sample(ctx, ctx->ws, d_in, nullptr, n_bits, n_sub, mode,
+                         sample_key, d_assign, l_ub, d_sub, sub_capacity_words,
+                         d_len, d_word_off, d_status, (hipStream_t)stream);
+}
+
+ssbh_status ssbh_sample_sifted(ssbh_ctx *ctx, const uint64_t *d_in,
+                               const uint64_t *d_keep, uint64_t n_bits,
+                               uint32_t n_sub, uint32_t mode,
+                               uint64_t sample_key, const uint32_t *d_assign,
+                               uint64_t l_ub, uint64_t *d_sub,
+                               uint64_t sub_capacity_words, uint64_t *d_len,
+                               uint64_t *d_word_off, int32_t *d_status,
+                               void *stream) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (n_bits && !d_keep) SSBH_INVAL("d_keep is null");
+    if (mode == SSBH_SAMPLE_PERMUTE)
+        SSBH_INVAL("sifting flags need i.i.d. or explicit V");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    return launch_sample(ctx, ctx->ws, d_in, d_keep, n_bits, n_sub, mode,
+                         sample_key, d_assign, l_ub, d_sub, sub_capacity_words,
+                         d_len, d_word_off, d_status, (hipStream_t)stream);
 }
 
 ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,

@@ -21,7 +21,8 @@ static ssbh_status enqueue_pipeline(ssbh_pipeline *p, hipStream_t st) {
     const ssbh_pipeline_desc &d = p->d;
     ssbh_status rc;
     if (d.d_in) {
-        rc = launch_sample(p->ctx, p->ws, d.d_in, d.n_bits, d.n_sub, d.mode,
+        rc = launch_sample(p->ctx, p->ws, d.d_in, d.d_keep, d.n_bits, d.n_sub,
+                           d.mode,
                            d.sample_key, d.d_assign, d.l_ub, d.d_sub,
                            d.sub_capacity_words, d.d_len, d.d_word_off,
                            d.d_status, st);

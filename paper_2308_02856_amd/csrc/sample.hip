@@ -16,6 +16,10 @@
 //              are shared with the neighbouring segments' runs).  OR into a
 //              zeroed buffer is order independent, so the result is
 //              bit-identical for every schedule.
+// Sifting (Sec. III.B step 2): with keep flags, V_i is still drawn for every
+// round (the draws do not depend on the flags) but only rounds with keep_i = 1
+// are counted and placed, which equals sifting every sub-block after the
+// division.
 // permutation mode: one wavefront gathers 64 bits B[k] = A[pi[k]] per step
 // and writes one 64-bit word with a ballot.
 #include <algorithm>
@@ -34,6 +38,7 @@ struct SampleArgs {
     uint32_t vbits;          // ceil(log2(ns))
     uint64_t key;
     const uint32_t *assign;  // explicit mode
+    const uint64_t *keep;    // sifting flags (nullptr = keep every round)
     uint64_t seg_bits;       // multiple of 64
     uint32_t nseg;
     uint32_t nchunk;
@@ -61,6 +66,11 @@ __device__ __forceinline__ uint32_t sample_v(const SampleArgs &a, uint64_t i) {
 
 __global__ void k_init_status(int32_t *status) { *status = 0; }
 
+// keep_i (1 without flags).  i >> 6 is the same word for all lanes of a step.
+__device__ __forceinline__ bool kept(const SampleArgs &a, uint64_t i) {
+    return !a.keep || ((a.keep[i >> 6] >> (i & 63)) & 1ull);
+}
+
 template <bool EXPLICIT>
 __global__ __launch_bounds__(256) void k_hist(SampleArgs a) {
     extern __shared__ uint32_t lds[];
@@ -83,8 +93,8 @@ __global__ __launch_bounds__(256) void k_hist(SampleArgs a) {
     bool bad = false;
     for (uint64_t i = i0 + lane; i < i1; i += 64) {
         const uint32_t v = sample_v<EXPLICIT>(a, i);
-        if (v < a.ns) atomicAdd(&hist[v], 1u);
-        else bad = true;
+        if (v >= a.ns) bad = true;
+        else if (kept(a, i)) atomicAdd(&hist[v], 1u);
     }
     if (bad) atomicExch(a.status, (int32_t)SSBH_E_INVAL);
     __builtin_amdgcn_wave_barrier();
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(64) void k_scatter(SampleArgs a) {
     uint64_t grp_next = load_word_group(a.in, (i0 >> 6) + 64, nw_in, lane);
     for (uint64_t base = i0; base < i1; base += 64) {
         const uint64_t i = base + lane;
-        const bool valid = i < i1;
+        const bool valid = i < i1 && kept(a, i);
         const uint32_t k = (uint32_t)((base - i0) >> 6) & 63u;
         if (k == 0 && base != i0) {
             grp = grp_next;
@@ -335,7 +345,7 @@ __global__ __launch_bounds__(64) void k_scatter_tab(SampleArgs a) {
     uint32_t v_next = (i0 + lane < i1) ? sample_v<EXPLICIT>(a, i0 + lane) : 0u;
     for (uint64_t base = i0; base < i1; base += 64) {
         const uint64_t i = base + lane;
-        const bool valid = i < i1;
+        const bool valid = i < i1 && kept(a, i);
         const uint32_t v = v_next;
         const uint32_t k = (uint32_t)((base - i0) >> 6) & 63u;
         if (k == 0 && base != i0) {
@@ -450,7 +460,8 @@ ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
 }
 
 ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
-                          uint64_t n, uint32_t ns, uint32_t mode, uint64_t key,
+                          const uint64_t *d_keep, uint64_t n, uint32_t ns,
+                          uint32_t mode, uint64_t key,
                           const uint32_t *d_assign, uint64_t l_ub,
                           uint64_t *d_sub, uint64_t sub_cap, uint64_t *d_len,
                           uint64_t *d_woff, int32_t *d_status,
@@ -468,6 +479,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     SSBH_CHECK_HIP(hipGetLastError());
 
     if (mode == SSBH_SAMPLE_PERMUTE) {
+        if (d_keep) SSBH_INVAL("sifting flags need i.i.d. or explicit V");
         if (!d_assign) SSBH_INVAL("permutation mode needs d_assign");
         if (n % ns) SSBH_INVAL("n_sub (%u) must divide n_bits (%llu)", ns,
                                (unsigned long long)n);
@@ -504,7 +516,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
 
     SampleArgs a{};
     a.in = d_in; a.n = n; a.ns = ns; a.vbits = ceil_log2(ns); a.key = key;
-    a.assign = d_assign; a.sub = d_sub; a.sub_cap = sub_cap; a.len = d_len;
+    a.assign = d_assign; a.keep = d_keep; a.sub = d_sub; a.sub_cap = sub_cap; a.len = d_len;
     a.woff = d_woff; a.l_ub = l_ub; a.status = d_status;
     const uint64_t seg = segment_bits(ns);
     a.seg_bits = seg;

@@ -226,7 +226,7 @@ static ssbh_status enqueue_job(ssbh_ctx *ctx, ServeState &S, Job &job) {
     }
     ssbh_status rc = launch_seed(j.seed_key, d_seed, p.seed_bits, st);
     if (rc != SSBH_OK) return rc;
-    rc = launch_sample(ctx, ws, d_in, p.n, j.n_sub, SSBH_SAMPLE_IID,
+    rc = launch_sample(ctx, ws, d_in, nullptr, p.n, j.n_sub, SSBH_SAMPLE_IID,
                        j.sample_key, nullptr, p.l_ub, d_sub, p.sub_cap, d_len,
                        d_woff, d_status, st);
     if (rc != SSBH_OK) return rc;

@@ -102,7 +102,8 @@ namespace ssbh {
 
 // Kernel-launch layers (one per source file).
 ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
-                          uint64_t n_bits, uint32_t n_sub, uint32_t mode,
+                          const uint64_t *d_keep, uint64_t n_bits,
+                          uint32_t n_sub, uint32_t mode,
                           uint64_t key, const uint32_t *d_assign,
                           uint64_t l_ub, uint64_t *d_sub, uint64_t sub_cap,
                           uint64_t *d_len, uint64_t *d_woff, int32_t *d_status,

@@ -67,7 +67,7 @@ class PipelineDesc(ctypes.Structure):
                 ("kernel", ctypes.c_uint32), ("d_out", ctypes.c_void_p),
                 ("out_capacity_bits", ctypes.c_uint64),
                 ("d_out_total_bits", ctypes.c_void_p),
-                ("d_status", ctypes.c_void_p)]
+                ("d_status", ctypes.c_void_p), ("d_keep", ctypes.c_void_p)]
 
 
 class SsbhError(RuntimeError):
@@ -101,6 +101,13 @@ def lib() -> ctypes.CDLL:
     L.ssbh_sample.restype = _i32
     L.ssbh_sample.argtypes = [_vp, _vp, _u64, _u32, _u32, _u64, _vp, _u64,
                               _vp, _u64, _vp, _vp, _vp, _vp]
+    L.ssbh_sample_sifted.restype = _i32
+    L.ssbh_sample_sifted.argtypes = [_vp, _vp, _vp, _u64, _u32, _u32, _u64,
+                                     _vp, _u64, _vp, _u64, _vp, _vp, _vp, _vp]
+    L.ssbh_ub_threshold.restype = _i32
+    L.ssbh_ub_threshold.argtypes = [_u64, ctypes.c_double, _u32,
+                                    ctypes.c_double, ctypes.POINTER(_u64),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.ssbh_hash_batch.restype = _i32
     L.ssbh_hash_batch.argtypes = [_vp, _vp, _u64, _vp, _vp, _u32, _u32, _u64,
                                   _u64, _vp, _vp, _u64, _u64, _u64, _u32, _vp,
@@ -221,6 +228,29 @@ class Context:
                                  int(sub_capacity), _ptr(length),
                                  _ptr(word_off), _ptr(status),
                                  _stream(stream)))
+        return sub, length, word_off, status
+
+    def sample_sifted(self, inp, keep, n_bits: int, n_sub: int,
+                      mode: int = SAMPLE_IID, key: int = 0, assign=None,
+                      l_ub: int = 0, sub=None, sub_capacity: int | None = None,
+                      length=None, word_off=None, status=None, stream=None):
+        """ssbh_sample_sifted; returns (sub, len, word_off, status)."""
+        dev = self._dev()
+        if sub_capacity is None:
+            sub_capacity = words(n_bits) + n_sub
+        if sub is None:
+            sub = torch.empty(max(1, sub_capacity), dtype=torch.int64, device=dev)
+        if length is None:
+            length = torch.empty(max(1, n_sub), dtype=torch.int64, device=dev)
+        if word_off is None:
+            word_off = torch.empty(max(1, n_sub), dtype=torch.int64, device=dev)
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+        _check(lib().ssbh_sample_sifted(
+            self._h, _ptr(inp), _ptr(keep), int(n_bits), int(n_sub), int(mode),
+            int(key) & (2**64 - 1), _ptr(assign), int(l_ub), _ptr(sub),
+            int(sub_capacity), _ptr(length), _ptr(word_off), _ptr(status),
+            _stream(stream)))
         return sub, length, word_off, status
 
     # ------------------------------------------------------------- hashing
@@ -396,6 +426,17 @@ class Pipeline:
             self.close()
         except Exception:
             pass
+
+
+def ub_threshold(n_rounds: int, p_sift: float, n_sub: int,
+                 eps: float) -> tuple[int, float]:
+    """ssbh_ub_threshold: (L_S^UB, abort-chance bound at it)."""
+    l_ub = _u64()
+    at = ctypes.c_double()
+    _check(lib().ssbh_ub_threshold(int(n_rounds), float(p_sift), int(n_sub),
+                                   float(eps), ctypes.byref(l_ub),
+                                   ctypes.byref(at)))
+    return int(l_ub.value), float(at.value)
 
 
 def status_name(code: int) -> str:
