@@ -128,7 +128,7 @@ def run_batched(ctx, ssbh, args):
     tot = torch.zeros(1, dtype=torch.int64, device="cuda")
     work = int((lens * mlen).sum())
     kernel = {"auto": ssbh.K_AUTO, "valu": ssbh.K_VALU,
-              "mfma": ssbh.K_MFMA_I8}[args.kernel]
+              "mfma": ssbh.K_MFMA_I8, "fft": ssbh.K_FFT}[args.kernel]
     tune_report = ""
     if kernel == ssbh.K_AUTO and not args.no_tune:
         log("batched: autotuning the hash kernel (untimed)")
@@ -519,7 +519,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--single-steps", type=int, default=2)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
+    ap.add_argument("--kernel", default="auto",
+                    choices=["auto", "valu", "mfma", "fft"],
                     help="hash kernel of the batched step (auto = tuned)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-subblocks", type=int, default=64)

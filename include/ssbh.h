@@ -56,7 +56,10 @@ typedef enum {
     SSBH_E_NOMEM = -3,             /* device memory or HBM budget exhausted  */
     SSBH_E_DEVICE = -4,            /* a HIP runtime call failed              */
     SSBH_E_UNKNOWN_JOB = -5,       /* serving: no such job id                */
-    SSBH_E_UNSUPPORTED = -6        /* outside this build's limits            */
+    SSBH_E_UNSUPPORTED = -6,       /* outside this build's limits            */
+    SSBH_E_PRECISION = -7          /* FFT hash: an output entry was not within
+                                      1/4 of an integer (never expected; the
+                                      output is then not trusted)            */
 } ssbh_status;
 
 /* Sampling modes (Sec. III.B step 1). */
@@ -77,8 +80,11 @@ enum {
 enum {
     SSBH_K_AUTO = 0,          /* library picks (autotuned)                    */
     SSBH_K_VALU = 1,          /* bit-sliced AND-XOR + popcount parity         */
-    SSBH_K_MFMA_I8 = 2        /* int8 matrix cores, int32 sums, then mod 2;
+    SSBH_K_MFMA_I8 = 2,       /* int8 matrix cores, int32 sums, then mod 2;
                                  only for a shared seed (seed_stride == 0)    */
+    SSBH_K_FFT = 3            /* middle product by double-precision FFTs,
+                                 every entry rounded and checked; only for a
+                                 shared seed of at most 2^18 bits             */
 };
 
 /* Limits of this build. */
@@ -366,6 +372,11 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
  * depend on any of them. */
 ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm,
                                    int ksplit);
+
+/* Force the FFT hash's chunk: sub-block pairs transformed per pass (each
+ * pair holds 2^18 complex doubles of scratch at the largest length; 0 =
+ * library choice).  The output bits do not depend on it. */
+ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs);
 
 /* Where the VALU hash kernel reads the 32-bit column words of the sub-blocks
  * from: 0 = staged in LDS with the seed window, 1 = through the scalar data

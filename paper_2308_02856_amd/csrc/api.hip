@@ -83,6 +83,8 @@ void Workspace::release() {
     plan.release();
     tiles.release();
     counters.release();
+    fft_spec.release();
+    fft_work.release();
 }
 
 // Default VALU schedule: 16 rows per lane, 4 wavefronts (4096 rows per
@@ -140,6 +142,12 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                 r.kernel = SSBH_K_MFMA_I8;
                 return launch_hash_mfma(ctx, ws, r, ms, stream);
             }
+            if (sscanf(choice.c_str(), "fft:%u", &d) == 1 && q.stride == 0) {
+                FftSchedule fs;
+                fs.chunk_pairs = d;
+                r.kernel = SSBH_K_FFT;
+                return launch_hash_fft(ctx, ws, r, fs, stream);
+            }
             if (sscanf(choice.c_str(), "valu:%d:%d:%u:%u", &a, &b, &d, &e) == 4) {
                 ValuSchedule vs = choose_valu(ctx, q);
                 vs.r = a; vs.waves = b; vs.chunk_cols = d; vs.tile_cols = e;
@@ -163,6 +171,11 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         }
         ms.ksplit = ctx->forced_mfma[3];
         return launch_hash_mfma(ctx, ws, q, ms, stream);
+    }
+    if (q.kernel == SSBH_K_FFT) {
+        FftSchedule fs;
+        fs.chunk_pairs = ctx->forced_fft_chunk;
+        return launch_hash_fft(ctx, ws, q, fs, stream);
     }
     if (q.kernel != SSBH_K_VALU) SSBH_INVAL("unknown kernel %u", q.kernel);
     return launch_hash_valu(ctx, ws, q, choose_valu(ctx, q), stream);
@@ -300,6 +313,14 @@ ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
     if (seed_bits && !d_seed) SSBH_INVAL("d_seed is null");
     if (kernel == SSBH_K_MFMA_I8 && seed_stride != 0)
         SSBH_INVAL("the MFMA kernel needs a shared seed (seed_stride = 0)");
+    if (kernel == SSBH_K_FFT && seed_stride != 0)
+        SSBH_INVAL("the FFT hash needs a shared seed (seed_stride = 0)");
+    if (kernel == SSBH_K_FFT && fft_length(seed_bits) > kMaxFftLength) {
+        set_error("the FFT hash supports seeds of at most %llu bits",
+                  (unsigned long long)kMaxFftLength);
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (kernel > SSBH_K_FFT) SSBH_INVAL("unknown kernel %u", kernel);
     std::lock_guard<std::mutex> lk(ctx->mu);
     SSBH_CHECK_HIP(hipSetDevice(ctx->device));
     HashRequest q{d_sub, sub_capacity_words, d_len, d_word_off, n_sub,
@@ -333,6 +354,14 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
     ctx->forced_valu_waves = waves;
     ctx->forced_tile_cols = tile_cols;
     ctx->forced_chunk_cols = chunk_cols;
+    return SSBH_OK;
+}
+
+ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->forced_fft_chunk = chunk_pairs;
     return SSBH_OK;
 }
 

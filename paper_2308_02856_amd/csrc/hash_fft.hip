@@ -1,0 +1,553 @@
+// Sub-quadratic shared-seed hash: the Toeplitz product as a middle product
+// computed with double-precision FFTs (the fast route for CPUs and GPUs that
+// Sec. I mentions), exact by construction of the bound and checked per output.
+//
+// With T[r][c] = s[c - r + M - 1] and xr_j the reversal of x_j,
+//     K_j[r] = (s * xr_j)[n_j + M - 2 - r]  mod 2,
+// a linear convolution of 0/1 sequences.  With L >= seed_bits a cyclic
+// convolution of length L gives those entries unaliased.  Two sub-blocks ride
+// in one complex transform (xr_a real, xr_b imaginary): the seed is real, so
+// the product with its spectrum keeps them apart and the inverse returns
+// (s * xr_a) + i (s * xr_b).
+//
+// Exactness: entries are integers in [0, n_j]; for 0/1 data and L <= 2^18 the
+// double-precision FFT error is below 1e-8, far from 1/2.  Every output entry
+// is rounded and its distance to the integer is checked (> 1/4 sets
+// SSBH_E_PRECISION), so a result is never silently wrong.
+//
+// Transform (four-step, N1 = 64, N2 = L / 64; natural input, transposed
+// frequency order Z[N2 k1 + k2] = X[k1 + 64 k2], which the pointwise product
+// does not mind):
+//   k_fft_cols   64-point FFTs down the columns of a 64-column tile (bits
+//                loaded and expanded on the fly), times w_L^(n2 k1), store.
+//   k_fft_rows   N2-point FFT of a row, times the seed spectrum, inverse FFT,
+//                times w_L^(-n2 k1), store (one pass over the data).
+//   k_fft_out    inverse 64-point FFTs down the columns, 1/L, round, parity;
+//                64 consecutive output rows per wavefront ballot.
+// The seed spectrum comes from the same two forward passes.  LDS FFTs are
+// Stockham autosort stages with radix-8 butterflies in registers (radix 2 or
+// 4 last), twiddles from a table of w_4096^k; the first stage of each pass
+// reads global memory (or bits) and the last one writes its result straight
+// out (spectrum product, twiddle, or parity ballot fused in).
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include <stdio.h>
+
+#include "ssbh_internal.hpp"
+
+namespace ssbh {
+
+ssbh_status plan_only(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                      hipStream_t stream);
+
+namespace {
+
+constexpr int kN1 = 64;        // column FFT length (and columns per tile)
+constexpr int kTW = 4096;      // size of the w_4096 twiddle table
+constexpr int kThreads = 256;
+
+struct FftArgs {
+    const uint64_t *sub;
+    const uint64_t *len, *woff, *mlen, *ooff;
+    const uint64_t *seed;
+    uint64_t seed_bits;
+    uint64_t mcap;
+    uint32_t ns;
+    uint32_t n2;               // L / 64
+    uint64_t L;
+    uint32_t pair0;            // first pair of this chunk
+    double2 *work;             // [pairs in chunk][L]
+    double2 *spec;             // [L], transposed frequency order
+    const double2 *tw;         // w_4096^k, k < 4096
+    const double2 *tlo, *thi;  // w_L^e = thi[e >> 9] * tlo[e & 511]
+    uint64_t *out;
+    int32_t *status;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+    return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 conj2(double2 a) {
+    return make_double2(a.x, -a.y);
+}
+// Multiply by -i (forward) or +i (inverse).
+template <bool INV>
+__device__ __forceinline__ double2 rot90(double2 a) {
+    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(double2 (&v)[2]) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2 (&v)[4]) {
+    const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const double2 a2 = cadd(v[1], v[3]), a3 = rot90<INV>(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+}
+
+// 8-point DFT, natural order in and out (radix-2 decimation in frequency,
+// then the bit-reversal permutation).
+template <bool INV>
+__device__ __forceinline__ void dft8(double2 (&v)[8]) {
+    const double h = 0.70710678118654752440;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double2 a = v[r], b = v[r + 4];
+        v[r] = cadd(a, b);
+        v[r + 4] = csub(a, b);
+    }
+    v[5] = cmul(v[5], make_double2(h, INV ? h : -h));
+    v[6] = rot90<INV>(v[6]);
+    v[7] = cmul(v[7], make_double2(-h, INV ? h : -h));
+#pragma unroll
+    for (int base = 0; base < 8; base += 4) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const double2 a = v[base + r], b = v[base + r + 2];
+            v[base + r] = cadd(a, b);
+            v[base + r + 2] = csub(a, b);
+        }
+    }
+    v[3] = rot90<INV>(v[3]);
+    v[7] = rot90<INV>(v[7]);
+#pragma unroll
+    for (int p = 0; p < 8; p += 2) {
+        const double2 a = v[p], b = v[p + 1];
+        v[p] = cadd(a, b);
+        v[p + 1] = csub(a, b);
+    }
+    double2 t = v[1]; v[1] = v[4]; v[4] = t;
+    t = v[3]; v[3] = v[6]; v[6] = t;
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dftR(double2 (&v)[R]) {
+    if constexpr (R == 8) dft8<INV>(v);
+    else if constexpr (R == 4) dft4<INV>(v);
+    else dft2<INV>(v);
+}
+
+// LDS address of element e of FFT f: F interleaved FFTs (e * F + f; lanes
+// walk f, so every access is contiguous), or one FFT with the element index
+// XOR-swizzled inside blocks of 8 (contiguous and stride-8 accesses of 8
+// lanes then cover all banks).
+template <int F>
+__device__ __forceinline__ int lds_addr(int f, int e) {
+    if constexpr (F > 1) return e * F + f;
+    else return e ^ ((e >> 3) & 7);
+}
+
+// Twiddles w^r, r < R, of w = w_4096^base (conjugated for the inverse):
+// w, w^2, w^4 from the table, the rest by products.
+template <int R, bool INV>
+__device__ __forceinline__ void twiddle(double2 (&v)[R], int base,
+                                        const double2 *tw) {
+    auto ld = [&](int k) { double2 w = tw[k]; return INV ? conj2(w) : w; };
+    const double2 w1 = ld(base);
+    v[1] = cmul(v[1], w1);
+    if constexpr (R >= 4) {
+        const double2 w2 = ld(2 * base);
+        const double2 w3 = cmul(w1, w2);
+        v[2] = cmul(v[2], w2);
+        v[3] = cmul(v[3], w3);
+        if constexpr (R == 8) {
+            const double2 w4 = ld(4 * base);
+            v[4] = cmul(v[4], w4);
+            v[5] = cmul(v[5], cmul(w4, w1));
+            v[6] = cmul(v[6], cmul(w4, w2));
+            v[7] = cmul(v[7], cmul(w4, w3));
+        }
+    }
+}
+
+// One radix-R Stockham stage over F FFTs of length N.  Group j of an FFT
+// takes elements j + r N/R (from `ld`), twiddles them by w_{Ns R}^(r (j mod
+// Ns)), transforms, and hands element (j / Ns) Ns R + (j mod Ns) + r Ns to
+// `st`.  MID: barrier between all loads and all stores (they share the LDS
+// buffer); END: barrier after the stores (the next stage reads them).
+template <int N, int R, int F, bool INV, bool MID, bool END, class Ld, class St>
+__device__ __forceinline__ void fft_stage(int span, const double2 *tw, Ld ld,
+                                          St st) {
+    constexpr int G = N / R;
+    constexpr int TOTAL = F * G;
+    constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
+    double2 v[PER][R];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int g = threadIdx.x + kThreads * p;
+        if (TOTAL % kThreads == 0 || g < TOTAL) {
+            const int f = g % F, j = g / F;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[p][r] = ld(f, j + r * G);
+            if (span > 1) twiddle<R, INV>(v[p], (j % span) * (kTW / (span * R)), tw);
+            dftR<R, INV>(v[p]);
+        }
+    }
+    if (MID) __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int g = threadIdx.x + kThreads * p;
+        if (TOTAL % kThreads == 0 || g < TOTAL) {
+            const int f = g % F, j = g / F;
+            const int d = (j / span) * span * R + (j % span);
+#pragma unroll
+            for (int r = 0; r < R; ++r) st(f, d + r * span, v[p][r]);
+        }
+    }
+    if (END) __syncthreads();
+}
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+// A whole FFT of length N over F transforms: the first stage reads with
+// `first_ld`, the last stage writes with `last_st`, the stages between go
+// through the LDS buffer.  Radix 8 stages, then one radix 2 or 4 stage when
+// log2 N is not a multiple of 3.  N >= 64.
+template <int N, int F, bool INV, class Ld, class St>
+__device__ __forceinline__ void fft_run(double2 *buf, const double2 *tw,
+                                        Ld first_ld, St last_st) {
+    constexpr int LG = ilog2c(N);
+    constexpr int S8 = LG / 3, REM = LG % 3;
+    constexpr int NST = S8 + (REM ? 1 : 0);
+    static_assert(NST >= 2, "at least two stages");
+    auto lds_ld = [&](int f, int e) { return buf[lds_addr<F>(f, e)]; };
+    auto lds_st = [&](int f, int e, double2 x) { buf[lds_addr<F>(f, e)] = x; };
+    int span = 1;
+    // First stage: from first_ld into LDS (first_ld may read the same LDS
+    // buffer, hence the barrier between loads and stores).
+    fft_stage<N, 8, F, INV, true, true>(span, tw, first_ld, lds_st);
+    span *= 8;
+#pragma unroll
+    for (int s = 1; s < NST - 1; ++s) {
+        fft_stage<N, 8, F, INV, true, true>(span, tw, lds_ld, lds_st);
+        span *= 8;
+    }
+    // Last stage: last_st may write the LDS buffer the stage reads.
+    if constexpr (REM == 0)
+        fft_stage<N, 8, F, INV, true, false>(span, tw, lds_ld, last_st);
+    else if constexpr (REM == 1)
+        fft_stage<N, 2, F, INV, true, false>(span, tw, lds_ld, last_st);
+    else
+        fft_stage<N, 4, F, INV, true, false>(span, tw, lds_ld, last_st);
+}
+
+__device__ __forceinline__ double2 omega_l(const FftArgs &a, uint64_t e) {
+    return cmul(a.thi[e >> 9], a.tlo[e & 511]);
+}
+
+// Bits b0 .. b0+63 of a bit string of nbits bits at words w (0 outside).
+__device__ __forceinline__ uint64_t window64(const uint64_t *w, int64_t nbits,
+                                             int64_t b0) {
+    if (b0 >= nbits || b0 <= -64) return 0ull;
+    const int64_t wi = b0 >> 6;                 // floor division
+    const int sh = (int)(b0 & 63);
+    const uint64_t lo = (wi >= 0) ? w[wi] : 0ull;
+    const uint64_t hi = ((wi + 1) * 64 < nbits) ? w[wi + 1] : 0ull;
+    uint64_t v = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+    const int64_t valid = nbits - b0;
+    if (valid < 64) v &= (1ull << valid) - 1ull;
+    return v;
+}
+
+// Forward column pass.  SEED: the input is the seed itself (u[q] = s[q],
+// real); else pair p's two reversed sub-blocks (real, imaginary).  The first
+// stage reads bits, the last stage stores times w_L^(n2 k1).
+template <bool SEED>
+__global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
+    __shared__ double2 buf[kN1 * kN1];
+    __shared__ uint64_t win[2][kN1];
+    if (*a.status) return;
+    const uint32_t n2 = a.n2;
+    const uint32_t c0 = blockIdx.x * kN1;
+    const uint32_t pl = blockIdx.y;
+    const int t = threadIdx.x;
+    // 64-bit windows: thread (n1, part) for the 64 columns of this tile.
+    if (t < 2 * kN1) {
+        const int n1 = t & (kN1 - 1), part = t >> 6;
+        uint64_t v = 0ull;
+        if (SEED) {
+            if (part == 0)
+                v = window64(a.seed, (int64_t)a.seed_bits,
+                             (int64_t)n2 * n1 + c0);
+        } else {
+            const uint64_t j = 2ull * (a.pair0 + pl) + part;
+            if (j < a.ns) {
+                const int64_t n = (int64_t)a.len[j];
+                // xr[q] = x[n-1-q] for q = n2*n1 + c0 + i, i < 64.
+                const int64_t b0 = n - 1 - ((int64_t)n2 * n1 + c0) - 63;
+                v = __brevll(window64(a.sub + a.woff[j], n, b0));
+            }
+        }
+        win[part][n1] = v;
+    }
+    __syncthreads();
+    double2 *y = a.work + (size_t)pl * a.L;
+    // Element (column i = f, row n1 = e).
+    auto ld = [&](int f, int e) {
+        return make_double2((double)((win[0][e] >> f) & 1ull),
+                            (double)((win[1][e] >> f) & 1ull));
+    };
+    auto st = [&](int f, int k1, double2 x) {
+        const uint64_t n2i = c0 + f;
+        y[(size_t)k1 * n2 + n2i] = cmul(x, omega_l(a, n2i * k1));
+    };
+    fft_run<kN1, kN1, false>(buf, a.tw, ld, st);
+}
+
+// Row pass.  SPEC: forward only, the result is the seed spectrum; else
+// forward, times the spectrum, inverse, times w_L^(-n2 k1).
+template <int N2, bool SPEC>
+__global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
+    __shared__ double2 buf[N2];
+    if (*a.status) return;
+    const uint32_t k1 = blockIdx.x;
+    const uint32_t pl = blockIdx.y;
+    double2 *y = a.work + (size_t)pl * a.L + (size_t)k1 * N2;
+    double2 *sp = a.spec + (size_t)k1 * N2;
+    auto gl_ld = [&](int, int e) { return y[e]; };
+    auto lds_ld = [&](int, int e) { return buf[lds_addr<1>(0, e)]; };
+    if (SPEC) {
+        auto spec_st = [&](int, int e, double2 x) { sp[e] = x; };
+        fft_run<N2, 1, false>(buf, a.tw, gl_ld, spec_st);
+        return;
+    }
+    // Forward, the spectrum product fused into the last stage's stores.
+    auto mul_st = [&](int, int e, double2 x) {
+        buf[lds_addr<1>(0, e)] = cmul(x, sp[e]);
+    };
+    fft_run<N2, 1, false>(buf, a.tw, gl_ld, mul_st);
+    __syncthreads();
+    auto out_st = [&](int, int e, double2 x) {
+        y[e] = cmul(x, conj2(omega_l(a, (uint64_t)e * k1)));
+    };
+    fft_run<N2, 1, true>(buf, a.tw, lds_ld, out_st);
+}
+
+// XOR `bits` (bit t = output row rlo + t, already cleared outside [0, m))
+// into the output at bit offset o + rlo.
+__device__ __forceinline__ void put_rows(uint64_t *out, uint64_t o, int64_t rlo,
+                                         uint64_t bits) {
+    if (!bits) return;
+    if (rlo < 0) {
+        bits >>= (int)(-rlo);
+        rlo = 0;
+    }
+    const uint64_t p = o + (uint64_t)rlo;
+    const uint64_t wq = p >> 6;
+    const int sh = (int)(p & 63);
+    atomicXor((unsigned long long *)&out[wq], (unsigned long long)(bits << sh));
+    if (sh && (bits >> (64 - sh)))
+        atomicXor((unsigned long long *)&out[wq + 1],
+                  (unsigned long long)(bits >> (64 - sh)));
+}
+
+// Inverse column pass and output.  The last stage hands the wavefront the 64
+// columns of one row n1 (lane = column), so the parities of 64 consecutive
+// output rows come out of one ballot.
+__global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
+    __shared__ double2 buf[kN1 * kN1];
+    if (*a.status) return;
+    const uint32_t n2 = a.n2;
+    const uint32_t c0 = blockIdx.x * kN1;
+    const uint32_t pl = blockIdx.y;
+    const double2 *w = a.work + (size_t)pl * a.L;
+    const int lane = threadIdx.x & 63;
+    const double scale = 1.0 / (double)a.L;
+    int64_t n[2], m[2];
+    uint64_t o[2];
+    bool has[2];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        const uint64_t j = 2ull * (a.pair0 + pl) + part;
+        has[part] = j < a.ns;
+        n[part] = has[part] ? (int64_t)a.len[j] : 0;
+        m[part] = has[part] ? (int64_t)a.mlen[j] : 0;
+        o[part] = has[part] ? a.ooff[j] : 0;
+    }
+    bool bad = false;
+    auto ld = [&](int f, int e) { return w[(size_t)e * n2 + c0 + f]; };
+    // Called with the same row n1 on all 64 lanes (f = lane).
+    auto st = [&](int f, int n1, double2 x) {
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+            if (!has[part]) continue;                        // uniform
+            // Lane i holds q = n2*n1 + c0 + i, i.e. row r = rhi - i.
+            const int64_t rhi = n[part] + (int64_t)a.mcap - 2 -
+                                ((int64_t)n2 * n1 + c0);
+            const int64_t rlo = rhi - 63;
+            if (rhi < 0 || rlo >= m[part]) continue;         // uniform
+            const double v = (part ? x.y : x.x) * scale;
+            const double rv = rint(v);
+            const int64_t r = rhi - f;
+            const bool need = r >= 0 && r < m[part];
+            if (need && (fabs(v - rv) > 0.25 || rv < -0.25)) bad = true;
+            const bool bit = need && (((int64_t)rv) & 1);
+            const uint64_t word = __brevll(ballot64(bit));  // bit t = row rlo + t
+            if (lane == 0) put_rows(a.out, o[part], rlo, word);
+        }
+    };
+    fft_run<kN1, kN1, true>(buf, a.tw, ld, st);
+    if (bad) atomicCAS(a.status, 0, (int32_t)SSBH_E_PRECISION);
+}
+
+// Twiddle tables, computed once per transform length on the host in long
+// double and kept by the context.
+struct FftTables {
+    DevBuf tw, tlo, thi;
+};
+std::mutex g_tab_mu;
+std::map<std::pair<int, uint64_t>, FftTables *> g_tables;   // (device, L)
+
+ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tables.find({device, L});
+    if (it != g_tables.end()) {
+        *out = it->second;
+        return SSBH_OK;
+    }
+    const long double two_pi = 6.283185307179586476925286766559L;
+    std::vector<double2> tw(kTW), tlo(512), thi(std::max<uint64_t>(1, L / 512));
+    for (int k = 0; k < kTW; ++k) {
+        const long double ang = -two_pi * (long double)k / (long double)kTW;
+        tw[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    for (uint64_t k = 0; k < 512; ++k) {
+        const long double ang = -two_pi * (long double)k / (long double)L;
+        tlo[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    for (uint64_t k = 0; k < thi.size(); ++k) {
+        const long double ang = -two_pi * (long double)(k * 512) / (long double)L;
+        thi[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    auto *t = new FftTables();
+    ssbh_status st;
+    if ((st = t->tw.reserve(tw.size() * sizeof(double2))) != SSBH_OK ||
+        (st = t->tlo.reserve(tlo.size() * sizeof(double2))) != SSBH_OK ||
+        (st = t->thi.reserve(thi.size() * sizeof(double2))) != SSBH_OK) {
+        t->tw.release(); t->tlo.release(); t->thi.release();
+        delete t;
+        return st;
+    }
+    if (hipMemcpy(t->tw.ptr, tw.data(), tw.size() * sizeof(double2),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->tlo.ptr, tlo.data(), tlo.size() * sizeof(double2),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->thi.ptr, thi.data(), thi.size() * sizeof(double2),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        t->tw.release(); t->tlo.release(); t->thi.release();
+        delete t;
+        set_error("twiddle table upload failed");
+        return SSBH_E_DEVICE;
+    }
+    g_tables[{device, L}] = t;
+    *out = t;
+    return SSBH_OK;
+}
+
+template <int N2>
+void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
+                 hipStream_t stream) {
+    if (spec)
+        hipLaunchKernelGGL((k_fft_rows<N2, true>), dim3(kN1, 1), dim3(kThreads),
+                           0, stream, a);
+    else
+        hipLaunchKernelGGL((k_fft_rows<N2, false>), dim3(kN1, pairs),
+                           dim3(kThreads), 0, stream, a);
+}
+
+void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
+    switch (a.n2) {
+    case 64: launch_rows<64>(a, pairs, spec, stream); break;
+    case 128: launch_rows<128>(a, pairs, spec, stream); break;
+    case 256: launch_rows<256>(a, pairs, spec, stream); break;
+    case 512: launch_rows<512>(a, pairs, spec, stream); break;
+    case 1024: launch_rows<1024>(a, pairs, spec, stream); break;
+    case 2048: launch_rows<2048>(a, pairs, spec, stream); break;
+    default: launch_rows<4096>(a, pairs, spec, stream); break;
+    }
+}
+
+}  // namespace
+
+uint64_t fft_length(uint64_t seed_bits) {
+    uint64_t L = 4096;
+    while (L < seed_bits) L <<= 1;
+    return L;
+}
+
+ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                            const FftSchedule &s, hipStream_t stream) {
+    if (q.stride != 0) {
+        set_error("the FFT hash needs a shared seed (seed_stride = 0)");
+        return SSBH_E_INVAL;
+    }
+    const uint64_t L = fft_length(q.seed_bits);
+    if (L > kMaxFftLength) {
+        set_error("the FFT hash supports seeds of at most %llu bits",
+                  (unsigned long long)kMaxFftLength);
+        return SSBH_E_UNSUPPORTED;
+    }
+    ssbh_status st = plan_only(ctx, ws, q, stream);
+    if (st != SSBH_OK) return st;
+    const uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : 32;
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u", s.chunk_pairs);
+    if (!q.n_sub) return SSBH_OK;
+    FftTables *tab = nullptr;
+    if ((st = get_tables(ctx->device, L, &tab)) != SSBH_OK) return st;
+    const uint64_t pairs = (q.n_sub + 1ull) / 2;
+    const uint32_t cp = (uint32_t)std::min<uint64_t>(pairs, chunk);
+    if ((st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK) return st;
+    if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
+        return st;
+    FftArgs a{};
+    uint64_t *plan = ws.plan.as<uint64_t>();
+    a.sub = q.sub; a.len = q.len; a.woff = q.woff;
+    a.mlen = plan; a.ooff = plan + q.n_sub;
+    a.seed = q.seed; a.seed_bits = q.seed_bits;
+    a.mcap = q.m_cap; a.ns = q.n_sub;
+    a.L = L; a.n2 = (uint32_t)(L / kN1);
+    a.work = ws.fft_work.as<double2>();
+    a.spec = ws.fft_spec.as<double2>();
+    a.tw = tab->tw.as<double2>();
+    a.tlo = tab->tlo.as<double2>();
+    a.thi = tab->thi.as<double2>();
+    a.out = q.out;
+    a.status = q.status;
+    const uint32_t tiles = a.n2 / kN1;
+    // Seed spectrum.
+    a.pair0 = 0;
+    hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
+                       stream, a);
+    rows(a, 1, true, stream);
+    for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
+        const uint32_t np = (uint32_t)std::min<uint64_t>(cp, pairs - p0);
+        a.pair0 = (uint32_t)p0;
+        hipLaunchKernelGGL(k_fft_cols<false>, dim3(tiles, np), dim3(kThreads),
+                           0, stream, a);
+        rows(a, np, false, stream);
+        hipLaunchKernelGGL(k_fft_out, dim3(tiles, np), dim3(kThreads), 0,
+                           stream, a);
+    }
+    SSBH_CHECK_HIP(hipGetLastError());
+    return SSBH_OK;
+}
+
+}  // namespace ssbh

@@ -55,6 +55,8 @@ struct Workspace {
     DevBuf plan;       // hashing: m_j, O_j, tile offsets (3 * n_sub u64)
     DevBuf tiles;      // hashing: tile list
     DevBuf counters;   // hashing: tile count, claim counter
+    DevBuf fft_spec;   // FFT hash: seed spectrum (L complex doubles)
+    DevBuf fft_work;   // FFT hash: transforms of a chunk of sub-block pairs
     char last_schedule[48] = "";   // kernel and schedule of the last hash
     void release();
 };
@@ -77,6 +79,12 @@ struct MfmaSchedule {
     int ksplit = 0;  // K splits per tile (0 = fill the chip in whole rounds)
 };
 
+// FFT hash schedule: sub-block pairs transformed per chunk (0 = default).
+struct FftSchedule {
+    uint32_t chunk_pairs = 0;
+};
+constexpr uint64_t kMaxFftLength = 1ull << 18;   // transform length limit
+
 struct ServeState;   // serving scheduler (serve.hip)
 
 }  // namespace ssbh
@@ -96,6 +104,7 @@ struct ssbh_ctx {
     uint32_t forced_chunk_cols = 0;
     int forced_scalar_x = -1;      // -1 = library choice
     int forced_mfma[4] = {0, 0, 0, 0};
+    uint32_t forced_fft_chunk = 0;
 };
 
 namespace ssbh {
@@ -139,6 +148,9 @@ ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,
 ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
                              const HashRequest &q, const MfmaSchedule &s,
                              hipStream_t stream);
+ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
+                            const FftSchedule &s, hipStream_t stream);
+uint64_t fft_length(uint64_t seed_bits);
 
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
                         hipStream_t stream);

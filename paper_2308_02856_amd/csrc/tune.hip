@@ -15,8 +15,10 @@ namespace {
 struct Candidate {
     std::string name;
     bool mfma;
+    bool fft = false;
     ValuSchedule v;
     MfmaSchedule m;
+    FftSchedule f;
 };
 
 std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
@@ -43,6 +45,18 @@ std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
                  k.v.chunk_cols, k.v.tile_cols);
         k.name = b;
         c.push_back(k);
+    }
+    if (q.stride == 0 && fft_length(q.seed_bits) <= kMaxFftLength) {
+        for (uint32_t cp : {16u, 32u, 64u, 128u}) {
+            Candidate k;
+            k.mfma = false;
+            k.fft = true;
+            k.f.chunk_pairs = cp;
+            char b[64];
+            snprintf(b, sizeof b, "fft:%u", cp);
+            k.name = b;
+            c.push_back(k);
+        }
     }
     if (q.stride == 0) {
         // ksplit 0 = the launcher's whole-rounds choice.
@@ -110,9 +124,10 @@ ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,
         for (uint32_t k = 0; k <= reps && rc == SSBH_OK; ++k) {
             (void)hipEventRecord(e0, st);
             HashRequest r = q;
-            r.kernel = c.mfma ? SSBH_K_MFMA_I8 : SSBH_K_VALU;
-            rc = c.mfma ? launch_hash_mfma(ctx, ctx->ws, r, c.m, st)
-                        : launch_hash_valu(ctx, ctx->ws, r, c.v, st);
+            r.kernel = c.fft ? SSBH_K_FFT : c.mfma ? SSBH_K_MFMA_I8 : SSBH_K_VALU;
+            rc = c.fft ? launch_hash_fft(ctx, ctx->ws, r, c.f, st)
+                 : c.mfma ? launch_hash_mfma(ctx, ctx->ws, r, c.m, st)
+                          : launch_hash_valu(ctx, ctx->ws, r, c.v, st);
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;

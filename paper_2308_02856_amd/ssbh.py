@@ -22,14 +22,15 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ssbh.h")
 OK, PENDING = 0, 1
 E_INVAL, E_ABORT_OVERSIZE, E_NOMEM, E_DEVICE, E_UNKNOWN_JOB, E_UNSUPPORTED = (
     -1, -2, -3, -4, -5, -6)
+E_PRECISION = -7
 SAMPLE_IID, SAMPLE_PERMUTE, SAMPLE_EXPLICIT = 0, 1, 2
 OUT_FIXED, OUT_RATIO, OUT_EXPLICIT = 0, 1, 2
-K_AUTO, K_VALU, K_MFMA_I8 = 0, 1, 2
+K_AUTO, K_VALU, K_MFMA_I8, K_FFT = 0, 1, 2, 3
 
 _STATUS_NAMES = {OK: "OK", PENDING: "PENDING", E_INVAL: "E_INVAL",
                  E_ABORT_OVERSIZE: "E_ABORT_OVERSIZE", E_NOMEM: "E_NOMEM",
                  E_DEVICE: "E_DEVICE", E_UNKNOWN_JOB: "E_UNKNOWN_JOB",
-                 E_UNSUPPORTED: "E_UNSUPPORTED"}
+                 E_UNSUPPORTED: "E_UNSUPPORTED", E_PRECISION: "E_PRECISION"}
 
 _lib = None
 _vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
@@ -134,6 +135,8 @@ def lib() -> ctypes.CDLL:
     L.ssbh_set_mfma_schedule.restype = _i32
     L.ssbh_set_mfma_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
+    L.ssbh_set_fft_schedule.restype = _i32
+    L.ssbh_set_fft_schedule.argtypes = [_vp, _u32]
     L.ssbh_set_column_path.restype = _i32
     L.ssbh_set_column_path.argtypes = [_vp, ctypes.c_int]
     L.ssbh_job_out_words.restype = _u64
@@ -388,6 +391,10 @@ class Context:
         """Force the matrix-core schedule (0s = library choice)."""
         _check(lib().ssbh_set_mfma_schedule(self._h, int(mt), int(nt), int(wm),
                                             int(ksplit)))
+
+    def set_fft_schedule(self, chunk_pairs: int = 0):
+        """Force the FFT hash's chunk of sub-block pairs (0 = library)."""
+        _check(lib().ssbh_set_fft_schedule(self._h, int(chunk_pairs)))
 
     def set_column_path(self, scalar_x: int = -1):
         """Column words via LDS (0), scalar loads (1) or library choice (-1)."""

@@ -1,0 +1,203 @@
+"""GPU parity of the FFT hash (shared seed): the middle product by
+double-precision FFTs, rounded and parity-taken, must equal the oracle bit
+for bit (tolerance 0), and equal the VALU and matrix-core kernels."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import first_diff, to_dev, to_dev_u32, to_host
+from workloads import bernoulli_bits, config, permutation, uniform_bits
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2308_02856_amd import ssbh
+    c = ssbh.Context(0)
+    yield c
+    c.close()
+
+
+def fft_hash(ctx, sub, ln, wo, ns, seed, seed_bits, cap, chunk=0, **kw):
+    import torch
+    from paper_2308_02856_amd import ssbh
+    ctx.set_fft_schedule(chunk)
+    try:
+        out, tot, st = ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed,
+                                      seed_bits, cap, kernel=ssbh.K_FFT, **kw)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_fft_schedule(0)
+    assert int(st.item()) == 0, ssbh.status_name(int(st.item()))
+    return to_host(out), int(tot.item())
+
+
+@pytest.mark.parametrize("n,ns,m", [(4096, 8, 2048), (1000, 7, 999),
+                                    (3000, 1, 777), (65, 3, 64),
+                                    (10000, 33, 4096), (200, 5, 900)])
+def test_equal_blocks_match_oracle(ctx, orc, n, ns, m):
+    from paper_2308_02856_amd import ssbh
+    N = n * ns
+    a = uniform_bits(N, n + ns + 1)
+    perm = permutation(N, m + 1)
+    sub, ln, wo, st = ctx.sample(to_dev(a), N, ns, ssbh.SAMPLE_PERMUTE,
+                                 assign=to_dev_u32(perm))
+    seed_bits = n + m - 1 + 5
+    seed = uniform_bits(seed_bits, 17 + m)
+    got, tot = fft_hash(ctx, sub, ln, wo, ns, to_dev(seed), seed_bits, m,
+                        out_rule=ssbh.OUT_FIXED, out_a=m)
+    osub, oln, owo, _ = orc.sample(a, N, ns, orc.SAMPLE_PERMUTE, assign=perm)
+    want, wtot = orc.hash_batch(osub, oln, owo, np.full(ns, m, np.uint64),
+                                seed, seed_bits, 0, m)
+    assert tot == wtot
+    assert np.array_equal(got[: want.size], want), first_diff(got[: want.size], want)
+
+
+@pytest.mark.parametrize("N,ns,chunk", [((1 << 20) + 999, 300, 0),
+                                        ((1 << 20) + 999, 300, 7),
+                                        (200000, 9, 1), (1 << 17, 1, 0),
+                                        (5000, 64, 3)])
+def test_uneven_blocks_match_oracle_valu_and_mfma(ctx, orc, N, ns, chunk):
+    import torch
+    from paper_2308_02856_amd import ssbh
+    a = bernoulli_bits(N, 0.3, N % 1009)
+    key = 0x3141 + ns
+    sub, ln, wo, st = ctx.sample(to_dev(a), N, ns, ssbh.SAMPLE_IID, key=key)
+    osub, oln, owo, _ = orc.sample(a, N, ns, orc.SAMPLE_IID, key=key)
+    om = orc.out_lengths(oln, orc.OUT_RATIO, 2, 5)
+    cap = int(om.max()) + 11
+    seed_bits = int(oln.max()) + cap - 1 + 3
+    seed = uniform_bits(seed_bits, 77)
+    kw = dict(out_rule=ssbh.OUT_RATIO, out_a=2, out_b=5)
+    got, tot = fft_hash(ctx, sub, ln, wo, ns, to_dev(seed), seed_bits, cap,
+                        chunk=chunk, **kw)
+    want, wtot = orc.hash_batch(osub, oln, owo, om, seed, seed_bits, 0, cap)
+    assert tot == wtot
+    assert np.array_equal(got[: want.size], want), first_diff(got[: want.size], want)
+    for kern in (ssbh.K_VALU, ssbh.K_MFMA_I8):
+        out, _, st2 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns,
+                                     to_dev(seed), seed_bits, cap,
+                                     kernel=kern, **kw)
+        torch.cuda.synchronize()
+        assert int(st2.item()) == 0
+        assert np.array_equal(to_host(out), got), kern
+
+
+def test_empty_and_degenerate_sub_blocks(ctx, orc):
+    """Empty sub-blocks, m_j = 0 and m_j > n_j, from explicit lengths."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    lens = np.array([0, 5, 64, 0, 1000, 3, 700], dtype=np.uint64)
+    outl = np.array([4, 0, 100, 0, 333, 9, 1], dtype=np.uint64)
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = uniform_bits(int(words.sum()) * 64, 5)
+    for j in range(len(lens)):          # clear the bits past n_j
+        r = int(lens[j]) % 64
+        if r and words[j]:
+            sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
+    cap = int(outl.max())
+    seed_bits = int(lens.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 6)
+    ns = len(lens)
+    dl = torch.from_numpy(outl.view(np.int64)).cuda()
+    got, tot = fft_hash(ctx, to_dev(sub), to_dev(lens), to_dev(wo), ns,
+                        to_dev(seed), seed_bits, cap,
+                        out_rule=ssbh.OUT_EXPLICIT, out_len=dl)
+    want, wtot = orc.hash_batch(sub, lens, wo, outl, seed, seed_bits, 0, cap)
+    assert tot == wtot
+    assert np.array_equal(got[: want.size], want)
+
+
+def test_rejects_independent_seeds_and_long_seeds(ctx):
+    from paper_2308_02856_amd import ssbh
+    n, ns = 4096, 4
+    sub = to_dev(uniform_bits(n, 1))
+    import torch
+    ln = torch.full((ns,), n // ns, dtype=torch.int64, device="cuda")
+    wo = torch.arange(ns, dtype=torch.int64, device="cuda") * (n // ns // 64)
+    seed = to_dev(uniform_bits(1 << 20, 2))
+    with pytest.raises(ssbh.SsbhError) as e:
+        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, 1 << 20, 100,
+                       out_rule=ssbh.OUT_FIXED, out_a=100, seed_stride=2000,
+                       kernel=ssbh.K_FFT)
+    assert e.value.status == ssbh.E_INVAL
+    with pytest.raises(ssbh.SsbhError) as e:
+        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, (1 << 18) + 1, 100,
+                       out_rule=ssbh.OUT_FIXED, out_a=100, kernel=ssbh.K_FFT)
+    assert e.value.status == ssbh.E_UNSUPPORTED
+
+
+def test_batched_workload_fft_equals_mfma(ctx, orc):
+    """Full batched workload (2^28 bits, 2048 sub-blocks): FFT == int8
+    matrix cores bit for bit, plus sampled rows against the oracle."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    c = config("batched")
+    n, ns = c["n_bits"], c["n_sub"]
+    a = bernoulli_bits(n, c["p"], c["input_seed"])
+    sub, ln, wo, st = ctx.sample(to_dev(a), n, ns, ssbh.SAMPLE_IID,
+                                 key=c["sample_key"])
+    torch.cuda.synchronize()
+    lens = to_host(ln)[:ns].astype(np.int64)
+    mlen = lens * 2 // 5
+    cap = int(mlen.max())
+    seed_bits = int(lens.max()) + cap - 1
+    seed_h = uniform_bits(seed_bits, c["seed_seed"])
+    seed = to_dev(seed_h)
+    kw = dict(out_rule=ssbh.OUT_RATIO, out_a=2, out_b=5)
+    got, tot = fft_hash(ctx, sub, ln, wo, ns, seed, seed_bits, cap, **kw)
+    out, tot2, st2 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed,
+                                    seed_bits, cap, kernel=ssbh.K_MFMA_I8, **kw)
+    torch.cuda.synchronize()
+    assert int(st2.item()) == 0 and tot == int(tot2.item())
+    assert np.array_equal(got, to_host(out))
+    # Sampled rows against the oracle (row windows, one row at a time).
+    osub, oln, owo, _ = orc.sample(a, n, ns, orc.SAMPLE_IID,
+                                   key=c["sample_key"])
+    ooff = np.concatenate([[0], np.cumsum(mlen)[:-1]])
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        j = int(rng.integers(0, ns))
+        r = int(rng.integers(0, int(mlen[j])))
+        want = orc.toeplitz_rowwin(osub[int(owo[j]):], int(oln[j]), seed_h,
+                                   seed_bits, 0, cap, r)
+        k = int(ooff[j]) + r
+        assert ((int(got[k >> 6]) >> (k & 63)) & 1) == want, (j, r)
+
+
+def test_fft_graph_pipeline_replays(ctx, orc):
+    import torch
+    from paper_2308_02856_amd import ssbh
+    n, ns = (1 << 19) + 3, 40
+    a = bernoulli_bits(n, 0.5, 91)
+    key = 0x99
+    osub, oln, owo, _ = orc.sample(a, n, ns, orc.SAMPLE_IID, key=key)
+    om = orc.out_lengths(oln, orc.OUT_RATIO, 1, 3)
+    cap = int(om.max())
+    seed_bits = int(oln.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 92)
+    want, wtot = orc.hash_batch(osub, oln, owo, om, seed, seed_bits, 0, cap)
+    sub_cap = (n + 63) // 64 + ns
+    sub = torch.empty(sub_cap, dtype=torch.int64, device="cuda")
+    ln = torch.empty(ns, dtype=torch.int64, device="cuda")
+    wo = torch.empty(ns, dtype=torch.int64, device="cuda")
+    out = torch.empty((wtot + 63) // 64, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pipe = ctx.pipeline(d_in=to_dev(a), n_bits=n, n_sub=ns,
+                        mode=ssbh.SAMPLE_IID, sample_key=key, d_sub=sub,
+                        sub_capacity_words=sub_cap, d_len=ln, d_word_off=wo,
+                        out_rule=ssbh.OUT_RATIO, out_a=1, out_b=3,
+                        d_seed=to_dev(seed), seed_bits=seed_bits, m_cap=cap,
+                        kernel=ssbh.K_FFT, d_out=out, out_capacity_bits=wtot,
+                        d_out_total_bits=tot, d_status=st)
+    for _ in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        pipe.launch()
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0 and int(tot.item()) == wtot
+        assert np.array_equal(to_host(out)[: want.size], want)
+    pipe.close()
