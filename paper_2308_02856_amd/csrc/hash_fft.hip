@@ -48,7 +48,7 @@ namespace {
 
 constexpr int kN1 = 64;        // column FFT length (and columns per tile)
 constexpr int kTW = 4096;      // size of the w_4096 twiddle table
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 
 struct FftArgs {
     const uint64_t *sub;
