@@ -36,9 +36,11 @@ CLOCK_GHZ = 2.4          # MI355X peak engine clock
 LANES_PER_CU_CLK = 128   # 32-bit VALU lanes retired per CU per clock
 BITOPS_PER_LANE_OP = 32  # v_bitop3_b32: 32 AND-XOR bit-products per lane
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak (TOP/s)
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E peak (GB/s)
 
 KERNEL_SOURCES = {"k_toeplitz_valu": "hash_valu.hip",
-                  "k_toeplitz_mfma": "hash_mfma.hip"}
+                  "k_toeplitz_mfma": "hash_mfma.hip",
+                  "k_fft_rows": "hash_fft.hip"}
 
 
 def log(msg: str) -> None:
@@ -89,6 +91,19 @@ def load_traffic(kernel: str, workload: str, schedule: str):
         return None
 
 
+def fft_length(seed_bits: int) -> int:
+    """Transform length of the FFT hash: the least power of two, at least
+    4096, that holds the seed."""
+    L = 4096
+    while L < seed_bits:
+        L *= 2
+    return L
+
+
+def kernel_avgs(rep: dict) -> dict:
+    return {k: round(ms * 1e3 / n, 2) for k, (n, ms) in rep.items()}
+
+
 def time_events(fn, reps: int) -> list[float]:
     """Milliseconds of each call of fn, from HIP events on the current stream."""
     import torch
@@ -130,6 +145,8 @@ def run_batched(ctx, ssbh, args):
     kernel = {"auto": ssbh.K_AUTO, "valu": ssbh.K_VALU,
               "mfma": ssbh.K_MFMA_I8, "fft": ssbh.K_FFT}[args.kernel]
     tune_report = ""
+    if args.fft_chunk:
+        ctx.set_fft_schedule(args.fft_chunk)
     if kernel == ssbh.K_AUTO and not args.no_tune:
         log("batched: autotuning the hash kernel (untimed)")
         tune_report = ctx.tune(sub, sub_cap, ln, wo, ns, seed, seed_bits, cap,
@@ -165,6 +182,17 @@ def run_batched(ctx, ssbh, args):
     hash_ms = time_events(hash_, max(3, args.steps))
     schedule = ctx.last_schedule()
     samp_ms = time_events(sample, max(3, args.steps))
+    # Per-kernel durations: HIP events recorded by the library around each
+    # launch, on the launch stream.
+    ctx.set_timing(True)
+    reps = max(3, args.steps)
+    for _ in range(reps):
+        hash_()
+    hash_kernels = ctx.timing_report()
+    for _ in range(reps):
+        sample()
+    sample_kernels = ctx.timing_report()
+    ctx.set_timing(False)
     # Sampling with sifting flags (Sec. III.B step 2): 96 % of rounds kept.
     keep = to_dev(bernoulli_bits(n, 0.96, c["input_seed"] + 1000))
     sub2 = torch.empty_like(sub)
@@ -187,6 +215,9 @@ def run_batched(ctx, ssbh, args):
                hash_ms=float(np.mean(hash_ms)), sample_ms=float(np.mean(samp_ms)),
                a=a, out=out, sub=sub, wo=wo, seed=seed, key=key, c=c,
                schedule=schedule, tune_report=tune_report, l_ub=l_ub,
+               hash_kernels=hash_kernels, sample_kernels=sample_kernels,
+               timed_calls=reps,
+               pairs=(ns + 1) // 2, fft_len=fft_length(seed_bits),
                sift_ms=float(np.mean(sift_ms)), l_ub_sifted=l_ub2)
     return res
 
@@ -242,6 +273,7 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     out = torch.empty(ns * m // 64, dtype=torch.int64, device="cuda")
     outv = torch.empty_like(out)
+    outf = torch.empty_like(out)
     tot = torch.zeros(1, dtype=torch.int64, device="cuda")
 
     def sample():
@@ -257,14 +289,17 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     sample()
     hash_(ssbh.K_MFMA_I8, out)
     hash_(ssbh.K_VALU, outv)
+    hash_(ssbh.K_FFT, outf)
     torch.cuda.synchronize()
     same = bool(torch.equal(out, outv)) and int(st.item()) == 0
+    same_fft = bool(torch.equal(out, outf))
     g_ms = float(np.mean(time_events(sample, 3)))
     mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
     mfma_sched = ctx.last_schedule()
     va_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
+    ff_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_FFT, outf), 3)))
     prods = L * m * ns
-    del d_in, perm, sub, out, outv
+    del d_in, perm, sub, out, outv, outf
     torch.cuda.empty_cache()
     return {
         "workload": "contraction", "n_bits": n, "n_sub": ns, "sub_bits": L,
@@ -276,7 +311,11 @@ def run_contraction(ctx, ssbh, args, peak_alu):
         "mfma_int8_tops": round(2 * prods / (mf_ms * 1e-3) / 1e12, 1),
         "mfma_frac": round(2 * prods / (mf_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
         "valu_frac": round(prods / (va_ms * 1e-3) / 1e12 / peak_alu, 4),
+        "fft_ms": round(ff_ms, 3),
+        "gbps_step_fft": round(n / ((g_ms + ff_ms) * 1e-3) / 1e9, 3),
+        "gbps_hash_fft": round(n / (ff_ms * 1e-3) / 1e9, 3),
         "mfma_equals_valu": same,
+        "fft_equals_mfma": same_fft,
         "mfma_traffic": load_traffic("k_toeplitz_mfma", "contraction",
                                      mfma_sched),
     }
@@ -523,6 +562,8 @@ def main() -> int:
                     choices=["auto", "valu", "mfma", "fft"],
                     help="hash kernel of the batched step (auto = tuned)")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--fft-chunk", type=int, default=0,
+                    help="force the FFT hash's pairs per chunk (0 = tuned)")
     ap.add_argument("--cpu-subblocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
@@ -577,25 +618,51 @@ def main() -> int:
     if args.mode == "hash-batched":
         print(json.dumps({"mode": args.mode, "hash_ms": res["hash_ms"],
                           "sample_ms": res["sample_ms"],
-                          "schedule": res["schedule"]}), flush=True)
+                          "schedule": res["schedule"],
+                          "kernel_avg_us": {**kernel_avgs(res["sample_kernels"]),
+                                            **kernel_avgs(res["hash_kernels"])}}),
+              flush=True)
         return 0
     single = None if args.skip_single else run_single(ctx, ssbh, args)
 
-    if res["schedule"].startswith("mfma"):
+    hk = res["hash_kernels"]
+    if res["schedule"].startswith("fft"):
+        # Dominant kernel: the row pass.  Per launch it reads and writes the
+        # transforms of its chunk of sub-block pairs (L complex doubles per
+        # pair each way) and reads the seed spectrum once.
+        kern = "k_fft_rows"
+        n_l, ms = hk[kern]
+        L = res["fft_len"]
+        per_pair = 2 * L * 16
+        total_bytes = (res["timed_calls"] * res["pairs"] * per_pair +
+                       n_l * L * 16)
+        achieved = total_bytes / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": kern, "schedule": res["schedule"],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(kern, "batched", res["schedule"]),
+                "avg_launch_us": round(ms * 1e3 / n_l, 2),
+                "algorithmic_bytes_per_launch": int(total_bytes / n_l)}
+        dtype = "f64"
+    elif res["schedule"].startswith("mfma"):
         kern = "k_toeplitz_mfma"
-        achieved = 2 * res["work"] / (res["hash_ms"] * 1e-3) / 1e12
+        n_l, ms = hk[kern]
+        achieved = 2 * res["work"] / (ms / n_l * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": kern, "schedule": res["schedule"],
                 "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
                 "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
-                "traffic": load_traffic(kern, "batched", res["schedule"])}
+                "traffic": load_traffic(kern, "batched", res["schedule"]),
+                "avg_launch_us": round(ms * 1e3 / n_l, 2)}
         dtype = "i8"
     else:
         kern = "k_toeplitz_valu"
-        achieved = res["work"] / (res["hash_ms"] * 1e-3) / 1e12
+        n_l, ms = hk[kern]
+        achieved = res["work"] / (ms / n_l * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": kern, "schedule": res["schedule"],
                 "achieved": round(achieved, 2), "peak": round(peak, 2),
                 "unit": "Tbit-op/s", "frac": round(achieved / peak, 4),
-                "traffic": load_traffic(kern, "batched", res["schedule"])}
+                "traffic": load_traffic(kern, "batched", res["schedule"]),
+                "avg_launch_us": round(ms * 1e3 / n_l, 2)}
         dtype = "u32"
     line = {
         "metric": METRIC,
@@ -623,6 +690,8 @@ def main() -> int:
         "sifted_sample_ms": round(res["sift_ms"], 4),
         "bit_products_per_s": float(f"{res['work'] / (res['hash_ms'] * 1e-3):.4g}"),
         "roofline": roof,
+        "kernel_avg_us": {**kernel_avgs(res["sample_kernels"]),
+                          **kernel_avgs(res["hash_kernels"])},
         "tuning": res["tune_report"].strip().splitlines(),
     }
     if single is not None:

@@ -373,6 +373,18 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
 ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm,
                                    int ksplit);
 
+/* Per-kernel timing: with on = 1, the synchronous entry points of this
+ * context record a HIP event before and after each launch of their main
+ * kernels (k_hist, k_scatter, k_perm_gather, k_toeplitz_valu,
+ * k_toeplitz_mfma, k_fft_spectrum, k_fft_cols, k_fft_rows, k_fft_out) on the
+ * launch stream; on = 0 stops it and frees the events.  Graph pipelines and
+ * serving jobs are never timed. */
+ssbh_status ssbh_set_timing(ssbh_ctx *ctx, int on);
+
+/* Wait for the recorded launches and write one line per kernel,
+ * "name launches total_ms", then forget them (truncated to len). */
+ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len);
+
 /* Force the FFT hash's chunk: sub-block pairs transformed per pass (each
  * pair holds 2^18 complex doubles of scratch at the largest length; 0 =
  * library choice).  The output bits do not depend on it. */

@@ -76,6 +76,60 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+int KernelTimer::begin(const char *name, hipStream_t stream) {
+    auto take = [&]() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) { e = pool.back(); pool.pop_back(); }
+        else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+        return e;
+    };
+    Rec r{name, take(), take()};
+    if (r.start) (void)hipEventRecord(r.start, stream);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+}
+
+void KernelTimer::end(int idx, hipStream_t stream) {
+    if (idx >= 0 && recs[idx].stop) (void)hipEventRecord(recs[idx].stop, stream);
+}
+
+std::string KernelTimer::report() {
+    std::vector<std::pair<std::string, std::pair<long, double>>> agg;
+    for (Rec &r : recs) {
+        float ms = 0.f;
+        if (r.start && r.stop && hipEventSynchronize(r.stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            bool found = false;
+            for (auto &a : agg)
+                if (a.first == r.name) {
+                    a.second.first += 1;
+                    a.second.second += ms;
+                    found = true;
+                }
+            if (!found) agg.push_back({r.name, {1, (double)ms}});
+        }
+        if (r.start) pool.push_back(r.start);
+        if (r.stop) pool.push_back(r.stop);
+    }
+    recs.clear();
+    std::string out;
+    char line[160];
+    for (auto &a : agg) {
+        snprintf(line, sizeof line, "%s %ld %.6f\n", a.first.c_str(),
+                 a.second.first, a.second.second);
+        out += line;
+    }
+    return out;
+}
+
+KernelTimer::~KernelTimer() {
+    for (Rec &r : recs) {
+        if (r.start) (void)hipEventDestroy(r.start);
+        if (r.stop) (void)hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
 void Workspace::release() {
     counts.release();
     offs.release();
@@ -85,6 +139,8 @@ void Workspace::release() {
     counters.release();
     fft_spec.release();
     fft_work.release();
+    delete timer;
+    timer = nullptr;
 }
 
 // Default VALU schedule: 16 rows per lane, 4 wavefronts (4096 rows per
@@ -354,6 +410,31 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
     ctx->forced_valu_waves = waves;
     ctx->forced_tile_cols = tile_cols;
     ctx->forced_chunk_cols = chunk_cols;
+    return SSBH_OK;
+}
+
+ssbh_status ssbh_set_timing(ssbh_ctx *ctx, int on) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    if (on && !ctx->ws.timer) ctx->ws.timer = new KernelTimer();
+    if (!on && ctx->ws.timer) {
+        (void)hipDeviceSynchronize();
+        delete ctx->ws.timer;
+        ctx->ws.timer = nullptr;
+    }
+    return SSBH_OK;
+}
+
+ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len) {
+    clear_error();
+    if (!ctx || !buf || !len) SSBH_INVAL("ctx and buf must be non-null");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    const std::string t = ctx->ws.timer ? ctx->ws.timer->report() : std::string();
+    strncpy(buf, t.c_str(), len - 1);
+    buf[len - 1] = 0;
     return SSBH_OK;
 }
 

@@ -534,17 +534,29 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     const uint32_t tiles = a.n2 / kN1;
     // Seed spectrum.
     a.pair0 = 0;
-    hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
-                       stream, a);
-    rows(a, 1, true, stream);
+    {
+        TimedLaunch timed(ws.timer, "k_fft_spectrum", stream);
+        hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
+                           stream, a);
+        rows(a, 1, true, stream);
+    }
     for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
         const uint32_t np = (uint32_t)std::min<uint64_t>(cp, pairs - p0);
         a.pair0 = (uint32_t)p0;
-        hipLaunchKernelGGL(k_fft_cols<false>, dim3(tiles, np), dim3(kThreads),
-                           0, stream, a);
-        rows(a, np, false, stream);
-        hipLaunchKernelGGL(k_fft_out, dim3(tiles, np), dim3(kThreads), 0,
-                           stream, a);
+        {
+            TimedLaunch timed(ws.timer, "k_fft_cols", stream);
+            hipLaunchKernelGGL(k_fft_cols<false>, dim3(tiles, np),
+                               dim3(kThreads), 0, stream, a);
+        }
+        {
+            TimedLaunch timed(ws.timer, "k_fft_rows", stream);
+            rows(a, np, false, stream);
+        }
+        {
+            TimedLaunch timed(ws.timer, "k_fft_out", stream);
+            hipLaunchKernelGGL(k_fft_out, dim3(tiles, np), dim3(kThreads), 0,
+                               stream, a);
+        }
     }
     SSBH_CHECK_HIP(hipGetLastError());
     return SSBH_OK;

@@ -383,6 +383,7 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
     // Mean sub-block length from the buffer capacity: the split count only
     // needs an estimate of the K chunks per tile.
     const uint64_t ncap = 64ull * q.sub_cap / q.n_sub + 64;
+    TimedLaunch timed(ws.timer, "k_toeplitz_mfma", stream);
 #define SSBH_MFMA_CASE(A, B, C, O)                                            \
     if (s.mt == A && s.nt == B && s.wm == C)                                  \
         return run_mfma<A, B, C, O>(ctx, ma, (uint32_t)s.ksplit, ncap, stream);

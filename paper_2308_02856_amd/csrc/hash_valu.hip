@@ -536,6 +536,7 @@ ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,
     uint32_t chunk = s.chunk_cols ? s.chunk_cols : 4096;
     chunk = (chunk + s.r - 1) / s.r * s.r;
     va.chunk = chunk;
+    TimedLaunch timed(ws.timer, "k_toeplitz_valu", stream);
 #define SSBH_VALU_CASE(RR, WW)                                                \
     if (s.r == RR && s.waves == WW)                                           \
         return s.scalar_x ? run_valu<RR, WW, true>(ctx, va, stream)           \

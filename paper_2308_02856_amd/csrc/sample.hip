@@ -493,6 +493,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
         const uint64_t total = (uint64_t)ns * wl;
         if (total) {
             const uint64_t waves = std::min<uint64_t>(total, (uint64_t)ctx->num_cus * 32);
+            TimedLaunch timed(ws.timer, "k_perm_gather", stream);
             hipLaunchKernelGGL(k_perm_gather, dim3((uint32_t)((waves + 3) / 4)),
                                dim3(256), 0, stream, d_in, n, d_assign, ns, L,
                                wl, d_sub, d_status);
@@ -554,12 +555,15 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
             return st;
         }
     }
-    if (ex)
-        hipLaunchKernelGGL(k_hist<true>, dim3(hist_blocks), dim3(64 * wpb),
-                           hist_lds, stream, a);
-    else
-        hipLaunchKernelGGL(k_hist<false>, dim3(hist_blocks), dim3(64 * wpb),
-                           hist_lds, stream, a);
+    {
+        TimedLaunch timed(ws.timer, "k_hist", stream);
+        if (ex)
+            hipLaunchKernelGGL(k_hist<true>, dim3(hist_blocks), dim3(64 * wpb),
+                               hist_lds, stream, a);
+        else
+            hipLaunchKernelGGL(k_hist<false>, dim3(hist_blocks), dim3(64 * wpb),
+                               hist_lds, stream, a);
+    }
     const uint32_t jb = (ns + 63) / 64;
     if (a.nseg) {
         hipLaunchKernelGGL(k_scan_part, dim3(jb, a.nchunk), dim3(64), 0,
@@ -572,6 +576,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     }
     hipLaunchKernelGGL(k_scan_words, dim3(1), dim3(1024), 0, stream, a);
     if (a.nseg) {
+        TimedLaunch timed(ws.timer, "k_scatter", stream);
         if (use_tab && ex)
             hipLaunchKernelGGL(k_scatter_tab<true>, dim3(a.nseg), dim3(64),
                                tab_lds, stream, a);

@@ -48,6 +48,27 @@ struct DevBuf {
 };
 
 // Scratch used by one sample / hash pipeline.
+// Optional per-kernel timing with HIP events on the launch stream (off by
+// default; never used on a captured stream).
+struct KernelTimer {
+    struct Rec { const char *name; hipEvent_t start, stop; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    int begin(const char *name, hipStream_t stream);
+    void end(int idx, hipStream_t stream);
+    std::string report();          // waits, aggregates, clears
+    ~KernelTimer();
+};
+
+struct TimedLaunch {
+    KernelTimer *t;
+    hipStream_t s;
+    int idx;
+    TimedLaunch(KernelTimer *timer, const char *name, hipStream_t stream)
+        : t(timer), s(stream), idx(timer ? timer->begin(name, stream) : -1) {}
+    ~TimedLaunch() { if (t) t->end(idx, s); }
+};
+
 struct Workspace {
     DevBuf counts;     // sampling: per-segment bucket counts  [segs][n_sub]
     DevBuf offs;       // sampling: per-segment bucket offsets [segs][n_sub]
@@ -58,6 +79,7 @@ struct Workspace {
     DevBuf fft_spec;   // FFT hash: seed spectrum (L complex doubles)
     DevBuf fft_work;   // FFT hash: transforms of a chunk of sub-block pairs
     char last_schedule[48] = "";   // kernel and schedule of the last hash
+    KernelTimer *timer = nullptr;  // per-kernel event timing (optional)
     void release();
 };
 

@@ -135,6 +135,10 @@ def lib() -> ctypes.CDLL:
     L.ssbh_set_mfma_schedule.restype = _i32
     L.ssbh_set_mfma_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
+    L.ssbh_set_timing.restype = _i32
+    L.ssbh_set_timing.argtypes = [_vp, ctypes.c_int]
+    L.ssbh_timing_report.restype = _i32
+    L.ssbh_timing_report.argtypes = [_vp, ctypes.c_char_p, _u64]
     L.ssbh_set_fft_schedule.restype = _i32
     L.ssbh_set_fft_schedule.argtypes = [_vp, _u32]
     L.ssbh_set_column_path.restype = _i32
@@ -391,6 +395,20 @@ class Context:
         """Force the matrix-core schedule (0s = library choice)."""
         _check(lib().ssbh_set_mfma_schedule(self._h, int(mt), int(nt), int(wm),
                                             int(ksplit)))
+
+    def set_timing(self, on: bool = True):
+        """Record HIP events around the main kernels of synchronous calls."""
+        _check(lib().ssbh_set_timing(self._h, 1 if on else 0))
+
+    def timing_report(self) -> dict:
+        """{kernel: (launches, total_ms)} since the last report."""
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().ssbh_timing_report(self._h, buf, 4096))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms = line.split()
+            out[name] = (int(cnt), float(ms))
+        return out
 
     def set_fft_schedule(self, chunk_pairs: int = 0):
         """Force the FFT hash's chunk of sub-block pairs (0 = library)."""
