@@ -385,6 +385,12 @@ ssbh_status ssbh_set_timing(ssbh_ctx *ctx, int on);
  * "name launches total_ms", then forget them (truncated to len). */
 ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len);
 
+/* Scatter kernel of the i.i.d. / explicit sampling: path 0 = library
+ * choice (a workgroup of four wavefronts per segment when its LDS tables fit
+ * in 64 KiB), 1 = one wavefront per segment.  The sub-blocks do not depend
+ * on it. */
+ssbh_status ssbh_set_sample_path(ssbh_ctx *ctx, int path);
+
 /* Force the FFT hash's chunk: sub-block pairs transformed per pass (each
  * pair holds 2^18 complex doubles of scratch at the largest length; 0 =
  * library choice).  The output bits do not depend on it. */

@@ -438,6 +438,15 @@ ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len) {
     return SSBH_OK;
 }
 
+ssbh_status ssbh_set_sample_path(ssbh_ctx *ctx, int path) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (path < 0 || path > 1) SSBH_INVAL("path must be 0 or 1");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->forced_scatter = path;
+    return SSBH_OK;
+}
+
 ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs) {
     clear_error();
     if (!ctx) SSBH_INVAL("ctx is null");

@@ -375,6 +375,174 @@ __global__ __launch_bounds__(64) void k_scatter_tab(SampleArgs a) {
     flush_runs(a, seg, cursor, stage, lane);
 }
 
+// V for the 128 rounds base .. base+127 (base even): lane l evaluates the
+// generator once, for the round pair base/2 + l, and the two halves are
+// handed to the lanes that own those rounds (vA: round base + l, vB: round
+// base + 64 + l).
+template <bool EXPLICIT>
+__device__ __forceinline__ void sample_v2(const SampleArgs &a, uint64_t base,
+                                          int lane, uint32_t &vA, uint32_t &vB) {
+    if constexpr (EXPLICIT) {
+        const uint64_t iA = base + lane, iB = base + 64 + lane;
+        vA = iA < a.n ? a.assign[iA] : 0u;
+        vB = iB < a.n ? a.assign[iB] : 0u;
+    } else {
+        const uint64_t r = splitmix64_at(a.key, (base >> 1) + (uint64_t)lane);
+        const int lo = (int)(uint32_t)r, hi = (int)(uint32_t)(r >> 32);
+        const int sa = lane >> 1, sb = 32 + (lane >> 1);
+        const uint32_t loA = (uint32_t)__shfl(lo, sa, 64), hiA = (uint32_t)__shfl(hi, sa, 64);
+        const uint32_t loB = (uint32_t)__shfl(lo, sb, 64), hiB = (uint32_t)__shfl(hi, sb, 64);
+        vA = __umulhi((lane & 1) ? hiA : loA, a.ns);
+        vB = __umulhi((lane & 1) ? hiB : loB, a.ns);
+    }
+}
+
+// Copy every run of the segment image to its sub-block (as flush_runs, with
+// `nt` threads): ends[j] is the end of run j, run j starts at ends[j-1].
+__device__ __forceinline__ void flush_runs_t(const SampleArgs &a, uint32_t seg,
+                                             const uint32_t *ends,
+                                             const uint32_t *stage, int t,
+                                             int nt) {
+    const uint32_t *off = a.offs + (uint64_t)seg * a.ns;
+    for (uint32_t j = t; j < a.ns; j += nt) {
+        const uint32_t end = ends[j];
+        const uint32_t start = j ? ends[j - 1] : 0u;
+        const uint32_t c = end - start;
+        if (!c) continue;
+        const uint64_t dst = 64ull * a.woff[j] + off[j];
+        const uint64_t d0 = dst >> 6, d1 = (dst + c - 1) >> 6;
+        for (uint64_t d = d0; d <= d1; ++d) {
+            const uint64_t lo = max(dst, d * 64), hi = min(dst + c, d * 64 + 64);
+            const uint32_t nb = (uint32_t)(hi - lo);
+            uint64_t bits = stage_bits64(stage, start + (uint32_t)(lo - dst));
+            if (nb < 64) bits &= (1ull << nb) - 1ull;
+            bits <<= (lo - d * 64);
+            if (nb == 64) a.sub[d] = bits;
+            else if (bits) atomicOr((unsigned long long *)&a.sub[d],
+                                    (unsigned long long)bits);
+        }
+    }
+}
+
+// Scatter with one workgroup of 4 wavefronts per segment; wavefront w takes
+// the w-th quarter of the segment.
+//   1. every wavefront counts its quarter per sub-block (LDS atomics);
+//   2. a workgroup scan turns the counts into each wavefront's first
+//      position of every run in the LDS image of the segment (sorted by
+//      sub-block, stable: quarter w comes after quarters < w);
+//   3. every wavefront ranks equal V_i inside each 64-round step: a 256-slot
+//      match table (OR of lane bits at slot V mod 256, read back) narrowed by
+//      ballots on the bits of V above 8, then advances its cursors and ORs
+//      the bits into the image;
+//   4. all runs are copied out as in flush_runs.
+// LDS: 4 cursor tables (4 n_sub words), 4 match tables (8 KiB), the image.
+template <bool EXPLICIT>
+__global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
+    extern __shared__ __align__(8) uint32_t lds[];
+    __shared__ uint32_t wsum[4];
+    if (*a.status) return;
+    const uint32_t ns = a.ns;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t *cur = lds;                                            // [4][ns]
+    uint64_t *tab = reinterpret_cast<uint64_t *>(lds + ((4 * ns + 1) & ~1u));
+    uint32_t *stage = reinterpret_cast<uint32_t *>(tab + 4 * 256);
+    const uint32_t seg = blockIdx.x;
+    const uint32_t nsw = (uint32_t)(a.seg_bits / 32) + 4;
+    for (uint32_t k = t; k < 4 * ns; k += 256) cur[k] = 0u;
+    for (uint32_t k = t; k < 4 * 256; k += 256) tab[k] = 0ull;
+    for (uint32_t k = t; k < nsw; k += 256) stage[k] = 0u;
+    __syncthreads();
+
+    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
+    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
+    const uint64_t qlen = a.seg_bits / 4;               // multiple of 128
+    const uint64_t qa = i0 + (uint64_t)w * qlen;
+    const uint64_t qb = min(qa + qlen, i1);
+    uint32_t *mc = cur + (uint32_t)w * ns;
+
+    // 1. Counts of this wavefront's quarter.
+    for (uint64_t base = qa; base < qb; base += 128) {
+        uint32_t vA, vB;
+        sample_v2<EXPLICIT>(a, base, lane, vA, vB);
+        const uint64_t iA = base + lane, iB = iA + 64;
+        if (iA < qb && vA < ns && kept(a, iA)) atomicAdd(&mc[vA], 1u);
+        if (iB < qb && vB < ns && kept(a, iB)) atomicAdd(&mc[vB], 1u);
+    }
+    __syncthreads();
+
+    // 2. Run starts: exclusive scan over sub-blocks of the segment totals,
+    //    then each quarter's offset inside its run.
+    {
+        const uint32_t per = (ns + 255) / 256;
+        const uint32_t v0 = min((uint32_t)t * per, ns), v1 = min(v0 + per, ns);
+        uint32_t sum = 0;
+        for (uint32_t v = v0; v < v1; ++v)
+            sum += cur[v] + cur[ns + v] + cur[2 * ns + v] + cur[3 * ns + v];
+        uint32_t incl = sum;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t x = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += x;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int k = 0; k < w; ++k) run += wsum[k];
+        for (uint32_t v = v0; v < v1; ++v) {
+            const uint32_t c0 = cur[v], c1 = cur[ns + v], c2 = cur[2 * ns + v],
+                           c3 = cur[3 * ns + v];
+            cur[v] = run;
+            cur[ns + v] = run + c0;
+            cur[2 * ns + v] = run + c0 + c1;
+            cur[3 * ns + v] = run + c0 + c1 + c2;
+            run += c0 + c1 + c2 + c3;
+        }
+    }
+    __syncthreads();
+
+    // 3. Stable placement.
+    uint64_t *mt = tab + (uint32_t)w * 256;
+    const uint64_t me = 1ull << lane;
+    const uint64_t below = me - 1ull;
+    const uint32_t hb = a.vbits > 8 ? a.vbits - 8 : 0;
+    const uint64_t nw_in = (a.n + 63) / 64;
+    auto place = [&](uint32_t v, bool valid, bool bit) {
+        const uint32_t slot = v & 255u;
+        if (valid) atomicOr((unsigned long long *)&mt[slot], (unsigned long long)me);
+        __builtin_amdgcn_wave_barrier();
+        uint64_t m = valid ? mt[slot] : 0ull;
+        for (uint32_t b = 0; b < hb; ++b) {
+            const bool hbit = (v >> (8 + b)) & 1u;
+            const uint64_t bal = ballot64(valid && hbit);
+            m &= hbit ? bal : ~bal;
+        }
+        if (valid) {
+            const uint32_t base = mc[v];
+            const uint32_t pos = base + (uint32_t)__popcll(m & below);
+            if (63 - __clzll((long long)m) == lane) {
+                mc[v] = base + (uint32_t)__popcll(m);
+                mt[slot] = 0ull;
+            }
+            if (bit) atomicOr(&stage[pos >> 5], 1u << (pos & 31));
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    for (uint64_t base = qa; base < qb; base += 128) {
+        uint32_t vA, vB;
+        sample_v2<EXPLICIT>(a, base, lane, vA, vB);
+        const uint64_t wi = base >> 6;
+        const uint64_t wA = wi < nw_in ? a.in[wi] : 0ull;
+        const uint64_t wB = wi + 1 < nw_in ? a.in[wi + 1] : 0ull;
+        const uint64_t iA = base + lane, iB = iA + 64;
+        place(vA, iA < qb && vA < ns && kept(a, iA), (wA >> lane) & 1ull);
+        place(vB, iB < qb && vB < ns && kept(a, iB), (wB >> lane) & 1ull);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __syncthreads();
+
+    // 4. Runs out; the last quarter's cursors are the run ends.
+    flush_runs_t(a, seg, cur + 3 * ns, stage, t, 256);
+}
+
 // Permutation mode: B[k] = A[pi[k]], sub-block j = B[jL, (j+1)L).
 __global__ __launch_bounds__(256) void k_perm_gather(
         const uint64_t *in, uint64_t n, const uint32_t *perm, uint32_t ns,
@@ -433,7 +601,7 @@ static uint64_t segment_bits(uint32_t ns) {
     uint64_t seg = 32ull * ns;
     seg = std::max<uint64_t>(seg, 1ull << 14);
     seg = std::min<uint64_t>(seg, 1ull << 18);
-    return (seg + 63) / 64 * 64;
+    return (seg + 511) / 512 * 512;
 }
 
 ScratchSizes sample_scratch(uint64_t n, uint32_t ns, uint32_t mode) {
@@ -542,6 +710,9 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     const size_t scat_lds = (size_t)ns * 4 + ((size_t)(seg / 32) + 4) * 4;
     const size_t tab_lds = scat_lds + (size_t)ns * 8;
     const bool use_tab = tab_lds <= 48 * 1024;
+    const size_t wg_lds = (size_t)((4 * ns + 1) & ~1u) * 4 + 4 * 256 * 8 +
+                          ((size_t)(seg / 32) + 4) * 4;
+    const bool use_wg = ns >= 2 && wg_lds <= 64 * 1024 && ctx->forced_scatter != 1;
     {
         const void *kh = ex ? (const void *)k_hist<true> : (const void *)k_hist<false>;
         const void *ksc = ex ? (const void *)k_scatter<true>
@@ -549,7 +720,11 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
         if ((st = ensure_dynamic_lds(kh, hist_lds)) != SSBH_OK) return st;
         const void *kt = ex ? (const void *)k_scatter_tab<true>
                             : (const void *)k_scatter_tab<false>;
-        if (use_tab) {
+        const void *kw = ex ? (const void *)k_scatter_wg<true>
+                            : (const void *)k_scatter_wg<false>;
+        if (use_wg) {
+            if ((st = ensure_dynamic_lds(kw, wg_lds)) != SSBH_OK) return st;
+        } else if (use_tab) {
             if ((st = ensure_dynamic_lds(kt, tab_lds)) != SSBH_OK) return st;
         } else if ((st = ensure_dynamic_lds(ksc, scat_lds)) != SSBH_OK) {
             return st;
@@ -577,7 +752,13 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     hipLaunchKernelGGL(k_scan_words, dim3(1), dim3(1024), 0, stream, a);
     if (a.nseg) {
         TimedLaunch timed(ws.timer, "k_scatter", stream);
-        if (use_tab && ex)
+        if (use_wg && ex)
+            hipLaunchKernelGGL(k_scatter_wg<true>, dim3(a.nseg), dim3(256),
+                               wg_lds, stream, a);
+        else if (use_wg)
+            hipLaunchKernelGGL(k_scatter_wg<false>, dim3(a.nseg), dim3(256),
+                               wg_lds, stream, a);
+        else if (use_tab && ex)
             hipLaunchKernelGGL(k_scatter_tab<true>, dim3(a.nseg), dim3(64),
                                tab_lds, stream, a);
         else if (use_tab)

@@ -127,6 +127,7 @@ struct ssbh_ctx {
     int forced_scalar_x = -1;      // -1 = library choice
     int forced_mfma[4] = {0, 0, 0, 0};
     uint32_t forced_fft_chunk = 0;
+    int forced_scatter = 0;        // 0 = library choice, 1 = one wave per segment
 };
 
 namespace ssbh {

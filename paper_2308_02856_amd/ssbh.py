@@ -135,6 +135,8 @@ def lib() -> ctypes.CDLL:
     L.ssbh_set_mfma_schedule.restype = _i32
     L.ssbh_set_mfma_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
+    L.ssbh_set_sample_path.restype = _i32
+    L.ssbh_set_sample_path.argtypes = [_vp, ctypes.c_int]
     L.ssbh_set_timing.restype = _i32
     L.ssbh_set_timing.argtypes = [_vp, ctypes.c_int]
     L.ssbh_timing_report.restype = _i32
@@ -395,6 +397,10 @@ class Context:
         """Force the matrix-core schedule (0s = library choice)."""
         _check(lib().ssbh_set_mfma_schedule(self._h, int(mt), int(nt), int(wm),
                                             int(ksplit)))
+
+    def set_sample_path(self, path: int = 0):
+        """Scatter kernel of the sampling: 0 = library, 1 = one wave/segment."""
+        _check(lib().ssbh_set_sample_path(self._h, int(path)))
 
     def set_timing(self, on: bool = True):
         """Record HIP events around the main kernels of synchronous calls."""
