@@ -91,15 +91,6 @@ def load_traffic(kernel: str, workload: str, schedule: str):
         return None
 
 
-def fft_length(seed_bits: int) -> int:
-    """Transform length of the FFT hash: the least power of two, at least
-    4096, that holds the seed."""
-    L = 4096
-    while L < seed_bits:
-        L *= 2
-    return L
-
-
 def kernel_avgs(rep: dict) -> dict:
     return {k: round(ms * 1e3 / n, 2) for k, (n, ms) in rep.items()}
 
@@ -217,7 +208,7 @@ def run_batched(ctx, ssbh, args):
                schedule=schedule, tune_report=tune_report, l_ub=l_ub,
                hash_kernels=hash_kernels, sample_kernels=sample_kernels,
                timed_calls=reps,
-               pairs=(ns + 1) // 2, fft_len=fft_length(seed_bits),
+               pairs=(ns + 1) // 2,
                sift_ms=float(np.mean(sift_ms)), l_ub_sifted=l_ub2)
     return res
 
@@ -632,7 +623,7 @@ def main() -> int:
         # pair each way) and reads the seed spectrum once.
         kern = "k_fft_rows"
         n_l, ms = hk[kern]
-        L = res["fft_len"]
+        L = int(res["schedule"].split(":L")[1])   # transform length
         per_pair = 2 * L * 16
         total_bytes = (res["timed_calls"] * res["pairs"] * per_pair +
                        n_l * L * 16)

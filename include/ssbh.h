@@ -350,8 +350,8 @@ ssbh_status ssbh_tune_table(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* The kernel and schedule that the last ssbh_hash_batch or ssbh_tune call on
  * this context launched, as "valu:R:waves:chunk_cols:tile_cols" or
- * "mfma:MT:NT:WM:ksplit" (ksplit 0 = automatic; empty before the first call;
- * truncated to len). */
+ * "mfma:MT:NT:WM:ksplit" (ksplit 0 = automatic) or "fft:chunk:L<length>"
+ * (empty before the first call; truncated to len). */
 ssbh_status ssbh_last_schedule(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* Force the schedule of the VALU hash kernel for later calls on this

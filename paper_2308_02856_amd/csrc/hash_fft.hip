@@ -11,7 +11,8 @@
 // (s * xr_a) + i (s * xr_b).
 //
 // Exactness: entries are integers in [0, n_j]; for 0/1 data and L <= 2^18 the
-// double-precision FFT error is below 1e-8, far from 1/2.  Every output entry
+// double-precision FFT error is below 1e-8, far from 1/2.  L is the smallest
+// of 2^k and 3 * 2^k (k >= 12) that holds the seed.  Every output entry
 // is rounded and its distance to the integer is checked (> 1/4 sets
 // SSBH_E_PRECISION), so a result is never silently wrong.
 //
@@ -26,7 +27,8 @@
 //                64 consecutive output rows per wavefront ballot.
 // The seed spectrum comes from the same two forward passes.  LDS FFTs are
 // Stockham autosort stages with radix-8 butterflies in registers (radix 2 or
-// 4 last), twiddles from a table of w_4096^k; the first stage of each pass
+// 4, then radix 3 when L has a factor 3), twiddles from tables of w_N^k; the
+// first stage of each pass
 // reads global memory (or bits) and the last one writes its result straight
 // out (spectrum product, twiddle, or parity ballot fused in).
 #include <algorithm>
@@ -47,7 +49,6 @@ ssbh_status plan_only(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
 namespace {
 
 constexpr int kN1 = 64;        // column FFT length (and columns per tile)
-constexpr int kTW = 4096;      // size of the w_4096 twiddle table
 constexpr int kThreads = 512;
 
 struct FftArgs {
@@ -62,7 +63,8 @@ struct FftArgs {
     uint32_t pair0;            // first pair of this chunk
     double2 *work;             // [pairs in chunk][L]
     double2 *spec;             // [L], transposed frequency order
-    const double2 *tw;         // w_4096^k, k < 4096
+    const double2 *tw64;       // w_64^k, k < 64 (column FFTs)
+    const double2 *twr;        // w_N2^k, k < N2 (row FFTs)
     const double2 *tlo, *thi;  // w_L^e = thi[e >> 9] * tlo[e & 511]
     uint64_t *out;
     int32_t *status;
@@ -138,10 +140,23 @@ __device__ __forceinline__ void dft8(double2 (&v)[8]) {
     t = v[3]; v[3] = v[6]; v[6] = t;
 }
 
+// 3-point DFT: with w = exp(-+2 pi i / 3), X1,2 = v0 - (v1 + v2)/2 -+ i (sqrt(3)/2)(v1 - v2).
+template <bool INV>
+__device__ __forceinline__ void dft3(double2 (&v)[3]) {
+    const double hs = 0.86602540378443864676;
+    const double2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    const double2 m = make_double2(fma(-0.5, t1.x, v[0].x), fma(-0.5, t1.y, v[0].y));
+    const double2 r = rot90<INV>(make_double2(hs * t2.x, hs * t2.y));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dftR(double2 (&v)[R]) {
     if constexpr (R == 8) dft8<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
+    else if constexpr (R == 3) dft3<INV>(v);
     else dft2<INV>(v);
 }
 
@@ -155,15 +170,17 @@ __device__ __forceinline__ int lds_addr(int f, int e) {
     else return e ^ ((e >> 3) & 7);
 }
 
-// Twiddles w^r, r < R, of w = w_4096^base (conjugated for the inverse):
-// w, w^2, w^4 from the table, the rest by products.
+// Twiddles w^r, r < R, of w = w_N^base from the table of w_N^k (conjugated
+// for the inverse): w, w^2, w^4 from the table, the rest by products.
 template <int R, bool INV>
 __device__ __forceinline__ void twiddle(double2 (&v)[R], int base,
                                         const double2 *tw) {
     auto ld = [&](int k) { double2 w = tw[k]; return INV ? conj2(w) : w; };
     const double2 w1 = ld(base);
     v[1] = cmul(v[1], w1);
-    if constexpr (R >= 4) {
+    if constexpr (R == 3) {
+        v[2] = cmul(v[2], ld(2 * base));
+    } else if constexpr (R >= 4) {
         const double2 w2 = ld(2 * base);
         const double2 w3 = cmul(w1, w2);
         v[2] = cmul(v[2], w2);
@@ -197,7 +214,7 @@ __device__ __forceinline__ void fft_stage(int span, const double2 *tw, Ld ld,
             const int f = g % F, j = g / F;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[p][r] = ld(f, j + r * G);
-            if (span > 1) twiddle<R, INV>(v[p], (j % span) * (kTW / (span * R)), tw);
+            if (span > 1) twiddle<R, INV>(v[p], (j % span) * (N / (span * R)), tw);
             dftR<R, INV>(v[p]);
         }
     }
@@ -217,36 +234,49 @@ __device__ __forceinline__ void fft_stage(int span, const double2 *tw, Ld ld,
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
-// A whole FFT of length N over F transforms: the first stage reads with
-// `first_ld`, the last stage writes with `last_st`, the stages between go
-// through the LDS buffer.  Radix 8 stages, then one radix 2 or 4 stage when
-// log2 N is not a multiple of 3.  N >= 64.
+// Stage radices of an N-point FFT, N = 2^a or 3 * 2^a: radix 8 while it
+// divides the power of two, then one radix 2 or 4, then one radix 3.
+constexpr int two_part(int n) { return n % 3 == 0 ? n / 3 : n; }
+constexpr int num_stages(int n) {
+    return ilog2c(two_part(n)) / 3 + (ilog2c(two_part(n)) % 3 ? 1 : 0) +
+           (n % 3 == 0 ? 1 : 0);
+}
+constexpr int radix_of(int n, int s) {
+    return s < ilog2c(two_part(n)) / 3 ? 8
+         : (s == ilog2c(two_part(n)) / 3 && ilog2c(two_part(n)) % 3)
+               ? (ilog2c(two_part(n)) % 3 == 1 ? 2 : 4)
+               : 3;
+}
+
+template <int N, int F, bool INV, int S, class Ld, class St, class LL, class LS>
+__device__ __forceinline__ void fft_stages(int span, const double2 *tw,
+                                           Ld first_ld, St last_st, LL lds_ld,
+                                           LS lds_st) {
+    constexpr int NST = num_stages(N);
+    constexpr int R = radix_of(N, S);
+    if constexpr (S == 0)
+        fft_stage<N, R, F, INV, true, true>(span, tw, first_ld, lds_st);
+    else if constexpr (S == NST - 1)
+        fft_stage<N, R, F, INV, true, false>(span, tw, lds_ld, last_st);
+    else
+        fft_stage<N, R, F, INV, true, true>(span, tw, lds_ld, lds_st);
+    if constexpr (S + 1 < NST)
+        fft_stages<N, F, INV, S + 1>(span * R, tw, first_ld, last_st, lds_ld,
+                                     lds_st);
+}
+
+// A whole FFT of length N (2^a or 3 * 2^a, N >= 64) over F transforms, with
+// the twiddle table of w_N^k: the first stage reads with `first_ld`, the last
+// stage writes with `last_st`, the stages between go through the LDS buffer.
+// Every stage has a barrier between its loads and stores (first_ld and
+// last_st may touch the same buffer) and the inner ones one after the stores.
 template <int N, int F, bool INV, class Ld, class St>
 __device__ __forceinline__ void fft_run(double2 *buf, const double2 *tw,
                                         Ld first_ld, St last_st) {
-    constexpr int LG = ilog2c(N);
-    constexpr int S8 = LG / 3, REM = LG % 3;
-    constexpr int NST = S8 + (REM ? 1 : 0);
-    static_assert(NST >= 2, "at least two stages");
+    static_assert(num_stages(N) >= 2, "at least two stages");
     auto lds_ld = [&](int f, int e) { return buf[lds_addr<F>(f, e)]; };
     auto lds_st = [&](int f, int e, double2 x) { buf[lds_addr<F>(f, e)] = x; };
-    int span = 1;
-    // First stage: from first_ld into LDS (first_ld may read the same LDS
-    // buffer, hence the barrier between loads and stores).
-    fft_stage<N, 8, F, INV, true, true>(span, tw, first_ld, lds_st);
-    span *= 8;
-#pragma unroll
-    for (int s = 1; s < NST - 1; ++s) {
-        fft_stage<N, 8, F, INV, true, true>(span, tw, lds_ld, lds_st);
-        span *= 8;
-    }
-    // Last stage: last_st may write the LDS buffer the stage reads.
-    if constexpr (REM == 0)
-        fft_stage<N, 8, F, INV, true, false>(span, tw, lds_ld, last_st);
-    else if constexpr (REM == 1)
-        fft_stage<N, 2, F, INV, true, false>(span, tw, lds_ld, last_st);
-    else
-        fft_stage<N, 4, F, INV, true, false>(span, tw, lds_ld, last_st);
+    fft_stages<N, F, INV, 0>(1, tw, first_ld, last_st, lds_ld, lds_st);
 }
 
 __device__ __forceinline__ double2 omega_l(const FftArgs &a, uint64_t e) {
@@ -309,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
         const uint64_t n2i = c0 + f;
         y[(size_t)k1 * n2 + n2i] = cmul(x, omega_l(a, n2i * k1));
     };
-    fft_run<kN1, kN1, false>(buf, a.tw, ld, st);
+    fft_run<kN1, kN1, false>(buf, a.tw64, ld, st);
 }
 
 // Row pass.  SPEC: forward only, the result is the seed spectrum; else
@@ -326,19 +356,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
     auto lds_ld = [&](int, int e) { return buf[lds_addr<1>(0, e)]; };
     if (SPEC) {
         auto spec_st = [&](int, int e, double2 x) { sp[e] = x; };
-        fft_run<N2, 1, false>(buf, a.tw, gl_ld, spec_st);
+        fft_run<N2, 1, false>(buf, a.twr, gl_ld, spec_st);
         return;
     }
     // Forward, the spectrum product fused into the last stage's stores.
     auto mul_st = [&](int, int e, double2 x) {
         buf[lds_addr<1>(0, e)] = cmul(x, sp[e]);
     };
-    fft_run<N2, 1, false>(buf, a.tw, gl_ld, mul_st);
+    fft_run<N2, 1, false>(buf, a.twr, gl_ld, mul_st);
     __syncthreads();
     auto out_st = [&](int, int e, double2 x) {
         y[e] = cmul(x, conj2(omega_l(a, (uint64_t)e * k1)));
     };
-    fft_run<N2, 1, true>(buf, a.tw, lds_ld, out_st);
+    fft_run<N2, 1, true>(buf, a.twr, lds_ld, out_st);
 }
 
 // XOR `bits` (bit t = output row rlo + t, already cleared outside [0, m))
@@ -404,14 +434,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
             if (lane == 0) put_rows(a.out, o[part], rlo, word);
         }
     };
-    fft_run<kN1, kN1, true>(buf, a.tw, ld, st);
+    fft_run<kN1, kN1, true>(buf, a.tw64, ld, st);
     if (bad) atomicCAS(a.status, 0, (int32_t)SSBH_E_PRECISION);
 }
 
 // Twiddle tables, computed once per transform length on the host in long
 // double and kept by the context.
 struct FftTables {
-    DevBuf tw, tlo, thi;
+    DevBuf tw64, twr, tlo, thi;
 };
 std::mutex g_tab_mu;
 std::map<std::pair<int, uint64_t>, FftTables *> g_tables;   // (device, L)
@@ -424,38 +454,32 @@ ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
         return SSBH_OK;
     }
     const long double two_pi = 6.283185307179586476925286766559L;
-    std::vector<double2> tw(kTW), tlo(512), thi(std::max<uint64_t>(1, L / 512));
-    for (int k = 0; k < kTW; ++k) {
-        const long double ang = -two_pi * (long double)k / (long double)kTW;
-        tw[k] = make_double2((double)cosl(ang), (double)sinl(ang));
-    }
-    for (uint64_t k = 0; k < 512; ++k) {
-        const long double ang = -two_pi * (long double)k / (long double)L;
-        tlo[k] = make_double2((double)cosl(ang), (double)sinl(ang));
-    }
-    for (uint64_t k = 0; k < thi.size(); ++k) {
-        const long double ang = -two_pi * (long double)(k * 512) / (long double)L;
-        thi[k] = make_double2((double)cosl(ang), (double)sinl(ang));
-    }
+    auto unit = [&](uint64_t k, uint64_t n) {
+        const long double ang = -two_pi * (long double)k / (long double)n;
+        return make_double2((double)cosl(ang), (double)sinl(ang));
+    };
+    const uint64_t n2 = L / kN1;
+    std::vector<double2> tw64(kN1), twr(n2), tlo(512), thi(L / 512);
+    for (uint64_t k = 0; k < tw64.size(); ++k) tw64[k] = unit(k, kN1);
+    for (uint64_t k = 0; k < twr.size(); ++k) twr[k] = unit(k, n2);
+    for (uint64_t k = 0; k < tlo.size(); ++k) tlo[k] = unit(k, L);
+    for (uint64_t k = 0; k < thi.size(); ++k) thi[k] = unit(k * 512, L);
     auto *t = new FftTables();
-    ssbh_status st;
-    if ((st = t->tw.reserve(tw.size() * sizeof(double2))) != SSBH_OK ||
-        (st = t->tlo.reserve(tlo.size() * sizeof(double2))) != SSBH_OK ||
-        (st = t->thi.reserve(thi.size() * sizeof(double2))) != SSBH_OK) {
-        t->tw.release(); t->tlo.release(); t->thi.release();
-        delete t;
-        return st;
-    }
-    if (hipMemcpy(t->tw.ptr, tw.data(), tw.size() * sizeof(double2),
-                  hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t->tlo.ptr, tlo.data(), tlo.size() * sizeof(double2),
-                  hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t->thi.ptr, thi.data(), thi.size() * sizeof(double2),
-                  hipMemcpyHostToDevice) != hipSuccess) {
-        t->tw.release(); t->tlo.release(); t->thi.release();
-        delete t;
-        set_error("twiddle table upload failed");
-        return SSBH_E_DEVICE;
+    DevBuf *bufs[4] = {&t->tw64, &t->twr, &t->tlo, &t->thi};
+    const std::vector<double2> *src[4] = {&tw64, &twr, &tlo, &thi};
+    for (int b = 0; b < 4; ++b) {
+        ssbh_status st = bufs[b]->reserve(src[b]->size() * sizeof(double2));
+        if (st == SSBH_OK &&
+            hipMemcpy(bufs[b]->ptr, src[b]->data(), src[b]->size() * sizeof(double2),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("twiddle table upload failed");
+            st = SSBH_E_DEVICE;
+        }
+        if (st != SSBH_OK) {
+            for (DevBuf *d : bufs) d->release();
+            delete t;
+            return st;
+        }
     }
     g_tables[{device, L}] = t;
     *out = t;
@@ -481,16 +505,26 @@ void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
     case 512: launch_rows<512>(a, pairs, spec, stream); break;
     case 1024: launch_rows<1024>(a, pairs, spec, stream); break;
     case 2048: launch_rows<2048>(a, pairs, spec, stream); break;
+    case 192: launch_rows<192>(a, pairs, spec, stream); break;
+    case 384: launch_rows<384>(a, pairs, spec, stream); break;
+    case 768: launch_rows<768>(a, pairs, spec, stream); break;
+    case 1536: launch_rows<1536>(a, pairs, spec, stream); break;
+    case 3072: launch_rows<3072>(a, pairs, spec, stream); break;
     default: launch_rows<4096>(a, pairs, spec, stream); break;
     }
 }
 
 }  // namespace
 
+// Transform length: the smallest supported L that holds the seed (2^k or
+// 3 * 2^k with row FFTs of L / 64 points); kMaxFftLength + 1 when none does.
 uint64_t fft_length(uint64_t seed_bits) {
-    uint64_t L = 4096;
-    while (L < seed_bits) L <<= 1;
-    return L;
+    static const uint64_t lengths[] = {4096,  8192,  12288,  16384,
+                                       24576, 32768, 49152,  65536,
+                                       98304, 131072, 196608, 262144};
+    for (uint64_t L : lengths)
+        if (L >= seed_bits) return L;
+    return kMaxFftLength + 1;
 }
 
 ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
@@ -508,7 +542,8 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
     const uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : 32;
-    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u", s.chunk_pairs);
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u:L%llu",
+             s.chunk_pairs, (unsigned long long)L);
     if (!q.n_sub) return SSBH_OK;
     FftTables *tab = nullptr;
     if ((st = get_tables(ctx->device, L, &tab)) != SSBH_OK) return st;
@@ -526,7 +561,8 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.L = L; a.n2 = (uint32_t)(L / kN1);
     a.work = ws.fft_work.as<double2>();
     a.spec = ws.fft_spec.as<double2>();
-    a.tw = tab->tw.as<double2>();
+    a.tw64 = tab->tw64.as<double2>();
+    a.twr = tab->twr.as<double2>();
     a.tlo = tab->tlo.as<double2>();
     a.thi = tab->thi.as<double2>();
     a.out = q.out;

@@ -201,3 +201,48 @@ def test_fft_graph_pipeline_replays(ctx, orc):
         assert int(st.item()) == 0 and int(tot.item()) == wtot
         assert np.array_equal(to_host(out)[: want.size], want)
     pipe.close()
+
+
+LENGTHS = [4096, 8192, 12288, 16384, 24576, 32768, 49152, 65536, 98304,
+           131072, 196608, 262144]
+
+
+@pytest.mark.parametrize("L", LENGTHS)
+def test_every_transform_length(ctx, orc, L):
+    """Seeds that select each supported transform length (2^k and 3 * 2^k):
+    FFT == VALU kernel on every bit, and sampled rows == the oracle."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    ns = 6
+    seed_bits = L - 3                       # selects exactly this length
+    lens = np.array([seed_bits // 2 - 7 * j for j in range(ns)], dtype=np.uint64)
+    M = int(seed_bits - int(lens.max()) + 1)            # n_max + M - 1 = seed_bits
+    outl = np.array([M - 11 * j for j in range(ns)], dtype=np.uint64)
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = uniform_bits(int(words.sum()) * 64, L)
+    for j in range(ns):
+        r = int(lens[j]) % 64
+        if r:
+            sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
+    seed = uniform_bits(seed_bits, L + 1)
+    dl = torch.from_numpy(outl.view(np.int64)).cuda()
+    args = (to_dev(sub), sub.size, to_dev(lens), to_dev(wo), ns, to_dev(seed),
+            seed_bits, M)
+    kw = dict(out_rule=ssbh.OUT_EXPLICIT, out_len=dl)
+    got, tot = fft_hash(ctx, args[0], args[2], args[3], ns, args[5],
+                        seed_bits, M, **kw)
+    assert ctx.last_schedule().endswith(":L%d" % L)
+    out, tot2, st = ctx.hash_batch(*args, kernel=ssbh.K_VALU, **kw)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and int(tot2.item()) == tot
+    assert np.array_equal(got, to_host(out))
+    ooff = np.concatenate([[0], np.cumsum(outl)[:-1]])
+    rng = np.random.default_rng(L)
+    for _ in range(12):
+        j = int(rng.integers(0, ns))
+        r = int(rng.integers(0, int(outl[j])))
+        want = orc.toeplitz_rowwin(sub[int(wo[j]):], int(lens[j]), seed,
+                                   seed_bits, 0, M, r)
+        k = int(ooff[j]) + r
+        assert ((int(got[k >> 6]) >> (k & 63)) & 1) == want, (j, r)
