@@ -246,3 +246,33 @@ def test_every_transform_length(ctx, orc, L):
                                    seed_bits, 0, M, r)
         k = int(ooff[j]) + r
         assert ((int(got[k >> 6]) >> (k & 63)) & 1) == want, (j, r)
+
+
+@pytest.mark.parametrize("density", [0.05, 0.5, 0.95])
+def test_seed_density_stays_exact(ctx, density):
+    """Sparse, half-dense and dense seeds (the error bound grows with the
+    seed's popcount) all give the VALU kernel's bits."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    ns = 10
+    seed_bits = 190000
+    lens = np.array([95000 - 313 * j for j in range(ns)], dtype=np.uint64)
+    M = seed_bits - int(lens.max()) + 1
+    outl = np.array([M - 97 * j for j in range(ns)], dtype=np.uint64)
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = bernoulli_bits(int(words.sum()) * 64, 0.5, 3)
+    for j in range(ns):
+        r = int(lens[j]) % 64
+        if r:
+            sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
+    seed = bernoulli_bits(seed_bits, density, 4)
+    dl = torch.from_numpy(outl.view(np.int64)).cuda()
+    kw = dict(out_rule=ssbh.OUT_EXPLICIT, out_len=dl)
+    d_sub, d_len, d_wo, d_seed = to_dev(sub), to_dev(lens), to_dev(wo), to_dev(seed)
+    got, tot = fft_hash(ctx, d_sub, d_len, d_wo, ns, d_seed, seed_bits, M, **kw)
+    out, tot2, st = ctx.hash_batch(d_sub, d_sub.numel(), d_len, d_wo, ns, d_seed,
+                                   seed_bits, M, kernel=ssbh.K_VALU, **kw)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and int(tot2.item()) == tot
+    assert np.array_equal(got, to_host(out))
