@@ -58,7 +58,9 @@ struct FftArgs {
     uint64_t seed_bits;
     uint64_t mcap;
     uint32_t ns;
-    uint32_t n2;               // L / 64
+    uint32_t n2;               // L / 64 (level-1 columns)
+    uint32_t nr;               // row FFT length: L / 64 (two levels) or
+                               // L / 4096 (three levels)
     uint64_t L;
     uint32_t pair0;            // first pair of this chunk
     double2 *work;             // [pairs in chunk][L]
@@ -66,6 +68,8 @@ struct FftArgs {
     const double2 *tw64;       // w_64^k, k < 64 (column FFTs)
     const double2 *twr;        // w_N2^k, k < N2 (row FFTs)
     const double2 *tlo, *thi;  // w_L^e = thi[e >> 9] * tlo[e & 511]
+    const double2 *rlo, *rhi;  // w_(64 nr)^e, same split (= w_L for two
+                               // levels, w_(L/64) for three)
     uint64_t *out;
     int32_t *status;
 };
@@ -282,6 +286,9 @@ __device__ __forceinline__ void fft_run(double2 *buf, const double2 *tw,
 __device__ __forceinline__ double2 omega_l(const FftArgs &a, uint64_t e) {
     return cmul(a.thi[e >> 9], a.tlo[e & 511]);
 }
+__device__ __forceinline__ double2 omega_r(const FftArgs &a, uint64_t e) {
+    return cmul(a.rhi[e >> 9], a.rlo[e & 511]);
+}
 
 // Bits b0 .. b0+63 of a bit string of nbits bits at words w (0 outside).
 __device__ __forceinline__ uint64_t window64(const uint64_t *w, int64_t nbits,
@@ -342,16 +349,20 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     fft_run<kN1, kN1, false>(buf, a.tw64, ld, st);
 }
 
-// Row pass.  SPEC: forward only, the result is the seed spectrum; else
-// forward, times the spectrum, inverse, times w_L^(-n2 k1).
+// Row pass over rows of N2 (= nr) points.  SPEC: forward only, the result is
+// the seed spectrum; else forward, times the spectrum, inverse, times
+// w_(64 N2)^(-e (row mod 64)) -- the inverse of the twiddle of the column
+// pass that made the row (w_L^(n2 k1) with two levels, w_(L/64)^(m2 l1) with
+// three).
 template <int N2, bool SPEC>
 __global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
     __shared__ double2 buf[N2];
     if (*a.status) return;
-    const uint32_t k1 = blockIdx.x;
+    const uint32_t row = blockIdx.x;
     const uint32_t pl = blockIdx.y;
-    double2 *y = a.work + (size_t)pl * a.L + (size_t)k1 * N2;
-    double2 *sp = a.spec + (size_t)k1 * N2;
+    const uint64_t k1 = row & 63u;
+    double2 *y = a.work + (size_t)pl * a.L + (size_t)row * N2;
+    double2 *sp = a.spec + (size_t)row * N2;
     auto gl_ld = [&](int, int e) { return y[e]; };
     auto lds_ld = [&](int, int e) { return buf[lds_addr<1>(0, e)]; };
     if (SPEC) {
@@ -366,9 +377,33 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
     fft_run<N2, 1, false>(buf, a.twr, gl_ld, mul_st);
     __syncthreads();
     auto out_st = [&](int, int e, double2 x) {
-        y[e] = cmul(x, conj2(omega_l(a, (uint64_t)e * k1)));
+        y[e] = cmul(x, conj2(omega_r(a, (uint64_t)e * k1)));
     };
     fft_run<N2, 1, true>(buf, a.twr, lds_ld, out_st);
+}
+
+// Middle column pass of the three-level transform, on each level-1 row
+// (k1) of L/64 = 64 nr points viewed as 64 x nr: 64-point FFTs down 64-column
+// tiles.  Forward: times w_(L/64)^(m2 l1).  Inverse (INV): the rows are
+// already multiplied by the inverse of that twiddle; after the inverse FFT
+// the level-1 twiddle is undone, times w_L^(-n2 k1) with n2 = nr m1 + m2.
+template <bool INV>
+__global__ __launch_bounds__(kThreads) void k_fft_mid(FftArgs a) {
+    __shared__ double2 buf[kN1 * kN1];
+    if (*a.status) return;
+    const uint32_t nr = a.nr;
+    const uint32_t c0 = blockIdx.x * kN1;
+    const uint64_t k1 = blockIdx.y;
+    const uint32_t pl = blockIdx.z;
+    double2 *y = a.work + (size_t)pl * a.L + (size_t)k1 * a.n2;
+    auto ld = [&](int f, int e) { return y[(size_t)e * nr + c0 + f]; };
+    auto st = [&](int f, int k, double2 x) {
+        const uint64_t m2 = c0 + f;
+        const double2 w = INV ? conj2(omega_l(a, ((uint64_t)k * nr + m2) * k1))
+                              : omega_r(a, m2 * (uint64_t)k);
+        y[(size_t)k * nr + m2] = cmul(x, w);
+    };
+    fft_run<kN1, kN1, INV>(buf, a.tw64, ld, st);
 }
 
 // XOR `bits` (bit t = output row rlo + t, already cleared outside [0, m))
@@ -441,10 +476,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
 // Twiddle tables, computed once per transform length on the host in long
 // double and kept by the context.
 struct FftTables {
-    DevBuf tw64, twr, tlo, thi;
+    DevBuf tw64, twr, tlo, thi, rlo, rhi;
 };
 std::mutex g_tab_mu;
 std::map<std::pair<int, uint64_t>, FftTables *> g_tables;   // (device, L)
+
+// Row FFT length: L / 64 up to 2^18, else L / 4096 (three levels).
+uint64_t row_length(uint64_t L) { return L <= (1ull << 18) ? L / 64 : L / 4096; }
 
 ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
     std::lock_guard<std::mutex> lk(g_tab_mu);
@@ -458,16 +496,19 @@ ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
         const long double ang = -two_pi * (long double)k / (long double)n;
         return make_double2((double)cosl(ang), (double)sinl(ang));
     };
-    const uint64_t n2 = L / kN1;
-    std::vector<double2> tw64(kN1), twr(n2), tlo(512), thi(L / 512);
+    const uint64_t nr = row_length(L), lr = 64 * nr;
+    std::vector<double2> tw64(kN1), twr(nr), tlo(512), thi(L / 512),
+        rlo(512), rhi(lr / 512);
     for (uint64_t k = 0; k < tw64.size(); ++k) tw64[k] = unit(k, kN1);
-    for (uint64_t k = 0; k < twr.size(); ++k) twr[k] = unit(k, n2);
+    for (uint64_t k = 0; k < twr.size(); ++k) twr[k] = unit(k, nr);
     for (uint64_t k = 0; k < tlo.size(); ++k) tlo[k] = unit(k, L);
     for (uint64_t k = 0; k < thi.size(); ++k) thi[k] = unit(k * 512, L);
+    for (uint64_t k = 0; k < rlo.size(); ++k) rlo[k] = unit(k, lr);
+    for (uint64_t k = 0; k < rhi.size(); ++k) rhi[k] = unit(k * 512, lr);
     auto *t = new FftTables();
-    DevBuf *bufs[4] = {&t->tw64, &t->twr, &t->tlo, &t->thi};
-    const std::vector<double2> *src[4] = {&tw64, &twr, &tlo, &thi};
-    for (int b = 0; b < 4; ++b) {
+    DevBuf *bufs[6] = {&t->tw64, &t->twr, &t->tlo, &t->thi, &t->rlo, &t->rhi};
+    const std::vector<double2> *src[6] = {&tw64, &twr, &tlo, &thi, &rlo, &rhi};
+    for (int b = 0; b < 6; ++b) {
         ssbh_status st = bufs[b]->reserve(src[b]->size() * sizeof(double2));
         if (st == SSBH_OK &&
             hipMemcpy(bufs[b]->ptr, src[b]->data(), src[b]->size() * sizeof(double2),
@@ -489,41 +530,46 @@ ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
 template <int N2>
 void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
                  hipStream_t stream) {
+    const uint32_t rows = (uint32_t)(a.L / N2);
     if (spec)
-        hipLaunchKernelGGL((k_fft_rows<N2, true>), dim3(kN1, 1), dim3(kThreads),
+        hipLaunchKernelGGL((k_fft_rows<N2, true>), dim3(rows, 1), dim3(kThreads),
                            0, stream, a);
     else
-        hipLaunchKernelGGL((k_fft_rows<N2, false>), dim3(kN1, pairs),
+        hipLaunchKernelGGL((k_fft_rows<N2, false>), dim3(rows, pairs),
                            dim3(kThreads), 0, stream, a);
 }
 
 void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
-    switch (a.n2) {
+    switch (a.nr) {
     case 64: launch_rows<64>(a, pairs, spec, stream); break;
     case 128: launch_rows<128>(a, pairs, spec, stream); break;
-    case 256: launch_rows<256>(a, pairs, spec, stream); break;
-    case 512: launch_rows<512>(a, pairs, spec, stream); break;
-    case 1024: launch_rows<1024>(a, pairs, spec, stream); break;
-    case 2048: launch_rows<2048>(a, pairs, spec, stream); break;
     case 192: launch_rows<192>(a, pairs, spec, stream); break;
+    case 256: launch_rows<256>(a, pairs, spec, stream); break;
     case 384: launch_rows<384>(a, pairs, spec, stream); break;
+    case 512: launch_rows<512>(a, pairs, spec, stream); break;
     case 768: launch_rows<768>(a, pairs, spec, stream); break;
+    case 1024: launch_rows<1024>(a, pairs, spec, stream); break;
     case 1536: launch_rows<1536>(a, pairs, spec, stream); break;
+    case 2048: launch_rows<2048>(a, pairs, spec, stream); break;
     case 3072: launch_rows<3072>(a, pairs, spec, stream); break;
-    default: launch_rows<4096>(a, pairs, spec, stream); break;
+    case 4096: launch_rows<4096>(a, pairs, spec, stream); break;
+    default: launch_rows<6144>(a, pairs, spec, stream); break;
     }
 }
 
 }  // namespace
 
-// Transform length: the smallest supported L that holds the seed (2^k or
-// 3 * 2^k with row FFTs of L / 64 points); kMaxFftLength + 1 when none does.
+// Transform length: the smallest supported L that holds the seed, 2^k or
+// 3 * 2^k: L <= 2^18 as 64 x (L/64), larger L as 64 x 64 x (L/4096) with
+// row FFTs of 96 .. 6144 points; kMaxFftLength + 1 when none holds it.
 uint64_t fft_length(uint64_t seed_bits) {
-    static const uint64_t lengths[] = {4096,  8192,  12288,  16384,
-                                       24576, 32768, 49152,  65536,
-                                       98304, 131072, 196608, 262144};
-    for (uint64_t L : lengths)
+    // Every length is a multiple of 4096 whose row length is a multiple of
+    // 64 (or a two-level length): 3 * 2^11 and 3 * 2^17 are left out.
+    for (uint64_t L = 4096; L <= kMaxFftLength;) {
         if (L >= seed_bits) return L;
+        L = (L % 3 == 0) ? L / 3 * 4 : L / 2 * 3;   // 2^k, 3 * 2^(k-1), 2^(k+1)
+        if (L == 6144 || L == 393216) L = L / 3 * 4;
+    }
     return kMaxFftLength + 1;
 }
 
@@ -541,7 +587,10 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
-    const uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : 32;
+    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : 32;
+    // At most 512 MiB of transforms per chunk.
+    chunk = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
     snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u:L%llu",
              s.chunk_pairs, (unsigned long long)L);
     if (!q.n_sub) return SSBH_OK;
@@ -559,12 +608,16 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.seed = q.seed; a.seed_bits = q.seed_bits;
     a.mcap = q.m_cap; a.ns = q.n_sub;
     a.L = L; a.n2 = (uint32_t)(L / kN1);
+    a.nr = (uint32_t)row_length(L);
+    const bool three = a.nr != a.n2;
     a.work = ws.fft_work.as<double2>();
     a.spec = ws.fft_spec.as<double2>();
     a.tw64 = tab->tw64.as<double2>();
     a.twr = tab->twr.as<double2>();
     a.tlo = tab->tlo.as<double2>();
     a.thi = tab->thi.as<double2>();
+    a.rlo = tab->rlo.as<double2>();
+    a.rhi = tab->rhi.as<double2>();
     a.out = q.out;
     a.status = q.status;
     const uint32_t tiles = a.n2 / kN1;
@@ -574,6 +627,9 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         TimedLaunch timed(ws.timer, "k_fft_spectrum", stream);
         hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
                            stream, a);
+        if (three)
+            hipLaunchKernelGGL(k_fft_mid<false>, dim3(a.nr / kN1, kN1, 1),
+                               dim3(kThreads), 0, stream, a);
         rows(a, 1, true, stream);
     }
     for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
@@ -584,9 +640,19 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             hipLaunchKernelGGL(k_fft_cols<false>, dim3(tiles, np),
                                dim3(kThreads), 0, stream, a);
         }
+        if (three) {
+            TimedLaunch timed(ws.timer, "k_fft_mid", stream);
+            hipLaunchKernelGGL(k_fft_mid<false>, dim3(a.nr / kN1, kN1, np),
+                               dim3(kThreads), 0, stream, a);
+        }
         {
             TimedLaunch timed(ws.timer, "k_fft_rows", stream);
             rows(a, np, false, stream);
+        }
+        if (three) {
+            TimedLaunch timed(ws.timer, "k_fft_mid", stream);
+            hipLaunchKernelGGL(k_fft_mid<true>, dim3(a.nr / kN1, kN1, np),
+                               dim3(kThreads), 0, stream, a);
         }
         {
             TimedLaunch timed(ws.timer, "k_fft_out", stream);

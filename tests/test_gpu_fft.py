@@ -124,7 +124,7 @@ def test_rejects_independent_seeds_and_long_seeds(ctx):
                        kernel=ssbh.K_FFT)
     assert e.value.status == ssbh.E_INVAL
     with pytest.raises(ssbh.SsbhError) as e:
-        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, (1 << 18) + 1, 100,
+        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, (3 << 23) + 1, 100,
                        out_rule=ssbh.OUT_FIXED, out_a=100, kernel=ssbh.K_FFT)
     assert e.value.status == ssbh.E_UNSUPPORTED
 
@@ -204,7 +204,7 @@ def test_fft_graph_pipeline_replays(ctx, orc):
 
 
 LENGTHS = [4096, 8192, 12288, 16384, 24576, 32768, 49152, 65536, 98304,
-           131072, 196608, 262144]
+           131072, 196608, 262144, 524288, 786432, 1048576]
 
 
 @pytest.mark.parametrize("L", LENGTHS)
@@ -276,3 +276,31 @@ def test_seed_density_stays_exact(ctx, density):
     torch.cuda.synchronize()
     assert int(st.item()) == 0 and int(tot2.item()) == tot
     assert np.array_equal(got, to_host(out))
+
+
+def test_single_block_workload_three_levels(ctx, orc):
+    """The single-block workload (n = 2^24 -> m = 2^23, seed n + m - 1 bits)
+    runs as a three-level transform of 3 * 2^23 points: equal to the VALU
+    kernel on every bit and to the oracle on sampled rows."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    c = config("single")
+    n, m = c["n_bits"], c["out_a"]
+    x = uniform_bits(n, c["input_seed"])
+    seed_bits = n + m - 1
+    seed_h = uniform_bits(seed_bits, c["seed_seed"])
+    d_x, seed = to_dev(x), to_dev(seed_h)
+    ln = torch.tensor([n], dtype=torch.int64, device="cuda")
+    wo = torch.zeros(1, dtype=torch.int64, device="cuda")
+    kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m)
+    got, tot = fft_hash(ctx, d_x, ln, wo, 1, seed, seed_bits, m, **kw)
+    assert ctx.last_schedule().endswith(":L%d" % (3 << 23))
+    out, tot2, st = ctx.hash_batch(d_x, d_x.numel(), ln, wo, 1, seed,
+                                   seed_bits, m, kernel=ssbh.K_VALU, **kw)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and tot == int(tot2.item()) == m
+    assert np.array_equal(got, to_host(out))
+    rng = np.random.default_rng(24)
+    for r in [0, 1, m - 1] + [int(v) for v in rng.integers(0, m, 10)]:
+        want = orc.toeplitz_rowwin(x, n, seed_h, seed_bits, 0, m, r)
+        assert ((int(got[r >> 6]) >> (r & 63)) & 1) == want, r
