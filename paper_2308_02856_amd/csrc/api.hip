@@ -177,6 +177,20 @@ std::string tune_bucket(const HashRequest &q) {
     return b;
 }
 
+// Untuned choice between the FFT and the quadratic kernels for a shared
+// seed.  Per sub-block the quadratic kernels do about n * m bit-products at
+// roughly 2.5e15 per second; the FFT does half a transform pair, about
+// L log2 L points at roughly 1e-12 s per point-level (both measured on
+// MI355X).  The FFT is taken when n * m >= 1024 L log2 L, n estimated from
+// the seed length (n_max + m_cap - 1 bits).
+bool fft_pays(const HashRequest &q) {
+    const uint64_t L = fft_length(q.seed_bits);
+    if (L > kMaxFftLength || q.seed_bits + 1 <= q.m_cap) return false;
+    const double n = (double)(q.seed_bits + 1 - q.m_cap);
+    const double m = (double)q.m_cap;
+    return n * m >= 1024.0 * (double)L * std::log2((double)L);
+}
+
 ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                         hipStream_t stream) {
     (void)hipGetLastError();   // clear errors left by earlier calls
@@ -210,6 +224,10 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                 r.kernel = SSBH_K_VALU;
                 return launch_hash_valu(ctx, ws, r, vs, stream);
             }
+        }
+        if (q.stride == 0 && !ctx->forced_valu_r && fft_pays(q)) {
+            r.kernel = SSBH_K_FFT;
+            return launch_hash(ctx, ws, r, stream);
         }
         if (q.stride == 0 && q.n_sub >= 64 && !ctx->forced_valu_r) {
             r.kernel = SSBH_K_MFMA_I8;

@@ -43,6 +43,7 @@ struct SampleArgs {
     uint32_t nseg;
     uint32_t nchunk;
     uint32_t *counts;        // [nseg][ns]
+    uint16_t *qcnt;          // [nseg][3][ns] counts of quarters 0..2
     uint32_t *offs;          // [nseg][ns]
     uint32_t *part;          // [nchunk][ns]
     uint64_t *sub;
@@ -101,6 +102,68 @@ __global__ __launch_bounds__(256) void k_hist(SampleArgs a) {
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): LDS atomics done
     uint32_t *dst = a.counts + (uint64_t)seg * a.ns;
     for (uint32_t j = lane; j < a.ns; j += 64) dst[j] = hist[j];
+}
+
+// Histogram for the workgroup scatter: one workgroup of four wavefronts per
+// segment, wavefront w counting quarter w of it.  Writes the segment totals
+// counts[seg][j] and the counts of quarters 0..2, qcnt[seg][w][j] (uint16: a
+// quarter has fewer than 2^16 rounds), which place each quarter's run inside
+// the segment's run.  Counting does not depend on the order of the rounds,
+// so lane l takes rounds 2l and 2l + 1 of every 128-round block from the low
+// and high halves of one SplitMix64 output.
+template <bool EXPLICIT>
+__global__ __launch_bounds__(256) void k_hist_q(SampleArgs a) {
+    extern __shared__ uint32_t lds[];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t ns = a.ns;
+    // Clear the sub-block buffer (the scatter ORs partial words into it).
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + t; k < a.sub_cap;
+         k += stride)
+        a.sub[k] = 0ull;
+    const uint32_t seg = blockIdx.x;
+    if (seg >= a.nseg) return;      // whole workgroup
+    uint32_t *hist = lds;           // [4][ns]
+    for (uint32_t k = t; k < 4 * ns; k += 256) hist[k] = 0u;
+    __syncthreads();
+    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
+    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
+    const uint64_t qlen = a.seg_bits / 4;               // multiple of 128
+    const uint64_t qa = i0 + (uint64_t)w * qlen;
+    const uint64_t qb = min(qa + qlen, i1);
+    uint32_t *h = hist + (uint32_t)w * ns;
+    bool bad = false;
+    for (uint64_t base = qa; base < qb; base += 128) {
+        const uint64_t iA = base + 2 * (uint64_t)lane, iB = iA + 1;
+        uint32_t vA, vB;
+        if constexpr (EXPLICIT) {
+            vA = iA < qb ? a.assign[iA] : 0u;
+            vB = iB < qb ? a.assign[iB] : 0u;
+        } else {
+            const uint64_t r = splitmix64_at(a.key, (base >> 1) + (uint64_t)lane);
+            vA = __umulhi((uint32_t)r, ns);
+            vB = __umulhi((uint32_t)(r >> 32), ns);
+        }
+        if (iA < qb) {
+            if (vA >= ns) bad = true;
+            else if (kept(a, iA)) atomicAdd(&h[vA], 1u);
+        }
+        if (iB < qb) {
+            if (vB >= ns) bad = true;
+            else if (kept(a, iB)) atomicAdd(&h[vB], 1u);
+        }
+    }
+    if (bad) atomicExch(a.status, (int32_t)SSBH_E_INVAL);
+    __syncthreads();
+    uint32_t *dst = a.counts + (uint64_t)seg * ns;
+    uint16_t *q = a.qcnt + (uint64_t)seg * 3 * ns;
+    for (uint32_t j = t; j < ns; j += 256) {
+        const uint32_t c0 = hist[j], c1 = hist[ns + j], c2 = hist[2 * ns + j];
+        dst[j] = c0 + c1 + c2 + hist[3 * ns + j];
+        q[j] = (uint16_t)c0;
+        q[ns + j] = (uint16_t)c1;
+        q[2 * ns + j] = (uint16_t)c2;
+    }
 }
 
 // part[c][j] = sum of counts[seg][j] over the segments of chunk c.
@@ -426,15 +489,15 @@ __device__ __forceinline__ void flush_runs_t(const SampleArgs &a, uint32_t seg,
 
 // Scatter with one workgroup of 4 wavefronts per segment; wavefront w takes
 // the w-th quarter of the segment.
-//   1. every wavefront counts its quarter per sub-block (LDS atomics);
-//   2. a workgroup scan turns the counts into each wavefront's first
-//      position of every run in the LDS image of the segment (sorted by
-//      sub-block, stable: quarter w comes after quarters < w);
-//   3. every wavefront ranks equal V_i inside each 64-round step: a 256-slot
+//   1. the segment totals and quarter counts of k_hist_q give each
+//      wavefront's first position of every run in the LDS image of the
+//      segment (sorted by sub-block, stable: quarter w comes after quarters
+//      < w);
+//   2. every wavefront ranks equal V_i inside each 64-round step: a 256-slot
 //      match table (OR of lane bits at slot V mod 256, read back) narrowed by
 //      ballots on the bits of V above 8, then advances its cursors and ORs
 //      the bits into the image;
-//   4. all runs are copied out as in flush_runs.
+//   3. all runs are copied out as in flush_runs.
 // LDS: 4 cursor tables (4 n_sub words), 4 match tables (8 KiB), the image.
 template <bool EXPLICIT>
 __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
@@ -448,7 +511,6 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     uint32_t *stage = reinterpret_cast<uint32_t *>(tab + 4 * 256);
     const uint32_t seg = blockIdx.x;
     const uint32_t nsw = (uint32_t)(a.seg_bits / 32) + 4;
-    for (uint32_t k = t; k < 4 * ns; k += 256) cur[k] = 0u;
     for (uint32_t k = t; k < 4 * 256; k += 256) tab[k] = 0ull;
     for (uint32_t k = t; k < nsw; k += 256) stage[k] = 0u;
     __syncthreads();
@@ -460,24 +522,16 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     const uint64_t qb = min(qa + qlen, i1);
     uint32_t *mc = cur + (uint32_t)w * ns;
 
-    // 1. Counts of this wavefront's quarter.
-    for (uint64_t base = qa; base < qb; base += 128) {
-        uint32_t vA, vB;
-        sample_v2<EXPLICIT>(a, base, lane, vA, vB);
-        const uint64_t iA = base + lane, iB = iA + 64;
-        if (iA < qb && vA < ns && kept(a, iA)) atomicAdd(&mc[vA], 1u);
-        if (iB < qb && vB < ns && kept(a, iB)) atomicAdd(&mc[vB], 1u);
-    }
-    __syncthreads();
-
-    // 2. Run starts: exclusive scan over sub-blocks of the segment totals,
-    //    then each quarter's offset inside its run.
+    // 1. Run starts: exclusive scan over sub-blocks of the segment totals
+    //    (from the histogram), then each quarter's offset inside its run from
+    //    the counts of the quarters before it.
     {
+        const uint32_t *cnt = a.counts + (uint64_t)seg * ns;
+        const uint16_t *q = a.qcnt + (uint64_t)seg * 3 * ns;
         const uint32_t per = (ns + 255) / 256;
         const uint32_t v0 = min((uint32_t)t * per, ns), v1 = min(v0 + per, ns);
         uint32_t sum = 0;
-        for (uint32_t v = v0; v < v1; ++v)
-            sum += cur[v] + cur[ns + v] + cur[2 * ns + v] + cur[3 * ns + v];
+        for (uint32_t v = v0; v < v1; ++v) sum += cnt[v];
         uint32_t incl = sum;
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t x = __shfl_up(incl, d, 64);
@@ -488,18 +542,17 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
         uint32_t run = incl - sum;
         for (int k = 0; k < w; ++k) run += wsum[k];
         for (uint32_t v = v0; v < v1; ++v) {
-            const uint32_t c0 = cur[v], c1 = cur[ns + v], c2 = cur[2 * ns + v],
-                           c3 = cur[3 * ns + v];
+            const uint32_t c0 = q[v], c1 = q[ns + v], c2 = q[2 * ns + v];
             cur[v] = run;
             cur[ns + v] = run + c0;
             cur[2 * ns + v] = run + c0 + c1;
             cur[3 * ns + v] = run + c0 + c1 + c2;
-            run += c0 + c1 + c2 + c3;
+            run += cnt[v];
         }
     }
     __syncthreads();
 
-    // 3. Stable placement.
+    // 2. Stable placement.
     uint64_t *mt = tab + (uint32_t)w * 256;
     const uint64_t me = 1ull << lane;
     const uint64_t below = me - 1ull;
@@ -539,7 +592,7 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __syncthreads();
 
-    // 4. Runs out; the last quarter's cursors are the run ends.
+    // 3. Runs out; the last quarter's cursors are the run ends.
     flush_runs_t(a, seg, cur + 3 * ns, stage, t, 256);
 }
 
@@ -597,10 +650,12 @@ uint32_t ceil_log2(uint32_t x) {
 
 // Segment size: about 32 bits per sub-block per segment (so runs are a few
 // words long), at least 2^14 bits, LDS image at most 32 KiB.
+// Segment length: about 32 rounds per sub-block, 2^14 .. 2^18 - 512 rounds
+// (a quarter stays below 2^16 rounds), a multiple of 512.
 static uint64_t segment_bits(uint32_t ns) {
     uint64_t seg = 32ull * ns;
     seg = std::max<uint64_t>(seg, 1ull << 14);
-    seg = std::min<uint64_t>(seg, 1ull << 18);
+    seg = std::min<uint64_t>(seg, (1ull << 18) - 512);
     return (seg + 511) / 512 * 512;
 }
 
@@ -610,8 +665,9 @@ ScratchSizes sample_scratch(uint64_t n, uint32_t ns, uint32_t mode) {
     const uint64_t seg = segment_bits(ns);
     const uint64_t nseg = (n + seg - 1) / seg;
     const uint64_t nchunk = (nseg + kSegChunk - 1) / kSegChunk;
-    z.counts = (size_t)std::max<uint64_t>(nseg, 1) * ns * 4;
-    z.offs = z.counts;
+    // counts [nseg][ns] uint32, then the quarter counts [nseg][3][ns] uint16.
+    z.offs = (size_t)std::max<uint64_t>(nseg, 1) * ns * 4;
+    z.counts = z.offs + (size_t)std::max<uint64_t>(nseg, 1) * ns * 6;
     z.part = (size_t)std::max<uint64_t>(nchunk, 1) * ns * 4;
     return z;
 }
@@ -697,6 +753,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     if ((st = ws.offs.reserve(sz.offs)) != SSBH_OK) return st;
     if ((st = ws.part.reserve(sz.part)) != SSBH_OK) return st;
     a.counts = ws.counts.as<uint32_t>();
+    a.qcnt = reinterpret_cast<uint16_t *>(a.counts + (size_t)std::max<uint32_t>(a.nseg, 1) * ns);
     a.offs = ws.offs.as<uint32_t>();
     a.part = ws.part.as<uint32_t>();
 
@@ -730,7 +787,20 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
             return st;
         }
     }
-    {
+    if (use_wg) {
+        // One workgroup per segment (extra workgroups only clear the buffer).
+        const uint32_t blocks = std::max<uint32_t>(
+            std::max<uint32_t>(a.nseg, 1),
+            (uint32_t)std::min<uint64_t>((sub_cap + 255) / 256, 2048));
+        const size_t q_lds = (size_t)4 * ns * 4;
+        TimedLaunch timed(ws.timer, "k_hist", stream);
+        if (ex)
+            hipLaunchKernelGGL(k_hist_q<true>, dim3(blocks), dim3(256), q_lds,
+                               stream, a);
+        else
+            hipLaunchKernelGGL(k_hist_q<false>, dim3(blocks), dim3(256), q_lds,
+                               stream, a);
+    } else {
         TimedLaunch timed(ws.timer, "k_hist", stream);
         if (ex)
             hipLaunchKernelGGL(k_hist<true>, dim3(hist_blocks), dim3(64 * wpb),

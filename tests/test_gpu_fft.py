@@ -304,3 +304,35 @@ def test_single_block_workload_three_levels(ctx, orc):
     for r in [0, 1, m - 1] + [int(v) for v in rng.integers(0, m, 10)]:
         want = orc.toeplitz_rowwin(x, n, seed_h, seed_bits, 0, m, r)
         assert ((int(got[r >> 6]) >> (r & 63)) & 1) == want, r
+
+
+@pytest.mark.parametrize("n,m,want_fft", [(1 << 16, 1 << 15, True),
+                                          (4000, 2000, False)])
+def test_untuned_auto_picks_fft_for_long_blocks(n, m, want_fft):
+    """Without a tuned entry, AUTO takes the FFT for a shared seed when the
+    quadratic work is far above the transform's (n m >= 1024 L log2 L), and
+    gives the VALU kernel's bits either way."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    ctx = ssbh.Context(0)
+    try:
+        ns = 4
+        words = (n + 63) // 64
+        sub = uniform_bits(ns * words * 64, n)
+        lens = np.full(ns, n, np.uint64)
+        wo = (np.arange(ns) * words).astype(np.uint64)
+        seed_bits = n + m - 1
+        seed = to_dev(uniform_bits(seed_bits, m))
+        args = (to_dev(sub), sub.size, to_dev(lens), to_dev(wo), ns, seed,
+                seed_bits, m)
+        kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m)
+        out, tot, st = ctx.hash_batch(*args, kernel=ssbh.K_AUTO, **kw)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        assert ctx.last_schedule().startswith("fft") == want_fft
+        ref, tot2, st2 = ctx.hash_batch(*args, kernel=ssbh.K_VALU, **kw)
+        torch.cuda.synchronize()
+        assert int(st2.item()) == 0 and int(tot.item()) == int(tot2.item())
+        assert np.array_equal(to_host(out), to_host(ref))
+    finally:
+        ctx.close()

@@ -77,3 +77,27 @@ def test_explicit_paths_match_oracle(ctx, orc, path):
     assert np.array_equal(to_host(ln)[:ns], oln)
     got = to_host(sub)[: osub.size]
     assert np.array_equal(got, osub), first_diff(got, osub)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_explicit_concentrated_assignment(ctx, orc, path):
+    """Every round of whole segments in one sub-block (the largest per-quarter
+    counts the scatter sees), the rest spread over a few sub-blocks."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    n, ns = (1 << 20) + 333, 2048
+    a = bernoulli_bits(n, 0.5, 9)
+    v = np.zeros(n, dtype=np.uint32)
+    v[n // 2:] = (np.arange(n - n // 2) % 3 + 2045).astype(np.uint32)
+    ctx.set_sample_path(path)
+    try:
+        sub, ln, wo, st = ctx.sample(to_dev(a), n, ns, ssbh.SAMPLE_EXPLICIT,
+                                     assign=to_dev_u32(v))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_sample_path(0)
+    assert int(st.item()) == 0
+    osub, oln, owo, _ = orc.sample(a, n, ns, orc.SAMPLE_EXPLICIT, assign=v)
+    assert np.array_equal(to_host(ln)[:ns], oln)
+    got = to_host(sub)[: osub.size]
+    assert np.array_equal(got, osub), first_diff(got, osub)
