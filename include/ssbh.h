@@ -89,6 +89,8 @@ enum {
 
 /* Limits of this build. */
 #define SSBH_MAX_SUB_LDS 16384u   /* n_sub limit of the i.i.d./explicit modes */
+#define SSBH_MAX_SAMPLE_BITS 4293918720ull  /* 2^32 - 2^20: n_bits limit of one
+                                               sampling call (32-bit indices) */
 
 /* ------------------------------------------------------------- context --- */
 
@@ -140,7 +142,8 @@ int ssbh_num_cus(const ssbh_ctx *ctx);
  *  d_word_off    output W_j = sum_{k<j} ceil(n_k/64) (n_sub uint64).
  *  d_status      device int32, overwritten with 0 or an error code.
  *  stream        hipStream_t.
- * n_bits = 0 gives n_sub empty sub-blocks. */
+ * n_bits = 0 gives n_sub empty sub-blocks; n_bits above SSBH_MAX_SAMPLE_BITS
+ * returns SSBH_E_UNSUPPORTED. */
 ssbh_status ssbh_sample(ssbh_ctx *ctx, const uint64_t *d_in, uint64_t n_bits,
                         uint32_t n_sub, uint32_t mode, uint64_t sample_key,
                         const uint32_t *d_assign, uint64_t l_ub,
@@ -284,7 +287,7 @@ typedef struct {
                                 ssbh_poll returns a terminal status;
                                 0: host memory (pinned for an overlapped
                                 copy), copied at admission                   */
-    uint64_t n_bits;         /* N < 2^32                                     */
+    uint64_t n_bits;         /* N <= SSBH_MAX_SAMPLE_BITS                    */
     uint32_t n_sub;          /* N_S <= SSBH_MAX_SUB_LDS                      */
     uint64_t sample_key;     /* key of the V_i draws                         */
     uint64_t l_ub;           /* L_S^UB (0 = library default above)           */
@@ -326,12 +329,15 @@ ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
 
 /* Autotuner: run ssbh_hash_batch on the given (real) arguments once per
  * candidate kernel and schedule (bit-sliced VALU schedules; int8 matrix-core
- * schedules when the seed is shared), `reps` timed runs each with HIP events,
+ * schedules and FFT chunk sizes when the seed is shared), `reps` timed runs
+ * each with HIP events,
  * and remember the fastest for the shape bucket of these arguments (seed
  * sharing, log2 of n_sub, m_cap and mean sub-block words).  Later calls with
  * kernel = SSBH_K_AUTO in the same bucket use it; without a tuned entry AUTO
- * picks the matrix cores for a shared seed and n_sub >= 64, else the VALU
- * kernel.  Blocks until the stream is idle; d_out holds a valid result
+ * picks, for a shared seed, the FFT when (seed_bits + 1 - m_cap) * m_cap >=
+ * 1024 L log2 L (L the transform length, the quadratic work well above the
+ * transform's), else the matrix cores when n_sub >= 64; the VALU kernel in
+ * every other case.  Blocks until the stream is idle; d_out holds a valid result
  * afterwards.  If report is non-null, a text table of the timings is written
  * (truncated to report_len bytes). */
 ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,

@@ -1,20 +1,21 @@
 // Sampling (Sec. III.B step 1) and the abort rule (Sec. III.B step 2,
 // Sec. III.D) on gfx950.
 //
-// i.i.d. / explicit modes: the input is cut into segments of seg_bits bits,
-// one wavefront per segment.
-//   k_hist     V_i for every bit of the segment (recomputed from the
-//              counter-based generator, never stored), LDS histogram ->
-//              counts[seg][j]; also clears the sub-block buffer.
+// i.i.d. / explicit modes: the input is cut into segments of seg_bits bits.
+//   k_hist_q   (default) one workgroup per segment: V_i for every bit
+//              (recomputed from the counter-based generator, never stored),
+//              LDS histograms per quarter -> counts[seg][j] and the quarter
+//              counts; also clears the sub-block buffer.
+//   k_hist     one wavefront per segment, counts[seg][j] only (fallback).
 //   k_scan_*   column scans of counts over segments -> offs[seg][j] (where the
 //              segment's run of sub-block j starts), n_j, W_j, max n_j, abort.
-//   k_scatter  V_i again; a stable rank inside every 64-bit step from a
-//              ballot-based match of equal V_i; the bits are ORed into an LDS
-//              image of the segment sorted by sub-block (stable), then every
-//              run is copied to its place in sub-block j: whole 64-bit words
-//              by plain stores, the two partial end words by atomic OR (they
-//              are shared with the neighbouring segments' runs).  OR into a
-//              zeroed buffer is order independent, so the result is
+//   k_scatter_wg (default), k_scatter_tab, k_scatter: V_i again; a stable
+//              rank of each bit among equal V_i; the bits are ORed into an
+//              LDS image of the segment sorted by sub-block (stable), then
+//              every run is copied to its place in sub-block j: whole 64-bit
+//              words by plain stores, the two partial end words by atomic OR
+//              (they are shared with the neighbouring segments' runs).  OR
+//              into a zeroed buffer is order independent, so the result is
 //              bit-identical for every schedule.
 // Sifting (Sec. III.B step 2): with keep flags, V_i is still drawn for every
 // round (the draws do not depend on the flags) but only rounds with keep_i = 1
@@ -30,6 +31,7 @@ namespace ssbh {
 namespace {
 
 constexpr uint32_t kSegChunk = 64;   // segments per partial-sum chunk
+constexpr uint64_t kWgMaxSeg = 65024;  // workgroup scatter: 16-bit positions
 
 struct SampleArgs {
     const uint64_t *in;
@@ -126,31 +128,37 @@ __global__ __launch_bounds__(256) void k_hist_q(SampleArgs a) {
     uint32_t *hist = lds;           // [4][ns]
     for (uint32_t k = t; k < 4 * ns; k += 256) hist[k] = 0u;
     __syncthreads();
-    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
-    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
-    const uint64_t qlen = a.seg_bits / 4;               // multiple of 128
-    const uint64_t qa = i0 + (uint64_t)w * qlen;
-    const uint64_t qb = min(qa + qlen, i1);
+    const uint32_t sb = (uint32_t)a.seg_bits;
+    const uint32_t i0 = seg * sb;
+    const uint32_t i1 = min(i0 + sb, (uint32_t)a.n);   // n <= 2^32 - 2^20
+    const uint32_t qlen = sb / 4;                       // multiple of 128
+    const uint32_t qa = i0 + (uint32_t)w * qlen;
+    const uint32_t qb = min(qa + qlen, i1);
+    const uint32_t nw_in = (uint32_t)((a.n + 63) / 64);
+    const uint32_t lane2 = 2u * (uint32_t)lane, sh = lane2 & 63u;
     uint32_t *h = hist + (uint32_t)w * ns;
     bool bad = false;
-    for (uint64_t base = qa; base < qb; base += 128) {
-        const uint64_t iA = base + 2 * (uint64_t)lane, iB = iA + 1;
+    for (uint32_t base = qa; base < qb; base += 128) {
+        const uint32_t iA = base + lane2, iB = iA + 1;
         uint32_t vA, vB;
         if constexpr (EXPLICIT) {
             vA = iA < qb ? a.assign[iA] : 0u;
             vB = iB < qb ? a.assign[iB] : 0u;
         } else {
-            const uint64_t r = splitmix64_at(a.key, (base >> 1) + (uint64_t)lane);
+            const uint64_t r = splitmix64_at(a.key, (uint64_t)((base >> 1) + (uint32_t)lane));
             vA = __umulhi((uint32_t)r, ns);
             vB = __umulhi((uint32_t)(r >> 32), ns);
         }
+        uint32_t kb = 3u;
+        if (a.keep)
+            kb = (uint32_t)(a.keep[min((base >> 6) + (uint32_t)(lane >> 5), nw_in - 1)] >> sh);
         if (iA < qb) {
             if (vA >= ns) bad = true;
-            else if (kept(a, iA)) atomicAdd(&h[vA], 1u);
+            else if (kb & 1u) atomicAdd(&h[vA], 1u);
         }
         if (iB < qb) {
             if (vB >= ns) bad = true;
-            else if (kept(a, iB)) atomicAdd(&h[vB], 1u);
+            else if (kb & 2u) atomicAdd(&h[vB], 1u);
         }
     }
     if (bad) atomicExch(a.status, (int32_t)SSBH_E_INVAL);
@@ -438,32 +446,11 @@ __global__ __launch_bounds__(64) void k_scatter_tab(SampleArgs a) {
     flush_runs(a, seg, cursor, stage, lane);
 }
 
-// V for the 128 rounds base .. base+127 (base even): lane l evaluates the
-// generator once, for the round pair base/2 + l, and the two halves are
-// handed to the lanes that own those rounds (vA: round base + l, vB: round
-// base + 64 + l).
-template <bool EXPLICIT>
-__device__ __forceinline__ void sample_v2(const SampleArgs &a, uint64_t base,
-                                          int lane, uint32_t &vA, uint32_t &vB) {
-    if constexpr (EXPLICIT) {
-        const uint64_t iA = base + lane, iB = base + 64 + lane;
-        vA = iA < a.n ? a.assign[iA] : 0u;
-        vB = iB < a.n ? a.assign[iB] : 0u;
-    } else {
-        const uint64_t r = splitmix64_at(a.key, (base >> 1) + (uint64_t)lane);
-        const int lo = (int)(uint32_t)r, hi = (int)(uint32_t)(r >> 32);
-        const int sa = lane >> 1, sb = 32 + (lane >> 1);
-        const uint32_t loA = (uint32_t)__shfl(lo, sa, 64), hiA = (uint32_t)__shfl(hi, sa, 64);
-        const uint32_t loB = (uint32_t)__shfl(lo, sb, 64), hiB = (uint32_t)__shfl(hi, sb, 64);
-        vA = __umulhi((lane & 1) ? hiA : loA, a.ns);
-        vB = __umulhi((lane & 1) ? hiB : loB, a.ns);
-    }
-}
-
 // Copy every run of the segment image to its sub-block (as flush_runs, with
 // `nt` threads): ends[j] is the end of run j, run j starts at ends[j-1].
+template <typename C>
 __device__ __forceinline__ void flush_runs_t(const SampleArgs &a, uint32_t seg,
-                                             const uint32_t *ends,
+                                             const C *ends,
                                              const uint32_t *stage, int t,
                                              int nt) {
     const uint32_t *off = a.offs + (uint64_t)seg * a.ns;
@@ -487,40 +474,62 @@ __device__ __forceinline__ void flush_runs_t(const SampleArgs &a, uint32_t seg,
     }
 }
 
-// Scatter with one workgroup of 4 wavefronts per segment; wavefront w takes
-// the w-th quarter of the segment.
+// popcount(m & lanes below this one) + acc.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t acc) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
+}
+
+// m & ~(bal ^ e) on both halves: keeps the lanes whose bit equals this
+// lane's bit (e = 0 or ~0, bal = ballot of that bit).
+__device__ __forceinline__ uint64_t narrow(uint64_t m, uint64_t bal, uint32_t e) {
+    const uint32_t lo = (uint32_t)m & ~((uint32_t)bal ^ e);
+    const uint32_t hi = (uint32_t)(m >> 32) & ~((uint32_t)(bal >> 32) ^ e);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Scatter with one workgroup of 4 wavefronts per segment (at most 65024
+// rounds, so positions fit 16-bit cursors); wavefront w takes the w-th
+// quarter of the segment.
 //   1. the segment totals and quarter counts of k_hist_q give each
 //      wavefront's first position of every run in the LDS image of the
 //      segment (sorted by sub-block, stable: quarter w comes after quarters
 //      < w);
-//   2. every wavefront ranks equal V_i inside each 64-round step: a 256-slot
-//      match table (OR of lane bits at slot V mod 256, read back) narrowed by
-//      ballots on the bits of V above 8, then advances its cursors and ORs
-//      the bits into the image;
+//   2. the wavefront walks its quarter in blocks of 128 rounds, lane l
+//      holding rounds 2l ("even") and 2l + 1 ("odd") from the low and high
+//      halves of one SplitMix64 output.  A 256-slot match table per
+//      wavefront (slot V mod 256 holds the mask of even lanes and the mask of
+//      odd lanes that ORed their bit there), narrowed by ballots on the HB
+//      bits of V above 8, gives for each of the lane's two values the even
+//      and the odd lanes holding it; the rank of a round among equal values
+//      of the block counts the even and odd rounds before it.  Each value's
+//      cursor is read once per block and advanced by the lane holding its
+//      last round; the bits are ORed into the image;
 //   3. all runs are copied out as in flush_runs.
-// LDS: 4 cursor tables (4 n_sub words), 4 match tables (8 KiB), the image.
-template <bool EXPLICIT>
+// Round indices fit 32 bits (n <= 2^32 - 2^20, so index + segment does too).
+// LDS: 4 match tables (16 KiB), 4 cursor tables (4 n_sub uint16), the image.
+template <bool EXPLICIT, int HB>
 __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
-    extern __shared__ __align__(8) uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t wsum[4];
     if (*a.status) return;
     const uint32_t ns = a.ns;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    uint32_t *cur = lds;                                            // [4][ns]
-    uint64_t *tab = reinterpret_cast<uint64_t *>(lds + ((4 * ns + 1) & ~1u));
-    uint32_t *stage = reinterpret_cast<uint32_t *>(tab + 4 * 256);
+    uint64_t *tab = reinterpret_cast<uint64_t *>(lds);              // [4][256][2]
+    uint16_t *cur = reinterpret_cast<uint16_t *>(tab + 4 * 256 * 2);  // [4][ns]
+    uint32_t *stage = reinterpret_cast<uint32_t *>(cur + 4 * ns);
     const uint32_t seg = blockIdx.x;
     const uint32_t nsw = (uint32_t)(a.seg_bits / 32) + 4;
-    for (uint32_t k = t; k < 4 * 256; k += 256) tab[k] = 0ull;
+    for (uint32_t k = t; k < 4 * 256 * 2; k += 256) tab[k] = 0ull;
     for (uint32_t k = t; k < nsw; k += 256) stage[k] = 0u;
-    __syncthreads();
 
-    const uint64_t i0 = (uint64_t)seg * a.seg_bits;
-    const uint64_t i1 = min(i0 + a.seg_bits, a.n);
-    const uint64_t qlen = a.seg_bits / 4;               // multiple of 128
-    const uint64_t qa = i0 + (uint64_t)w * qlen;
-    const uint64_t qb = min(qa + qlen, i1);
-    uint32_t *mc = cur + (uint32_t)w * ns;
+    const uint32_t n32 = (uint32_t)a.n;
+    const uint32_t sb = (uint32_t)a.seg_bits;
+    const uint32_t i0 = seg * sb;
+    const uint32_t i1 = min(i0 + sb, n32);
+    const uint32_t qlen = sb / 4;                       // multiple of 128
+    const uint32_t qa = i0 + (uint32_t)w * qlen;
+    const uint32_t qb = min(qa + qlen, i1);
 
     // 1. Run starts: exclusive scan over sub-blocks of the segment totals
     //    (from the histogram), then each quarter's offset inside its run from
@@ -543,51 +552,100 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
         for (int k = 0; k < w; ++k) run += wsum[k];
         for (uint32_t v = v0; v < v1; ++v) {
             const uint32_t c0 = q[v], c1 = q[ns + v], c2 = q[2 * ns + v];
-            cur[v] = run;
-            cur[ns + v] = run + c0;
-            cur[2 * ns + v] = run + c0 + c1;
-            cur[3 * ns + v] = run + c0 + c1 + c2;
+            cur[v] = (uint16_t)run;
+            cur[ns + v] = (uint16_t)(run + c0);
+            cur[2 * ns + v] = (uint16_t)(run + c0 + c1);
+            cur[3 * ns + v] = (uint16_t)(run + c0 + c1 + c2);
             run += cnt[v];
         }
     }
     __syncthreads();
 
-    // 2. Stable placement.
-    uint64_t *mt = tab + (uint32_t)w * 256;
+    // 2. Stable placement, 128 rounds per step.
+    uint64_t *mt = tab + (uint32_t)w * 512;             // [slot][even, odd]
+    uint16_t *mc = cur + (uint32_t)w * ns;
     const uint64_t me = 1ull << lane;
-    const uint64_t below = me - 1ull;
-    const uint32_t hb = a.vbits > 8 ? a.vbits - 8 : 0;
-    const uint64_t nw_in = (a.n + 63) / 64;
-    auto place = [&](uint32_t v, bool valid, bool bit) {
-        const uint32_t slot = v & 255u;
-        if (valid) atomicOr((unsigned long long *)&mt[slot], (unsigned long long)me);
-        __builtin_amdgcn_wave_barrier();
-        uint64_t m = valid ? mt[slot] : 0ull;
-        for (uint32_t b = 0; b < hb; ++b) {
-            const bool hbit = (v >> (8 + b)) & 1u;
-            const uint64_t bal = ballot64(valid && hbit);
-            m &= hbit ? bal : ~bal;
+    const uint32_t nw_in = (n32 + 63) / 64;
+    const uint32_t lane2 = 2u * (uint32_t)lane;
+    const uint32_t sh = lane2 & 63u;
+    // Input and flag words of the next block are loaded one block ahead.
+    const uint32_t wl = (uint32_t)(lane >> 5);
+    uint64_t wd_next = 0ull, kw_next = ~0ull;
+    if (qa < qb) {
+        const uint32_t wi = min((qa >> 6) + wl, nw_in - 1);
+        wd_next = a.in[wi];
+        if (a.keep) kw_next = a.keep[wi];
+    }
+    for (uint32_t base = qa; base < qb; base += 128) {
+        const uint64_t wd = wd_next, kw = kw_next;
+        if (base + 128 < qb) {
+            const uint32_t wi = min(((base + 128) >> 6) + wl, nw_in - 1);
+            wd_next = a.in[wi];
+            if (a.keep) kw_next = a.keep[wi];
         }
-        if (valid) {
-            const uint32_t base = mc[v];
-            const uint32_t pos = base + (uint32_t)__popcll(m & below);
-            if (63 - __clzll((long long)m) == lane) {
-                mc[v] = base + (uint32_t)__popcll(m);
-                mt[slot] = 0ull;
+        const uint32_t iE = base + lane2, iO = iE + 1;
+        uint32_t vE, vO;
+        if constexpr (EXPLICIT) {
+            vE = iE < qb ? a.assign[iE] : 0u;
+            vO = iO < qb ? a.assign[iO] : 0u;
+        } else {
+            const uint64_t r = splitmix64_at(a.key, (uint64_t)((base >> 1) + (uint32_t)lane));
+            vE = __umulhi((uint32_t)r, ns);
+            vO = __umulhi((uint32_t)(r >> 32), ns);
+        }
+        bool okE = iE < qb, okO = iO < qb;
+        if constexpr (EXPLICIT) {
+            okE = okE && vE < ns;
+            okO = okO && vO < ns;
+        }
+        const uint32_t kb = (uint32_t)(kw >> sh);      // all ones without flags
+        okE = okE && (kb & 1u);
+        okO = okO && (kb & 2u);
+        const uint32_t sE = vE & 255u, sO = vO & 255u;
+        if (okE) atomicOr((unsigned long long *)&mt[2 * sE], (unsigned long long)me);
+        if (okO) atomicOr((unsigned long long *)&mt[2 * sO + 1], (unsigned long long)me);
+        __builtin_amdgcn_wave_barrier();
+        const ulonglong2 pE = *reinterpret_cast<const ulonglong2 *>(&mt[2 * sE]);
+        const ulonglong2 pO = *reinterpret_cast<const ulonglong2 *>(&mt[2 * sO]);
+        uint64_t mEE = okE ? pE.x : 0ull, mEO = okE ? pE.y : 0ull;
+        uint64_t mOE = okO ? pO.x : 0ull, mOO = okO ? pO.y : 0ull;
+#pragma unroll
+        for (int b = 0; b < HB; ++b) {
+            const uint32_t eE = (uint32_t)__builtin_amdgcn_sbfe((int)vE, 8 + b, 1);
+            const uint32_t eO = (uint32_t)__builtin_amdgcn_sbfe((int)vO, 8 + b, 1);
+            const uint64_t balE = ballot64(eE != 0u), balO = ballot64(eO != 0u);
+            mEE = narrow(mEE, balE, eE);
+            mEO = narrow(mEO, balO, eE);
+            mOE = narrow(mOE, balE, eO);
+            mOO = narrow(mOO, balO, eO);
+        }
+        const uint32_t cE = mc[okE ? vE : 0u];
+        const uint32_t cO = mc[okO ? vO : 0u];
+        __builtin_amdgcn_wave_barrier();
+        // Even round: rank among equal values = even and odd lanes below.
+        const uint32_t rEE = rank_below(mEE, 0u), rEO = rank_below(mEO, 0u);
+        const uint32_t tEE = (uint32_t)__popcll(mEE), tEO = (uint32_t)__popcll(mEO);
+        // Odd round: even lanes up to and including this one, odd lanes below.
+        const uint32_t rOE = rank_below(mOE, (okE && vE == vO) ? 1u : 0u);
+        const uint32_t rOO = rank_below(mOO, 0u);
+        const uint32_t tOE = (uint32_t)__popcll(mOE), tOO = (uint32_t)__popcll(mOO);
+        if (okE) {
+            const uint32_t pos = cE + rEE + rEO;
+            if (rEE + 1u == tEE) {                      // last even lane of V
+                mt[2 * sE] = 0ull;
+                if (rEO == tEO) mc[vE] = (uint16_t)(cE + tEE + tEO);
             }
-            if (bit) atomicOr(&stage[pos >> 5], 1u << (pos & 31));
+            if ((wd >> sh) & 1ull) atomicOr(&stage[pos >> 5], 1u << (pos & 31));
+        }
+        if (okO) {
+            const uint32_t pos = cO + rOE + rOO;
+            if (rOO + 1u == tOO) {                      // last odd lane of V
+                mt[2 * sO + 1] = 0ull;
+                if (rOE == tOE) mc[vO] = (uint16_t)(cO + tOE + tOO);
+            }
+            if ((wd >> sh) & 2ull) atomicOr(&stage[pos >> 5], 1u << (pos & 31));
         }
         __builtin_amdgcn_wave_barrier();
-    };
-    for (uint64_t base = qa; base < qb; base += 128) {
-        uint32_t vA, vB;
-        sample_v2<EXPLICIT>(a, base, lane, vA, vB);
-        const uint64_t wi = base >> 6;
-        const uint64_t wA = wi < nw_in ? a.in[wi] : 0ull;
-        const uint64_t wB = wi + 1 < nw_in ? a.in[wi + 1] : 0ull;
-        const uint64_t iA = base + lane, iB = iA + 64;
-        place(vA, iA < qb && vA < ns && kept(a, iA), (wA >> lane) & 1ull);
-        place(vB, iB < qb && vB < ns && kept(a, iB), (wB >> lane) & 1ull);
     }
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __syncthreads();
@@ -651,12 +709,36 @@ uint32_t ceil_log2(uint32_t x) {
 // Segment size: about 32 bits per sub-block per segment (so runs are a few
 // words long), at least 2^14 bits, LDS image at most 32 KiB.
 // Segment length: about 32 rounds per sub-block, 2^14 .. 2^18 - 512 rounds
-// (a quarter stays below 2^16 rounds), a multiple of 512.
+// (a quarter stays below 2^16 rounds), a multiple of 512; at most 65024
+// while 32 n_sub <= 2^16, so the workgroup scatter's positions fit 16 bits.
 static uint64_t segment_bits(uint32_t ns) {
     uint64_t seg = 32ull * ns;
     seg = std::max<uint64_t>(seg, 1ull << 14);
     seg = std::min<uint64_t>(seg, (1ull << 18) - 512);
-    return (seg + 511) / 512 * 512;
+    seg = (seg + 511) / 512 * 512;
+    if (seg > kWgMaxSeg && seg <= (1ull << 16)) seg = kWgMaxSeg;
+    return seg;
+}
+
+template <bool EX>
+void launch_scatter_wg_t(int hb, const SampleArgs &a, size_t lds,
+                         hipStream_t stream) {
+    const dim3 g(a.nseg), b(256);
+    switch (hb) {
+    case 0: hipLaunchKernelGGL((k_scatter_wg<EX, 0>), g, b, lds, stream, a); break;
+    case 1: hipLaunchKernelGGL((k_scatter_wg<EX, 1>), g, b, lds, stream, a); break;
+    case 2: hipLaunchKernelGGL((k_scatter_wg<EX, 2>), g, b, lds, stream, a); break;
+    case 3: hipLaunchKernelGGL((k_scatter_wg<EX, 3>), g, b, lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_scatter_wg<EX, 4>), g, b, lds, stream, a); break;
+    }
+}
+
+// The workgroup scatter for ceil(log2 n_sub) - 8 = hb high bits (n_sub <=
+// 4096 on this path, so hb <= 4).
+void launch_scatter_wg(bool ex, int hb, const SampleArgs &a, size_t lds,
+                       hipStream_t stream) {
+    if (ex) launch_scatter_wg_t<true>(hb, a, lds, stream);
+    else launch_scatter_wg_t<false>(hb, a, lds, stream);
 }
 
 ScratchSizes sample_scratch(uint64_t n, uint32_t ns, uint32_t mode) {
@@ -694,8 +776,8 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     if (!d_sub || !d_len || !d_woff || !d_status)
         SSBH_INVAL("d_sub, d_len, d_word_off and d_status must be non-null");
     if (n && !d_in) SSBH_INVAL("d_in is null");
-    if (n >= (1ull << 32)) {
-        set_error("n_bits must be below 2^32");
+    if (n > SSBH_MAX_SAMPLE_BITS) {
+        set_error("n_bits must be at most %llu", (unsigned long long)SSBH_MAX_SAMPLE_BITS);
         return SSBH_E_UNSUPPORTED;
     }
     (void)hipGetLastError();   // clear errors left by earlier calls
@@ -767,9 +849,10 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     const size_t scat_lds = (size_t)ns * 4 + ((size_t)(seg / 32) + 4) * 4;
     const size_t tab_lds = scat_lds + (size_t)ns * 8;
     const bool use_tab = tab_lds <= 48 * 1024;
-    const size_t wg_lds = (size_t)((4 * ns + 1) & ~1u) * 4 + 4 * 256 * 8 +
+    const size_t wg_lds = (size_t)4 * 2 * 256 * 8 + (size_t)4 * ns * 2 +
                           ((size_t)(seg / 32) + 4) * 4;
-    const bool use_wg = ns >= 2 && wg_lds <= 64 * 1024 && ctx->forced_scatter != 1;
+    const bool use_wg = ns >= 2 && ns <= 4096 && seg <= kWgMaxSeg &&
+                        wg_lds <= 64 * 1024 && ctx->forced_scatter != 1;
     {
         const void *kh = ex ? (const void *)k_hist<true> : (const void *)k_hist<false>;
         const void *ksc = ex ? (const void *)k_scatter<true>
@@ -777,10 +860,8 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
         if ((st = ensure_dynamic_lds(kh, hist_lds)) != SSBH_OK) return st;
         const void *kt = ex ? (const void *)k_scatter_tab<true>
                             : (const void *)k_scatter_tab<false>;
-        const void *kw = ex ? (const void *)k_scatter_wg<true>
-                            : (const void *)k_scatter_wg<false>;
         if (use_wg) {
-            if ((st = ensure_dynamic_lds(kw, wg_lds)) != SSBH_OK) return st;
+            // at most 64 KiB: no opt-in needed
         } else if (use_tab) {
             if ((st = ensure_dynamic_lds(kt, tab_lds)) != SSBH_OK) return st;
         } else if ((st = ensure_dynamic_lds(ksc, scat_lds)) != SSBH_OK) {
@@ -822,12 +903,8 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     hipLaunchKernelGGL(k_scan_words, dim3(1), dim3(1024), 0, stream, a);
     if (a.nseg) {
         TimedLaunch timed(ws.timer, "k_scatter", stream);
-        if (use_wg && ex)
-            hipLaunchKernelGGL(k_scatter_wg<true>, dim3(a.nseg), dim3(256),
-                               wg_lds, stream, a);
-        else if (use_wg)
-            hipLaunchKernelGGL(k_scatter_wg<false>, dim3(a.nseg), dim3(256),
-                               wg_lds, stream, a);
+        if (use_wg)
+            launch_scatter_wg(ex, a.vbits > 8 ? a.vbits - 8 : 0, a, wg_lds, stream);
         else if (use_tab && ex)
             hipLaunchKernelGGL(k_scatter_tab<true>, dim3(a.nseg), dim3(64),
                                tab_lds, stream, a);

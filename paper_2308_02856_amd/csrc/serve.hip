@@ -148,7 +148,8 @@ static ssbh_status plan_job(const ssbh_ctx *ctx, const ssbh_job &j,
                             JobPlan &p) {
     if (j.n_sub == 0 || j.n_sub > SSBH_MAX_SUB_LDS)
         SSBH_INVAL("n_sub must be in [1, %u]", SSBH_MAX_SUB_LDS);
-    if (j.n_bits >= (1ull << 32)) SSBH_INVAL("n_bits must be below 2^32");
+    if (j.n_bits > SSBH_MAX_SAMPLE_BITS)
+        SSBH_INVAL("n_bits must be at most %llu", (unsigned long long)SSBH_MAX_SAMPLE_BITS);
     if (j.n_bits && !j.in) SSBH_INVAL("job input is null");
     if (!j.out) SSBH_INVAL("job output is null");
     if (j.out_rule == SSBH_OUT_RATIO) {

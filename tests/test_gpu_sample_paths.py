@@ -101,3 +101,14 @@ def test_explicit_concentrated_assignment(ctx, orc, path):
     assert np.array_equal(to_host(ln)[:ns], oln)
     got = to_host(sub)[: osub.size]
     assert np.array_equal(got, osub), first_diff(got, osub)
+
+
+def test_rejects_n_bits_above_limit(ctx):
+    """n_bits past 2^32 - 2^20 (32-bit round indices) is refused on the host,
+    before any launch."""
+    from paper_2308_02856_amd import ssbh
+    a = to_dev(np.zeros(4, dtype=np.uint64))
+    with pytest.raises(ssbh.SsbhError) as e:
+        ctx.sample(a, (1 << 32) - (1 << 20) + 1, 16, ssbh.SAMPLE_IID, key=1,
+                   sub_capacity=8)
+    assert e.value.status == ssbh.E_UNSUPPORTED
