@@ -92,6 +92,8 @@ __device__ __forceinline__ double2 rot90(double2 a) {
     return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
 
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
 template <bool INV>
 __device__ __forceinline__ void dft2(double2 (&v)[2]) {
     const double2 a = v[0], b = v[1];
@@ -157,10 +159,59 @@ __device__ __forceinline__ void dft3(double2 (&v)[3]) {
 }
 
 template <int R, bool INV>
+__device__ __forceinline__ void dftR(double2 (&v)[R]);
+
+// x * w_12^q (q taken mod 12; w_12 = exp(-2 pi i / 12), conjugated for the
+// inverse).  q is a compile-time constant after unrolling, so the trivial
+// cases cost nothing and the others are one complex multiply by constants.
+template <bool INV>
+__device__ __forceinline__ double2 mul_w12(double2 x, int q) {
+    const double c = 0.86602540378443864676;   // cos 30 deg
+    q %= 12;
+    if (q == 0) return x;
+    if (q == 3) return rot90<INV>(x);
+    if (q == 6) return make_double2(-x.x, -x.y);
+    if (q == 9) return rot90<!INV>(x);
+    const double cs[12] = {1, c, 0.5, 0, -0.5, -c, -1, -c, -0.5, 0, 0.5, c};
+    const double sn[12] = {0, 0.5, c, 1, c, 0.5, 0, -0.5, -c, -1, -c, -0.5};
+    return cmul(x, make_double2(cs[q], INV ? sn[q] : -sn[q]));
+}
+
+// R1 * R2-point DFT (R1 R2 divides 12), natural order in and out, by one
+// Cooley-Tukey split: R2 DFTs of R1 points on the stride-R2 subsequences,
+// the constant twiddles w_R^(n2 k1), then R1 DFTs of R2 points.
+template <int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_ct(double2 (&v)[R1 * R2]) {
+    constexpr int R = R1 * R2;
+    double2 u[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        double2 t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
+        dftR<R1, INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1)
+            u[n2][k1] = mul_w12<INV>(t[k1], n2 * k1 * (12 / R));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        double2 t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) t[n2] = u[n2][k1];
+        dftR<R2, INV>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+}
+
+template <int R, bool INV>
 __device__ __forceinline__ void dftR(double2 (&v)[R]) {
     if constexpr (R == 8) dft8<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
     else if constexpr (R == 3) dft3<INV>(v);
+    else if constexpr (R == 6) dft_ct<2, 3, INV>(v);
+    else if constexpr (R == 12) dft_ct<4, 3, INV>(v);
     else dft2<INV>(v);
 }
 
@@ -175,27 +226,22 @@ __device__ __forceinline__ int lds_addr(int f, int e) {
 }
 
 // Twiddles w^r, r < R, of w = w_N^base from the table of w_N^k (conjugated
-// for the inverse): w, w^2, w^4 from the table, the rest by products.
+// for the inverse): the powers w^(2^b) from the table, every other power as
+// a product of them (r = 2^b + rest: w^r = w^(2^b) w^rest).
 template <int R, bool INV>
 __device__ __forceinline__ void twiddle(double2 (&v)[R], int base,
                                         const double2 *tw) {
     auto ld = [&](int k) { double2 w = tw[k]; return INV ? conj2(w) : w; };
-    const double2 w1 = ld(base);
-    v[1] = cmul(v[1], w1);
-    if constexpr (R == 3) {
-        v[2] = cmul(v[2], ld(2 * base));
-    } else if constexpr (R >= 4) {
-        const double2 w2 = ld(2 * base);
-        const double2 w3 = cmul(w1, w2);
-        v[2] = cmul(v[2], w2);
-        v[3] = cmul(v[3], w3);
-        if constexpr (R == 8) {
-            const double2 w4 = ld(4 * base);
-            v[4] = cmul(v[4], w4);
-            v[5] = cmul(v[5], cmul(w4, w1));
-            v[6] = cmul(v[6], cmul(w4, w2));
-            v[7] = cmul(v[7], cmul(w4, w3));
-        }
+    double2 p2[4];
+#pragma unroll
+    for (int b = 0; (1 << b) < R; ++b) p2[b] = ld((1 << b) * base);
+    double2 wr[R];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const int hb = ilog2c(r);
+        const int rest = r - (1 << hb);
+        wr[r] = rest ? cmul(p2[hb], wr[rest]) : p2[hb];
+        v[r] = cmul(v[r], wr[r]);
     }
 }
 
@@ -236,20 +282,17 @@ __device__ __forceinline__ void fft_stage(int span, const double2 *tw, Ld ld,
     if (END) __syncthreads();
 }
 
-constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
-
 // Stage radices of an N-point FFT, N = 2^a or 3 * 2^a: radix 8 while it
-// divides the power of two, then one radix 2 or 4, then one radix 3.
+// divides the power of two; the remaining 2 or 4 is merged with the 3 into
+// one radix-6 or radix-12 stage, or is a stage of its own when there is no 3.
 constexpr int two_part(int n) { return n % 3 == 0 ? n / 3 : n; }
+constexpr int pow2_bits(int n) { return ilog2c(two_part(n)); }
 constexpr int num_stages(int n) {
-    return ilog2c(two_part(n)) / 3 + (ilog2c(two_part(n)) % 3 ? 1 : 0) +
-           (n % 3 == 0 ? 1 : 0);
+    return pow2_bits(n) / 3 + (n % 3 == 0 ? 1 : (pow2_bits(n) % 3 ? 1 : 0));
 }
 constexpr int radix_of(int n, int s) {
-    return s < ilog2c(two_part(n)) / 3 ? 8
-         : (s == ilog2c(two_part(n)) / 3 && ilog2c(two_part(n)) % 3)
-               ? (ilog2c(two_part(n)) % 3 == 1 ? 2 : 4)
-               : 3;
+    return s < pow2_bits(n) / 3 ? 8
+         : (n % 3 == 0 ? 3 : 1) * (1 << (pow2_bits(n) % 3));
 }
 
 template <int N, int F, bool INV, int S, class Ld, class St, class LL, class LS>
