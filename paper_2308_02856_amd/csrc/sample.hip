@@ -38,6 +38,7 @@ struct SampleArgs {
     uint64_t n;
     uint32_t ns;
     uint32_t vbits;          // ceil(log2(ns))
+    uint32_t vshift;         // 32 - log2(ns) when ns is a power of two >= 2
     uint64_t key;
     const uint32_t *assign;  // explicit mode
     const uint64_t *keep;    // sifting flags (nullptr = keep every round)
@@ -65,6 +66,13 @@ __device__ __forceinline__ uint32_t sample_v(const SampleArgs &a, uint64_t i) {
         const uint32_t u = (i & 1ull) ? (uint32_t)(r >> 32) : (uint32_t)r;
         return __umulhi(u, a.ns);   // floor(u * ns / 2^32)
     }
+}
+
+// V = floor(u * ns / 2^32); a shift when ns is a power of two (POW2).
+template <bool POW2>
+__device__ __forceinline__ uint32_t v_of(const SampleArgs &a, uint32_t u) {
+    if constexpr (POW2) return u >> a.vshift;
+    else return __umulhi(u, a.ns);
 }
 
 __global__ void k_init_status(int32_t *status) { *status = 0; }
@@ -113,7 +121,7 @@ __global__ __launch_bounds__(256) void k_hist(SampleArgs a) {
 // the segment's run.  Counting does not depend on the order of the rounds,
 // so lane l takes rounds 2l and 2l + 1 of every 128-round block from the low
 // and high halves of one SplitMix64 output.
-template <bool EXPLICIT>
+template <bool EXPLICIT, bool POW2>
 __global__ __launch_bounds__(256) void k_hist_q(SampleArgs a) {
     extern __shared__ uint32_t lds[];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -138,28 +146,32 @@ __global__ __launch_bounds__(256) void k_hist_q(SampleArgs a) {
     const uint32_t lane2 = 2u * (uint32_t)lane, sh = lane2 & 63u;
     uint32_t *h = hist + (uint32_t)w * ns;
     bool bad = false;
-    for (uint32_t base = qa; base < qb; base += 128) {
+    // SplitMix64 counter of output (base / 2 + lane): advances by 64 outputs
+    // per block of 128 rounds.
+    uint64_t z = a.key + ((uint64_t)((qa >> 1) + (uint32_t)lane) + 1ull) * kSplitMixGamma;
+    for (uint32_t base = qa; base < qb; base += 128, z += 64ull * kSplitMixGamma) {
         const uint32_t iA = base + lane2, iB = iA + 1;
         uint32_t vA, vB;
         if constexpr (EXPLICIT) {
             vA = iA < qb ? a.assign[iA] : 0u;
             vB = iB < qb ? a.assign[iB] : 0u;
         } else {
-            const uint64_t r = splitmix64_at(a.key, (uint64_t)((base >> 1) + (uint32_t)lane));
-            vA = __umulhi((uint32_t)r, ns);
-            vB = __umulhi((uint32_t)(r >> 32), ns);
+            const uint64_t r = splitmix64_mix(z);
+            vA = v_of<POW2>(a, (uint32_t)r);
+            vB = v_of<POW2>(a, (uint32_t)(r >> 32));
         }
         uint32_t kb = 3u;
         if (a.keep)
             kb = (uint32_t)(a.keep[min((base >> 6) + (uint32_t)(lane >> 5), nw_in - 1)] >> sh);
-        if (iA < qb) {
-            if (vA >= ns) bad = true;
-            else if (kb & 1u) atomicAdd(&h[vA], 1u);
+        bool okA = iA < qb && (kb & 1u), okB = iB < qb && (kb & 2u);
+        if constexpr (EXPLICIT) {
+            // Out-of-range V is an error even on a dropped (unkept) round.
+            bad = bad || (iA < qb && vA >= ns) || (iB < qb && vB >= ns);
+            okA = okA && vA < ns;
+            okB = okB && vB < ns;
         }
-        if (iB < qb) {
-            if (vB >= ns) bad = true;
-            else if (kb & 2u) atomicAdd(&h[vB], 1u);
-        }
+        if (okA) atomicAdd(&h[vA], 1u);
+        if (okB) atomicAdd(&h[vB], 1u);
     }
     if (bad) atomicExch(a.status, (int32_t)SSBH_E_INVAL);
     __syncthreads();
@@ -508,7 +520,7 @@ __device__ __forceinline__ uint64_t narrow(uint64_t m, uint64_t bal, uint32_t e)
 //   3. all runs are copied out as in flush_runs.
 // Round indices fit 32 bits (n <= 2^32 - 2^20, so index + segment does too).
 // LDS: 4 match tables (16 KiB), 4 cursor tables (4 n_sub uint16), the image.
-template <bool EXPLICIT, int HB>
+template <bool EXPLICIT, int HB, bool POW2>
 __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t wsum[4];
@@ -576,7 +588,9 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
         wd_next = a.in[wi];
         if (a.keep) kw_next = a.keep[wi];
     }
-    for (uint32_t base = qa; base < qb; base += 128) {
+    // SplitMix64 counter of output (base / 2 + lane), 64 outputs per block.
+    uint64_t z = a.key + ((uint64_t)((qa >> 1) + (uint32_t)lane) + 1ull) * kSplitMixGamma;
+    for (uint32_t base = qa; base < qb; base += 128, z += 64ull * kSplitMixGamma) {
         const uint64_t wd = wd_next, kw = kw_next;
         if (base + 128 < qb) {
             const uint32_t wi = min(((base + 128) >> 6) + wl, nw_in - 1);
@@ -589,9 +603,9 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
             vE = iE < qb ? a.assign[iE] : 0u;
             vO = iO < qb ? a.assign[iO] : 0u;
         } else {
-            const uint64_t r = splitmix64_at(a.key, (uint64_t)((base >> 1) + (uint32_t)lane));
-            vE = __umulhi((uint32_t)r, ns);
-            vO = __umulhi((uint32_t)(r >> 32), ns);
+            const uint64_t r = splitmix64_mix(z);
+            vE = v_of<POW2>(a, (uint32_t)r);
+            vO = v_of<POW2>(a, (uint32_t)(r >> 32));
         }
         bool okE = iE < qb, okO = iO < qb;
         if constexpr (EXPLICIT) {
@@ -720,25 +734,26 @@ static uint64_t segment_bits(uint32_t ns) {
     return seg;
 }
 
-template <bool EX>
+template <bool EX, bool P2>
 void launch_scatter_wg_t(int hb, const SampleArgs &a, size_t lds,
                          hipStream_t stream) {
     const dim3 g(a.nseg), b(256);
     switch (hb) {
-    case 0: hipLaunchKernelGGL((k_scatter_wg<EX, 0>), g, b, lds, stream, a); break;
-    case 1: hipLaunchKernelGGL((k_scatter_wg<EX, 1>), g, b, lds, stream, a); break;
-    case 2: hipLaunchKernelGGL((k_scatter_wg<EX, 2>), g, b, lds, stream, a); break;
-    case 3: hipLaunchKernelGGL((k_scatter_wg<EX, 3>), g, b, lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_scatter_wg<EX, 4>), g, b, lds, stream, a); break;
+    case 0: hipLaunchKernelGGL((k_scatter_wg<EX, 0, P2>), g, b, lds, stream, a); break;
+    case 1: hipLaunchKernelGGL((k_scatter_wg<EX, 1, P2>), g, b, lds, stream, a); break;
+    case 2: hipLaunchKernelGGL((k_scatter_wg<EX, 2, P2>), g, b, lds, stream, a); break;
+    case 3: hipLaunchKernelGGL((k_scatter_wg<EX, 3, P2>), g, b, lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_scatter_wg<EX, 4, P2>), g, b, lds, stream, a); break;
     }
 }
 
 // The workgroup scatter for ceil(log2 n_sub) - 8 = hb high bits (n_sub <=
-// 4096 on this path, so hb <= 4).
+// 4096 on this path, so hb <= 4); V by a shift when n_sub is a power of two.
 void launch_scatter_wg(bool ex, int hb, const SampleArgs &a, size_t lds,
                        hipStream_t stream) {
-    if (ex) launch_scatter_wg_t<true>(hb, a, lds, stream);
-    else launch_scatter_wg_t<false>(hb, a, lds, stream);
+    if (ex) launch_scatter_wg_t<true, false>(hb, a, lds, stream);
+    else if (a.vshift) launch_scatter_wg_t<false, true>(hb, a, lds, stream);
+    else launch_scatter_wg_t<false, false>(hb, a, lds, stream);
 }
 
 ScratchSizes sample_scratch(uint64_t n, uint32_t ns, uint32_t mode) {
@@ -823,6 +838,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
 
     SampleArgs a{};
     a.in = d_in; a.n = n; a.ns = ns; a.vbits = ceil_log2(ns); a.key = key;
+    a.vshift = (ns >= 2 && (ns & (ns - 1)) == 0) ? 32 - a.vbits : 0;
     a.assign = d_assign; a.keep = d_keep; a.sub = d_sub; a.sub_cap = sub_cap; a.len = d_len;
     a.woff = d_woff; a.l_ub = l_ub; a.status = d_status;
     const uint64_t seg = segment_bits(ns);
@@ -876,11 +892,14 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
         const size_t q_lds = (size_t)4 * ns * 4;
         TimedLaunch timed(ws.timer, "k_hist", stream);
         if (ex)
-            hipLaunchKernelGGL(k_hist_q<true>, dim3(blocks), dim3(256), q_lds,
-                               stream, a);
+            hipLaunchKernelGGL((k_hist_q<true, false>), dim3(blocks), dim3(256),
+                               q_lds, stream, a);
+        else if (a.vshift)
+            hipLaunchKernelGGL((k_hist_q<false, true>), dim3(blocks), dim3(256),
+                               q_lds, stream, a);
         else
-            hipLaunchKernelGGL(k_hist_q<false>, dim3(blocks), dim3(256), q_lds,
-                               stream, a);
+            hipLaunchKernelGGL((k_hist_q<false, false>), dim3(blocks), dim3(256),
+                               q_lds, stream, a);
     } else {
         TimedLaunch timed(ws.timer, "k_hist", stream);
         if (ex)

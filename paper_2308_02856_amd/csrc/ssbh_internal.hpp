@@ -198,11 +198,15 @@ ssbh_status ensure_dynamic_lds(const void *kernel, size_t bytes);
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output t of the stream
 // seeded with `key` is mix(key + (t + 1) * golden_gamma).
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t key, uint64_t t) {
-    uint64_t z = key + (t + 1ull) * 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kSplitMixGamma = 0x9E3779B97F4A7C15ull;
+// The output function of SplitMix64 applied to the counter value z.
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t key, uint64_t t) {
+    return splitmix64_mix(key + (t + 1ull) * kSplitMixGamma);
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) {
