@@ -492,11 +492,13 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t acc) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
 }
 
-// m & ~(bal ^ e) on both halves: keeps the lanes whose bit equals this
-// lane's bit (e = 0 or ~0, bal = ballot of that bit).
+// m & ~(bal ^ e) on both halves, one v_bitop3 each (truth table 0x90):
+// keeps the lanes whose bit equals this lane's bit (e = 0 or ~0, bal = the
+// ballot of that bit).
 __device__ __forceinline__ uint64_t narrow(uint64_t m, uint64_t bal, uint32_t e) {
-    const uint32_t lo = (uint32_t)m & ~((uint32_t)bal ^ e);
-    const uint32_t hi = (uint32_t)(m >> 32) & ~((uint32_t)(bal >> 32) ^ e);
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)m, (uint32_t)bal, e, 0x90);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(m >> 32),
+                                                    (uint32_t)(bal >> 32), e, 0x90);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -519,7 +521,9 @@ __device__ __forceinline__ uint64_t narrow(uint64_t m, uint64_t bal, uint32_t e)
 //      last round; the bits are ORed into the image;
 //   3. all runs are copied out as in flush_runs.
 // Round indices fit 32 bits (n <= 2^32 - 2^20, so index + segment does too).
-// LDS: 4 match tables (16 KiB), 4 cursor tables (4 n_sub uint16), the image.
+// LDS: 4 match tables (16 KiB) and a zero slot, 4 cursor tables (4 n_sub
+// uint16), the image (n_sub = 2048: 40,944 bytes with the scan words, so
+// four workgroups share a CU's 160 KiB).
 template <bool EXPLICIT, int HB, bool POW2>
 __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -528,11 +532,12 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     const uint32_t ns = a.ns;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     uint64_t *tab = reinterpret_cast<uint64_t *>(lds);              // [4][256][2]
-    uint16_t *cur = reinterpret_cast<uint16_t *>(tab + 4 * 256 * 2);  // [4][ns]
+    const uint64_t *zero2 = tab + 4 * 256 * 2;        // one zero slot, never ORed
+    uint16_t *cur = reinterpret_cast<uint16_t *>(tab + 4 * 256 * 2 + 2);  // [4][ns]
     uint32_t *stage = reinterpret_cast<uint32_t *>(cur + 4 * ns);
     const uint32_t seg = blockIdx.x;
     const uint32_t nsw = (uint32_t)(a.seg_bits / 32) + 4;
-    for (uint32_t k = t; k < 4 * 256 * 2; k += 256) tab[k] = 0ull;
+    for (uint32_t k = t; k < 4 * 256 * 2 + 2; k += 256) tab[k] = 0ull;
     for (uint32_t k = t; k < nsw; k += 256) stage[k] = 0u;
 
     const uint32_t n32 = (uint32_t)a.n;
@@ -619,10 +624,10 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
         if (okE) atomicOr((unsigned long long *)&mt[2 * sE], (unsigned long long)me);
         if (okO) atomicOr((unsigned long long *)&mt[2 * sO + 1], (unsigned long long)me);
         __builtin_amdgcn_wave_barrier();
-        const ulonglong2 pE = *reinterpret_cast<const ulonglong2 *>(&mt[2 * sE]);
-        const ulonglong2 pO = *reinterpret_cast<const ulonglong2 *>(&mt[2 * sO]);
-        uint64_t mEE = okE ? pE.x : 0ull, mEO = okE ? pE.y : 0ull;
-        uint64_t mOE = okO ? pO.x : 0ull, mOO = okO ? pO.y : 0ull;
+        // A round that is not placed reads the zero slot: all its masks are 0.
+        const ulonglong2 pE = *reinterpret_cast<const ulonglong2 *>(okE ? &mt[2 * sE] : zero2);
+        const ulonglong2 pO = *reinterpret_cast<const ulonglong2 *>(okO ? &mt[2 * sO] : zero2);
+        uint64_t mEE = pE.x, mEO = pE.y, mOE = pO.x, mOO = pO.y;
 #pragma unroll
         for (int b = 0; b < HB; ++b) {
             const uint32_t eE = (uint32_t)__builtin_amdgcn_sbfe((int)vE, 8 + b, 1);
@@ -865,7 +870,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
     const size_t scat_lds = (size_t)ns * 4 + ((size_t)(seg / 32) + 4) * 4;
     const size_t tab_lds = scat_lds + (size_t)ns * 8;
     const bool use_tab = tab_lds <= 48 * 1024;
-    const size_t wg_lds = (size_t)4 * 2 * 256 * 8 + (size_t)4 * ns * 2 +
+    const size_t wg_lds = ((size_t)4 * 256 * 2 + 2) * 8 + (size_t)4 * ns * 2 +
                           ((size_t)(seg / 32) + 4) * 4;
     const bool use_wg = ns >= 2 && ns <= 4096 && seg <= kWgMaxSeg &&
                         wg_lds <= 64 * 1024 && ctx->forced_scatter != 1;
