@@ -84,7 +84,7 @@ enum {
                                  only for a shared seed (seed_stride == 0)    */
     SSBH_K_FFT = 3            /* middle product by double-precision FFTs,
                                  every entry rounded and checked; only for a
-                                 shared seed of at most 3 * 2^23 bits         */
+                                 shared seed of at most 2^31 bits             */
 };
 
 /* Limits of this build. */

@@ -10,27 +10,32 @@
 // the product with its spectrum keeps them apart and the inverse returns
 // (s * xr_a) + i (s * xr_b).
 //
-// Exactness: entries are integers in [0, n_j]; for 0/1 data and L <= 2^18 the
-// double-precision FFT error is below 1e-8, far from 1/2.  L is the smallest
-// of 2^k and 3 * 2^k (k >= 12) that holds the seed.  Every output entry
-// is rounded and its distance to the integer is checked (> 1/4 sets
-// SSBH_E_PRECISION), so a result is never silently wrong.
+// Exactness: entries are integers in [0, n_j]; for 0/1 data the
+// double-precision FFT error is of order eps log2 L |x| |s| (about 1e-8 at
+// L = 2^18, a few 1e-6 at 2^31), far from 1/2.  L is the smallest of 2^k and
+// 3 * 2^k (k >= 12) that holds the seed.  Every output entry is rounded and
+// its distance to the integer is checked (> 1/4 sets SSBH_E_PRECISION), so a
+// result is never silently wrong.
 //
 // Transform (four-step, N1 = 64, N2 = L / 64; natural input, transposed
 // frequency order Z[N2 k1 + k2] = X[k1 + 64 k2], which the pointwise product
 // does not mind):
 //   k_fft_cols   64-point FFTs down the columns of a 64-column tile (bits
 //                loaded and expanded on the fly), times w_L^(n2 k1), store.
-//   k_fft_rows   N2-point FFT of a row, times the seed spectrum, inverse FFT,
-//                times w_L^(-n2 k1), store (one pass over the data).
+//   k_fft_mid    (L > 2^18) the same split applied again to every row, once
+//                for three levels (64 x 64 x L/4096), twice for four
+//                (64 x 64 x 64 x L/2^18, L > 3 * 2^23), forward and inverse.
+//   k_fft_rows   row FFT (64 .. 8192 points), times the seed spectrum,
+//                inverse FFT, times the inverse of the row's twiddle, store
+//                (one pass over the data).
 //   k_fft_out    inverse 64-point FFTs down the columns, 1/L, round, parity;
 //                64 consecutive output rows per wavefront ballot.
-// The seed spectrum comes from the same two forward passes.  LDS FFTs are
-// Stockham autosort stages with radix-8 butterflies in registers (radix 2 or
-// 4, then radix 3 when L has a factor 3), twiddles from tables of w_N^k; the
-// first stage of each pass
-// reads global memory (or bits) and the last one writes its result straight
-// out (spectrum product, twiddle, or parity ballot fused in).
+// The seed spectrum comes from the same forward passes.  LDS FFTs are
+// Stockham autosort stages with radix-8 butterflies in registers (then one
+// radix 2, 3, 4, 6 or 12 stage for the rest), twiddles from tables of w_N^k;
+// the first stage of each pass reads global memory (or bits) and the last
+// one writes its result straight out (spectrum product, twiddle, or parity
+// ballot fused in).
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -59,8 +64,8 @@ struct FftArgs {
     uint64_t mcap;
     uint32_t ns;
     uint32_t n2;               // L / 64 (level-1 columns)
-    uint32_t nr;               // row FFT length: L / 64 (two levels) or
-                               // L / 4096 (three levels)
+    uint32_t nr;               // row FFT length: L / 64, L / 4096 or
+                               // L / 2^18 (two, three or four levels)
     uint64_t L;
     uint32_t pair0;            // first pair of this chunk
     double2 *work;             // [pairs in chunk][L]
@@ -68,8 +73,10 @@ struct FftArgs {
     const double2 *tw64;       // w_64^k, k < 64 (column FFTs)
     const double2 *twr;        // w_N2^k, k < N2 (row FFTs)
     const double2 *tlo, *thi;  // w_L^e = thi[e >> 9] * tlo[e & 511]
-    const double2 *rlo, *rhi;  // w_(64 nr)^e, same split (= w_L for two
-                               // levels, w_(L/64) for three)
+    const double2 *rlo, *rhi;  // w_(64 nr)^e, same split (the parent of a
+                               // row: w_L, w_(L/64) or w_(L/4096))
+    const double2 *wlo[3], *whi[3];  // w_(L/64^d)^e for level d, same split
+    int lvl;                   // level of a middle pass (1 or 2)
     uint64_t *out;
     int32_t *status;
 };
@@ -395,8 +402,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
 // Row pass over rows of N2 (= nr) points.  SPEC: forward only, the result is
 // the seed spectrum; else forward, times the spectrum, inverse, times
 // w_(64 N2)^(-e (row mod 64)) -- the inverse of the twiddle of the column
-// pass that made the row (w_L^(n2 k1) with two levels, w_(L/64)^(m2 l1) with
-// three).
+// pass that made the row (k_fft_cols with two levels, the last k_fft_mid
+// with three or four).
 template <int N2, bool SPEC>
 __global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
     __shared__ double2 buf[N2];
@@ -425,26 +432,37 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
     fft_run<N2, 1, true>(buf, a.twr, lds_ld, out_st);
 }
 
-// Middle column pass of the three-level transform, on each level-1 row
-// (k1) of L/64 = 64 nr points viewed as 64 x nr: 64-point FFTs down 64-column
-// tiles.  Forward: times w_(L/64)^(m2 l1).  Inverse (INV): the rows are
-// already multiplied by the inverse of that twiddle; after the inverse FFT
-// the level-1 twiddle is undone, times w_L^(-n2 k1) with n2 = nr m1 + m2.
+__device__ __forceinline__ double2 omega_d(const FftArgs &a, int d, uint64_t e) {
+    return cmul(a.whi[d][e >> 9], a.wlo[d][e & 511]);
+}
+
+// Middle column pass at level d (1 or 2) of a transform with three or four
+// levels.  Each row of level d (P = L / 64^d points; row index p < 64^d,
+// its index in its parent kp = p mod 64) is viewed as 64 x C, C = P / 64,
+// and transformed by 64-point FFTs down 64-column tiles.  Forward: times
+// w_P^(m l) (m the column, l the output of the 64-point FFT), which makes
+// the rows of level d + 1.  Inverse (INV): the rows of level d + 1 are
+// already back in place; after the inverse FFT the twiddle of the level
+// above is undone, times w_(64 P)^(-q kp) with q = C k + m the element of
+// this row.
 template <bool INV>
 __global__ __launch_bounds__(kThreads) void k_fft_mid(FftArgs a) {
     __shared__ double2 buf[kN1 * kN1];
     if (*a.status) return;
-    const uint32_t nr = a.nr;
+    const int d = a.lvl;
+    const uint64_t P = a.L >> (6 * d);
+    const uint32_t C = (uint32_t)(P >> 6);
     const uint32_t c0 = blockIdx.x * kN1;
-    const uint64_t k1 = blockIdx.y;
+    const uint64_t p = blockIdx.y;
+    const uint64_t kp = p & 63u;
     const uint32_t pl = blockIdx.z;
-    double2 *y = a.work + (size_t)pl * a.L + (size_t)k1 * a.n2;
-    auto ld = [&](int f, int e) { return y[(size_t)e * nr + c0 + f]; };
+    double2 *y = a.work + (size_t)pl * a.L + (size_t)p * P;
+    auto ld = [&](int f, int e) { return y[(size_t)e * C + c0 + f]; };
     auto st = [&](int f, int k, double2 x) {
-        const uint64_t m2 = c0 + f;
-        const double2 w = INV ? conj2(omega_l(a, ((uint64_t)k * nr + m2) * k1))
-                              : omega_r(a, m2 * (uint64_t)k);
-        y[(size_t)k * nr + m2] = cmul(x, w);
+        const uint64_t m = c0 + f;
+        const double2 w = INV ? conj2(omega_d(a, d - 1, ((uint64_t)k * C + m) * kp))
+                              : omega_d(a, d, m * (uint64_t)k);
+        y[(size_t)k * C + m] = cmul(x, w);
     };
     fft_run<kN1, kN1, INV>(buf, a.tw64, ld, st);
 }
@@ -519,13 +537,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
 // Twiddle tables, computed once per transform length on the host in long
 // double and kept by the context.
 struct FftTables {
-    DevBuf tw64, twr, tlo, thi, rlo, rhi;
+    DevBuf tw64, twr, lo[3], hi[3];   // lo/hi[d]: w_(L/64^d), 512 + P/512 entries
 };
 std::mutex g_tab_mu;
 std::map<std::pair<int, uint64_t>, FftTables *> g_tables;   // (device, L)
 
-// Row FFT length: L / 64 up to 2^18, else L / 4096 (three levels).
-uint64_t row_length(uint64_t L) { return L <= (1ull << 18) ? L / 64 : L / 4096; }
+// Levels of the transform: 64 x (L/64) up to 2^18, 64 x 64 x (L/4096) up to
+// 3 * 2^23, 64 x 64 x 64 x (L/2^18) above.
+int fft_levels(uint64_t L) {
+    return L <= (1ull << 18) ? 2 : L <= (3ull << 23) ? 3 : 4;
+}
+// Row FFT length.
+uint64_t row_length(uint64_t L) { return L >> (6 * (fft_levels(L) - 1)); }
 
 ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
     std::lock_guard<std::mutex> lk(g_tab_mu);
@@ -539,22 +562,30 @@ ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
         const long double ang = -two_pi * (long double)k / (long double)n;
         return make_double2((double)cosl(ang), (double)sinl(ang));
     };
-    const uint64_t nr = row_length(L), lr = 64 * nr;
-    std::vector<double2> tw64(kN1), twr(nr), tlo(512), thi(L / 512),
-        rlo(512), rhi(lr / 512);
-    for (uint64_t k = 0; k < tw64.size(); ++k) tw64[k] = unit(k, kN1);
-    for (uint64_t k = 0; k < twr.size(); ++k) twr[k] = unit(k, nr);
-    for (uint64_t k = 0; k < tlo.size(); ++k) tlo[k] = unit(k, L);
-    for (uint64_t k = 0; k < thi.size(); ++k) thi[k] = unit(k * 512, L);
-    for (uint64_t k = 0; k < rlo.size(); ++k) rlo[k] = unit(k, lr);
-    for (uint64_t k = 0; k < rhi.size(); ++k) rhi[k] = unit(k * 512, lr);
+    const int levels = fft_levels(L);
+    const uint64_t nr = row_length(L);
+    std::vector<std::vector<double2>> src;
+    std::vector<DevBuf *> bufs;
     auto *t = new FftTables();
-    DevBuf *bufs[6] = {&t->tw64, &t->twr, &t->tlo, &t->thi, &t->rlo, &t->rhi};
-    const std::vector<double2> *src[6] = {&tw64, &twr, &tlo, &thi, &rlo, &rhi};
-    for (int b = 0; b < 6; ++b) {
-        ssbh_status st = bufs[b]->reserve(src[b]->size() * sizeof(double2));
+    src.emplace_back(kN1);
+    for (uint64_t k = 0; k < (uint64_t)kN1; ++k) src.back()[k] = unit(k, kN1);
+    bufs.push_back(&t->tw64);
+    src.emplace_back(nr);
+    for (uint64_t k = 0; k < nr; ++k) src.back()[k] = unit(k, nr);
+    bufs.push_back(&t->twr);
+    for (int d = 0; d <= levels - 2; ++d) {       // w_P for the parents of rows
+        const uint64_t P = L >> (6 * d);
+        src.emplace_back(512);
+        for (uint64_t k = 0; k < 512; ++k) src.back()[k] = unit(k, P);
+        bufs.push_back(&t->lo[d]);
+        src.emplace_back(P / 512);
+        for (uint64_t k = 0; k < P / 512; ++k) src.back()[k] = unit(k * 512, P);
+        bufs.push_back(&t->hi[d]);
+    }
+    for (size_t b = 0; b < bufs.size(); ++b) {
+        ssbh_status st = bufs[b]->reserve(src[b].size() * sizeof(double2));
         if (st == SSBH_OK &&
-            hipMemcpy(bufs[b]->ptr, src[b]->data(), src[b]->size() * sizeof(double2),
+            hipMemcpy(bufs[b]->ptr, src[b].data(), src[b].size() * sizeof(double2),
                       hipMemcpyHostToDevice) != hipSuccess) {
             set_error("twiddle table upload failed");
             st = SSBH_E_DEVICE;
@@ -596,18 +627,19 @@ void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
     case 2048: launch_rows<2048>(a, pairs, spec, stream); break;
     case 3072: launch_rows<3072>(a, pairs, spec, stream); break;
     case 4096: launch_rows<4096>(a, pairs, spec, stream); break;
-    default: launch_rows<6144>(a, pairs, spec, stream); break;
+    case 6144: launch_rows<6144>(a, pairs, spec, stream); break;
+    default: launch_rows<8192>(a, pairs, spec, stream); break;
     }
 }
 
 }  // namespace
 
 // Transform length: the smallest supported L that holds the seed, 2^k or
-// 3 * 2^k: L <= 2^18 as 64 x (L/64), larger L as 64 x 64 x (L/4096) with
-// row FFTs of 96 .. 6144 points; kMaxFftLength + 1 when none holds it.
+// 3 * 2^k, 4096 <= L <= 2^31, with two, three or four levels and row FFTs of
+// 64 .. 8192 points; kMaxFftLength + 1 when none holds it.
 uint64_t fft_length(uint64_t seed_bits) {
-    // Every length is a multiple of 4096 whose row length is a multiple of
-    // 64 (or a two-level length): 3 * 2^11 and 3 * 2^17 are left out.
+    // Every row length is a multiple of 64: 3 * 2^11 (two levels) and
+    // 3 * 2^17 (three levels) are left out.
     for (uint64_t L = 4096; L <= kMaxFftLength;) {
         if (L >= seed_bits) return L;
         L = (L % 3 == 0) ? L / 3 * 4 : L / 2 * 3;   // 2^k, 3 * 2^(k-1), 2^(k+1)
@@ -652,15 +684,32 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.mcap = q.m_cap; a.ns = q.n_sub;
     a.L = L; a.n2 = (uint32_t)(L / kN1);
     a.nr = (uint32_t)row_length(L);
-    const bool three = a.nr != a.n2;
+    const int levels = fft_levels(L);
     a.work = ws.fft_work.as<double2>();
     a.spec = ws.fft_spec.as<double2>();
     a.tw64 = tab->tw64.as<double2>();
     a.twr = tab->twr.as<double2>();
-    a.tlo = tab->tlo.as<double2>();
-    a.thi = tab->thi.as<double2>();
-    a.rlo = tab->rlo.as<double2>();
-    a.rhi = tab->rhi.as<double2>();
+    for (int d = 0; d <= levels - 2; ++d) {
+        a.wlo[d] = tab->lo[d].as<double2>();
+        a.whi[d] = tab->hi[d].as<double2>();
+    }
+    a.tlo = a.wlo[0];
+    a.thi = a.whi[0];
+    a.rlo = a.wlo[levels - 2];
+    a.rhi = a.whi[levels - 2];
+    // Middle passes, forward (levels 1, 2) and inverse (2, 1).
+    auto mids = [&](bool inv, uint32_t np) {
+        for (int i = 0; i < levels - 2; ++i) {
+            const int d = inv ? levels - 2 - i : 1 + i;
+            a.lvl = d;
+            const uint64_t C = (L >> (6 * d)) >> 6;
+            const dim3 g((uint32_t)(C / kN1), 1u << (6 * d), np);
+            if (inv)
+                hipLaunchKernelGGL(k_fft_mid<true>, g, dim3(kThreads), 0, stream, a);
+            else
+                hipLaunchKernelGGL(k_fft_mid<false>, g, dim3(kThreads), 0, stream, a);
+        }
+    };
     a.out = q.out;
     a.status = q.status;
     const uint32_t tiles = a.n2 / kN1;
@@ -670,9 +719,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         TimedLaunch timed(ws.timer, "k_fft_spectrum", stream);
         hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
                            stream, a);
-        if (three)
-            hipLaunchKernelGGL(k_fft_mid<false>, dim3(a.nr / kN1, kN1, 1),
-                               dim3(kThreads), 0, stream, a);
+        mids(false, 1);
         rows(a, 1, true, stream);
     }
     for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
@@ -683,19 +730,17 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             hipLaunchKernelGGL(k_fft_cols<false>, dim3(tiles, np),
                                dim3(kThreads), 0, stream, a);
         }
-        if (three) {
+        if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
-            hipLaunchKernelGGL(k_fft_mid<false>, dim3(a.nr / kN1, kN1, np),
-                               dim3(kThreads), 0, stream, a);
+            mids(false, np);
         }
         {
             TimedLaunch timed(ws.timer, "k_fft_rows", stream);
             rows(a, np, false, stream);
         }
-        if (three) {
+        if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
-            hipLaunchKernelGGL(k_fft_mid<true>, dim3(a.nr / kN1, kN1, np),
-                               dim3(kThreads), 0, stream, a);
+            mids(true, np);
         }
         {
             TimedLaunch timed(ws.timer, "k_fft_out", stream);

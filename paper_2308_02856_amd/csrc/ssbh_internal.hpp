@@ -105,7 +105,7 @@ struct MfmaSchedule {
 struct FftSchedule {
     uint32_t chunk_pairs = 0;
 };
-constexpr uint64_t kMaxFftLength = 3ull << 23;   // transform length limit
+constexpr uint64_t kMaxFftLength = 1ull << 31;   // transform length limit
 
 struct ServeState;   // serving scheduler (serve.hip)
 

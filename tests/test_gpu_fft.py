@@ -124,7 +124,7 @@ def test_rejects_independent_seeds_and_long_seeds(ctx):
                        kernel=ssbh.K_FFT)
     assert e.value.status == ssbh.E_INVAL
     with pytest.raises(ssbh.SsbhError) as e:
-        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, (3 << 23) + 1, 100,
+        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, (1 << 31) + 1, 100,
                        out_rule=ssbh.OUT_FIXED, out_a=100, kernel=ssbh.K_FFT)
     assert e.value.status == ssbh.E_UNSUPPORTED
 
@@ -204,13 +204,14 @@ def test_fft_graph_pipeline_replays(ctx, orc):
 
 
 LENGTHS = [4096, 8192, 12288, 16384, 24576, 32768, 49152, 65536, 98304,
-           131072, 196608, 262144, 524288, 786432, 1048576]
+           131072, 196608, 262144, 524288, 786432, 1048576, 1 << 25, 3 << 24]
 
 
 @pytest.mark.parametrize("L", LENGTHS)
 def test_every_transform_length(ctx, orc, L):
-    """Seeds that select each supported transform length (2^k and 3 * 2^k):
-    FFT == VALU kernel on every bit, and sampled rows == the oracle."""
+    """Seeds that select transform lengths with two, three and four levels
+    (2^k and 3 * 2^k): FFT == VALU kernel on every bit, and sampled rows ==
+    the oracle."""
     import torch
     from paper_2308_02856_amd import ssbh
     ns = 6
@@ -336,3 +337,27 @@ def test_untuned_auto_picks_fft_for_long_blocks(n, m, want_fft):
         assert np.array_equal(to_host(out), to_host(ref))
     finally:
         ctx.close()
+
+
+def test_four_level_single_block_960_mbit(ctx, orc):
+    """Table I's fourth input size as one block: n = 960.40 Mbit hashed to
+    m = 74.406 Mbit (seed n + m - 1 bits, transform length 2^30, four
+    levels); sampled rows, including both ends, against the oracle."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    n, m = 960_400_000, 74_406_000
+    x = uniform_bits(n, 2960)
+    seed_bits = n + m - 1
+    seed_h = uniform_bits(seed_bits, 2961)
+    d_x, seed = to_dev(x), to_dev(seed_h)
+    ln = torch.tensor([n], dtype=torch.int64, device="cuda")
+    wo = torch.zeros(1, dtype=torch.int64, device="cuda")
+    got, tot = fft_hash(ctx, d_x, ln, wo, 1, seed, seed_bits, m,
+                        out_rule=ssbh.OUT_FIXED, out_a=m)
+    assert ctx.last_schedule().endswith(":L%d" % (1 << 30)) and tot == m
+    del d_x, seed
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(960)
+    for r in [0, 1, 63, 64, m - 1] + [int(v) for v in rng.integers(0, m, 6)]:
+        want = orc.toeplitz_rowwin(x, n, seed_h, seed_bits, 0, m, r)
+        assert ((int(got[r >> 6]) >> (r & 63)) & 1) == want, r
