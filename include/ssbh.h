@@ -83,8 +83,14 @@ enum {
     SSBH_K_MFMA_I8 = 2,       /* int8 matrix cores, int32 sums, then mod 2;
                                  only for a shared seed (seed_stride == 0)    */
     SSBH_K_FFT = 3            /* middle product by double-precision FFTs,
-                                 every entry rounded and checked; only for a
-                                 shared seed of at most 2^31 bits             */
+                                 every entry rounded and checked.  Shared
+                                 seed of at most 2^31 bits: two sub-blocks
+                                 per transform.  Seed stride S > 0 (at most
+                                 2^31): one transform per sub-block with the
+                                 spectrum of its own seed; needs every
+                                 n_j + m_cap - 1 <= the transform length of
+                                 S (true when S >= n_max + m_cap - 1), else
+                                 *d_status = SSBH_E_UNSUPPORTED              */
 };
 
 /* Limits of this build. */

@@ -387,11 +387,10 @@ ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
     if (seed_bits && !d_seed) SSBH_INVAL("d_seed is null");
     if (kernel == SSBH_K_MFMA_I8 && seed_stride != 0)
         SSBH_INVAL("the MFMA kernel needs a shared seed (seed_stride = 0)");
-    if (kernel == SSBH_K_FFT && seed_stride != 0)
-        SSBH_INVAL("the FFT hash needs a shared seed (seed_stride = 0)");
-    if (kernel == SSBH_K_FFT && fft_length(seed_bits) > kMaxFftLength) {
-        set_error("the FFT hash supports seeds of at most %llu bits",
-                  (unsigned long long)kMaxFftLength);
+    if (kernel == SSBH_K_FFT &&
+        fft_length(seed_stride ? seed_stride : seed_bits) > kMaxFftLength) {
+        set_error("the FFT hash supports seeds (or seed strides) of at most "
+                  "%llu bits", (unsigned long long)kMaxFftLength);
         return SSBH_E_UNSUPPORTED;
     }
     if (kernel > SSBH_K_FFT) SSBH_INVAL("unknown kernel %u", kernel);

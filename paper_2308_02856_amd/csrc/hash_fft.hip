@@ -77,6 +77,9 @@ struct FftArgs {
                                // row: w_L, w_(L/64) or w_(L/4096))
     const double2 *wlo[3], *whi[3];  // w_(L/64^d)^e for level d, same split
     int lvl;                   // level of a middle pass (1 or 2)
+    int solo;                  // independent seeds: "pair" pair0 + p is the
+                               // one sub-block pair0 + p (imaginary part 0)
+    uint64_t seed_off;         // first seed bit of the spectrum's seed
     uint64_t *out;
     int32_t *status;
 };
@@ -354,9 +357,18 @@ __device__ __forceinline__ uint64_t window64(const uint64_t *w, int64_t nbits,
     return v;
 }
 
-// Forward column pass.  SEED: the input is the seed itself (u[q] = s[q],
-// real); else pair p's two reversed sub-blocks (real, imaginary).  The first
-// stage reads bits, the last stage stores times w_L^(n2 k1).
+// Sub-block in part `part` (0 real, 1 imaginary) of transform pl of the
+// chunk; a.ns when there is none.
+__device__ __forceinline__ uint64_t sub_of(const FftArgs &a, uint32_t pl, int part) {
+    if (a.solo) return part ? (uint64_t)a.ns : (uint64_t)a.pair0 + pl;
+    return 2ull * (a.pair0 + pl) + part;
+}
+
+// Forward column pass.  SEED: the input is the seed from bit seed_off on
+// (u[q] = s[seed_off + q], real); else pair p's two reversed sub-blocks
+// (real, imaginary).  The first stage reads bits, the last stage stores
+// times w_L^(n2 k1).  A sub-block whose n_j + m_cap - 1 exceeds L (possible
+// only with a seed stride below n_max + m_cap - 1) sets SSBH_E_UNSUPPORTED.
 template <bool SEED>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     __shared__ double2 buf[kN1 * kN1];
@@ -373,11 +385,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
         if (SEED) {
             if (part == 0)
                 v = window64(a.seed, (int64_t)a.seed_bits,
-                             (int64_t)n2 * n1 + c0);
+                             (int64_t)(a.seed_off + (uint64_t)n2 * n1 + c0));
         } else {
-            const uint64_t j = 2ull * (a.pair0 + pl) + part;
+            const uint64_t j = sub_of(a, pl, part);
             if (j < a.ns) {
                 const int64_t n = (int64_t)a.len[j];
+                if (n1 == 0 && blockIdx.x == 0 && (uint64_t)n + a.mcap - 1 > a.L)
+                    atomicCAS(a.status, 0, (int32_t)SSBH_E_UNSUPPORTED);
                 // xr[q] = x[n-1-q] for q = n2*n1 + c0 + i, i < 64.
                 const int64_t b0 = n - 1 - ((int64_t)n2 * n1 + c0) - 63;
                 v = __brevll(window64(a.sub + a.woff[j], n, b0));
@@ -502,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     bool has[2];
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
-        const uint64_t j = 2ull * (a.pair0 + pl) + part;
+        const uint64_t j = sub_of(a, pl, part);
         has[part] = j < a.ns;
         n[part] = has[part] ? (int64_t)a.len[j] : 0;
         m[part] = has[part] ? (int64_t)a.mlen[j] : 0;
@@ -650,14 +664,12 @@ uint64_t fft_length(uint64_t seed_bits) {
 
 ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                             const FftSchedule &s, hipStream_t stream) {
-    if (q.stride != 0) {
-        set_error("the FFT hash needs a shared seed (seed_stride = 0)");
-        return SSBH_E_INVAL;
-    }
-    const uint64_t L = fft_length(q.seed_bits);
+    // Transform length: the whole seed when it is shared, one stride of it
+    // (the seed of one sub-block) otherwise.
+    const uint64_t L = fft_length(q.stride ? q.stride : q.seed_bits);
     if (L > kMaxFftLength) {
-        set_error("the FFT hash supports seeds of at most %llu bits",
-                  (unsigned long long)kMaxFftLength);
+        set_error("the FFT hash supports seeds (or seed strides) of at most "
+                  "%llu bits", (unsigned long long)kMaxFftLength);
         return SSBH_E_UNSUPPORTED;
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
@@ -671,8 +683,9 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     if (!q.n_sub) return SSBH_OK;
     FftTables *tab = nullptr;
     if ((st = get_tables(ctx->device, L, &tab)) != SSBH_OK) return st;
-    const uint64_t pairs = (q.n_sub + 1ull) / 2;
-    const uint32_t cp = (uint32_t)std::min<uint64_t>(pairs, chunk);
+    const bool solo = q.stride != 0;
+    const uint64_t pairs = solo ? q.n_sub : (q.n_sub + 1ull) / 2;
+    const uint32_t cp = solo ? 1u : (uint32_t)std::min<uint64_t>(pairs, chunk);
     if ((st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK) return st;
     if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
         return st;
@@ -713,17 +726,22 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.out = q.out;
     a.status = q.status;
     const uint32_t tiles = a.n2 / kN1;
-    // Seed spectrum.
-    a.pair0 = 0;
-    {
+    a.solo = solo ? 1 : 0;
+    // Seed spectrum: once for a shared seed; with a seed stride, the
+    // spectrum of sub-block j's seed before each of its transforms.
+    auto spectrum = [&](uint64_t seed_off) {
+        a.pair0 = 0;
+        a.seed_off = seed_off;
         TimedLaunch timed(ws.timer, "k_fft_spectrum", stream);
         hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
                            stream, a);
         mids(false, 1);
         rows(a, 1, true, stream);
-    }
+    };
+    if (!solo) spectrum(0);
     for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
         const uint32_t np = (uint32_t)std::min<uint64_t>(cp, pairs - p0);
+        if (solo) spectrum(p0 * q.stride);
         a.pair0 = (uint32_t)p0;
         {
             TimedLaunch timed(ws.timer, "k_fft_cols", stream);

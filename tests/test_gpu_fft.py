@@ -110,23 +110,65 @@ def test_empty_and_degenerate_sub_blocks(ctx, orc):
     assert np.array_equal(got[: want.size], want)
 
 
-def test_rejects_independent_seeds_and_long_seeds(ctx):
+def test_rejects_long_seeds_and_short_strides(ctx):
+    """Seeds (or seed strides) past 2^31 are refused on the host; a stride
+    below n_max + m_cap - 1 whose transform cannot hold a sub-block gives
+    SSBH_E_UNSUPPORTED on the device."""
+    import torch
     from paper_2308_02856_amd import ssbh
     n, ns = 4096, 4
     sub = to_dev(uniform_bits(n, 1))
-    import torch
     ln = torch.full((ns,), n // ns, dtype=torch.int64, device="cuda")
     wo = torch.arange(ns, dtype=torch.int64, device="cuda") * (n // ns // 64)
     seed = to_dev(uniform_bits(1 << 20, 2))
     with pytest.raises(ssbh.SsbhError) as e:
-        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, 1 << 20, 100,
-                       out_rule=ssbh.OUT_FIXED, out_a=100, seed_stride=2000,
-                       kernel=ssbh.K_FFT)
-    assert e.value.status == ssbh.E_INVAL
-    with pytest.raises(ssbh.SsbhError) as e:
         ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, (1 << 31) + 1, 100,
                        out_rule=ssbh.OUT_FIXED, out_a=100, kernel=ssbh.K_FFT)
     assert e.value.status == ssbh.E_UNSUPPORTED
+    with pytest.raises(ssbh.SsbhError) as e:
+        ctx.hash_batch(sub, sub.numel(), ln, wo, 1, seed, 1 << 20, 100,
+                       out_rule=ssbh.OUT_FIXED, out_a=100,
+                       seed_stride=(1 << 31) + 1, kernel=ssbh.K_FFT)
+    assert e.value.status == ssbh.E_UNSUPPORTED
+    # n_j = 5000, m = 100: n + m - 1 = 5099 > 4096 = the length for a
+    # stride of 2000 (overlapping seeds, legal for the quadratic kernels).
+    big = to_dev(uniform_bits(4 * 5000, 3))
+    ln2 = torch.full((2,), 5000, dtype=torch.int64, device="cuda")
+    wo2 = torch.tensor([0, 79], dtype=torch.int64, device="cuda")
+    out, tot, st = ctx.hash_batch(big, big.numel(), ln2, wo2, 2, seed, 1 << 20,
+                                  100, out_rule=ssbh.OUT_FIXED, out_a=100,
+                                  seed_stride=2000, kernel=ssbh.K_FFT)
+    torch.cuda.synchronize()
+    assert int(st.item()) == ssbh.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("ns,n,m,extra", [(1, 5000, 1200, 0), (5, 30000, 9000, 7),
+                                          (4, 100000, 37000, 64), (7, 1000, 999, 3)])
+def test_independent_seeds_match_oracle_and_valu(ctx, orc, ns, n, m, extra):
+    """Seed stride S = n_max + m - 1 + extra (the paper's independent seeds):
+    one transform per sub-block with its own seed spectrum; equal to the
+    oracle and to the VALU kernel on every bit."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    N = n * ns + 333
+    a = uniform_bits(N, ns * 7 + n)
+    key = 0x5EED + ns
+    sub, ln, wo, st = ctx.sample(to_dev(a), N, ns, ssbh.SAMPLE_IID, key=key)
+    osub, oln, owo, _ = orc.sample(a, N, ns, orc.SAMPLE_IID, key=key)
+    S = int(oln.max()) + m - 1 + extra
+    seed_bits = ns * S
+    seed = uniform_bits(seed_bits, n + m)
+    kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m, seed_stride=S)
+    got, tot = fft_hash(ctx, sub, ln, wo, ns, to_dev(seed), seed_bits, m, **kw)
+    want, wtot = orc.hash_batch(osub, oln, owo, np.full(ns, m, np.uint64),
+                                seed, seed_bits, S, m)
+    assert tot == wtot
+    assert np.array_equal(got[: want.size], want), first_diff(got[: want.size], want)
+    out, tot2, st2 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns, to_dev(seed),
+                                    seed_bits, m, kernel=ssbh.K_VALU, **kw)
+    torch.cuda.synchronize()
+    assert int(st2.item()) == 0
+    assert np.array_equal(got, to_host(out))
 
 
 def test_batched_workload_fft_equals_mfma(ctx, orc):

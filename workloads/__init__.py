@@ -19,4 +19,6 @@ from .gen import (  # noqa: F401
     unpack_bits,
     pack_bits,
 )
-from .configs import CONFIGS, config, serving_jobs, serving_pools  # noqa: F401
+from .configs import (  # noqa: F401
+    CONFIGS, TABLE1, TABLE1_N_SUB, config, serving_jobs, serving_pools,
+    table1_instance)

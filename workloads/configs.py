@@ -17,6 +17,9 @@ run (tests, benchmark, smoke check) sees the same synthetic data.
                   log-uniform in 2^20..2^28, Bernoulli(p), p ~ U[0.2, 0.5],
                   sub-block size log-uniform in 2^16..2^18, output ratio
                   q/1000 with q uniform in 200..600, fresh keys per job.
+* ``TABLE1``      the five input/output sizes of the paper's FPGA experiment
+                  (96.04 .. 1920 Mbit in, 6.054 .. 152.56 Mbit out), uniform
+                  bits, hashed as one block and by 20 sub-blocks.
 """
 
 from __future__ import annotations
@@ -58,6 +61,40 @@ CONFIGS = {
         sample_key_base=_KEY_BASE + 0x105, seed_key_base=_KEY_BASE + 0x205,
     ),
 }
+
+
+# Table I of the paper (Sec. IV.C): input and output sizes of the FPGA
+# experiment (Mbit) and its measured speeds in output bits per second, for
+# direct hashing of one block ("traditional"; not measured at the two largest
+# sizes) and for the sub-block method with p_S = 0.05, i.e. 20 sub-blocks.
+# Context only: other hardware.
+TABLE1 = [
+    dict(input_mbit=96.040, output_mbit=6.054, fpga_traditional=498.60,
+         fpga_ours=9899.80),
+    dict(input_mbit=192.08, output_mbit=13.302, fpga_traditional=249.31,
+         fpga_ours=4972.47),
+    dict(input_mbit=288.12, output_mbit=20.736, fpga_traditional=166.24,
+         fpga_ours=3318.63),
+    dict(input_mbit=960.40, output_mbit=74.406, fpga_traditional=None,
+         fpga_ours=997.05),
+    dict(input_mbit=1920.00, output_mbit=152.56, fpga_traditional=None,
+         fpga_ours=498.62),
+]
+TABLE1_N_SUB = 20
+
+
+def table1_instance(k: int) -> dict:
+    """Sizes and keys of Table I row k: n input bits (uniform), m output
+    bits in total; the sub-block method divides the input i.i.d. into
+    TABLE1_N_SUB sub-blocks and gives each floor(m / TABLE1_N_SUB) output
+    bits, hashed with its own seed."""
+    row = TABLE1[k]
+    n = int(round(row["input_mbit"] * 1e6))
+    m = int(round(row["output_mbit"] * 1e6))
+    return dict(row, n_bits=n, m_bits=m, n_sub=TABLE1_N_SUB,
+                sub_out=m // TABLE1_N_SUB, input_seed=1000 + k,
+                seed_seed=2000 + k, sub_seed_seed=3000 + k,
+                sample_key=_KEY_BASE + 0x110 + k)
 
 
 def config(name: str) -> dict:
