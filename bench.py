@@ -9,7 +9,8 @@ input Gbit/s of that step with the input resident in HBM.  The same line
 reports the plain single-block hash (n = 2^24 -> m = 2^23) that the method is
 compared with (bit-sliced kernel and FFT, the faster one counts), the contraction workload (2^30 bits, 8192 equal sub-blocks,
 int8 matrix cores against the bit-sliced kernel), the small workload through a
-captured HIP graph, the serving stream (p50/p99 latency, sustained Gbit/s),
+captured HIP graph, the five input/output sizes of the paper's Table I (one
+block and 20 sub-blocks with independent seeds, both by the FFT hash), the serving stream (p50/p99 latency, sustained Gbit/s),
 the roofline of the dominant kernel (timed with HIP events on its stream) and
 the CPU oracle timed on a bounded sample.
 """
@@ -247,6 +248,115 @@ def run_single(ctx, ssbh, args):
     res["fft_equals_valu"] = bool(torch.equal(words["valu"], words["fft"]))
     res["ms"] = min(res["ms_valu"], res["ms_fft"])
     return res
+
+
+# ------------------------------------------------------------------ Table I
+
+def run_table1(ctx, ssbh, args):
+    """The input/output sizes of the paper's FPGA experiment (Table I, five
+    rows, uniform synthetic bits), hashed on the GPU two ways with the FFT
+    hash: one block directly ("traditional", seed n + m - 1 bits) and the
+    sub-block method (i.i.d. division into 20 sub-blocks, floor(m / 20)
+    output bits each, every sub-block with its own seed of L_S^UB + l - 1
+    bits, L_S^UB at eps = 1e-8).  Speeds are output bits per second, the unit
+    of the table, next to the FPGA's (context: other hardware).  The first
+    row is also hashed by the bit-sliced kernel and must give the same bits."""
+    import torch
+    from workloads import TABLE1, table1_instance, uniform_bits
+    out_rows = []
+    ks = range(len(TABLE1)) if args.table1_rows is None else [
+        int(v) for v in args.table1_rows.split(",")]
+    for k in ks:
+        c = table1_instance(k)
+        n, m, ns, lt = c["n_bits"], c["m_bits"], c["n_sub"], c["sub_out"]
+        log(f"table1 row {k}: {n} -> {m} bits")
+        x = to_dev(uniform_bits(n, c["input_seed"]))
+        # Traditional: one block.
+        sb = n + m - 1
+        seed = to_dev(uniform_bits(sb, c["seed_seed"]))
+        ln = torch.tensor([n], dtype=torch.int64, device="cuda")
+        wo = torch.zeros(1, dtype=torch.int64, device="cuda")
+        out = torch.empty((m + 63) // 64, dtype=torch.int64, device="cuda")
+        tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+        def trad(kernel=ssbh.K_FFT):
+            ctx.hash_batch(x, x.numel(), ln, wo, 1, seed, sb, m,
+                           out_rule=ssbh.OUT_FIXED, out_a=m, out=out,
+                           out_capacity_bits=m, total=tot, status=st,
+                           reset_status=False, kernel=kernel)
+
+        trad()
+        torch.cuda.synchronize()
+        ms_trad = float(np.mean(time_events(trad, args.table1_reps)))
+        if int(st.item()) != 0:
+            raise RuntimeError(f"table1 row {k}: traditional status {int(st.item())}")
+        trad_sched = ctx.last_schedule()
+        row = {"input_mbit": c["input_mbit"], "output_mbit": c["output_mbit"],
+               "traditional": {"ms": round(ms_trad, 3),
+                               "out_bits_per_s": round(m / (ms_trad * 1e-3)),
+                               "in_gbps": round(n / (ms_trad * 1e-3) / 1e9, 3),
+                               "schedule": trad_sched}}
+        if k == 0:
+            ref = out.clone()
+            trad(ssbh.K_VALU)
+            torch.cuda.synchronize()
+            row["traditional"]["fft_equals_valu"] = bool(
+                int(st.item()) == 0 and torch.equal(ref, out))
+        del seed
+        # Sub-block method: 20 sub-blocks, independent seeds.
+        l_ub, _ = ssbh.ub_threshold(n, 1.0 / ns, ns, 1e-8)
+        S = l_ub + lt - 1
+        seeds = to_dev(uniform_bits(ns * S, c["sub_seed_seed"]))
+        subcap = (n + 63) // 64 + ns
+        sub = torch.empty(subcap, dtype=torch.int64, device="cuda")
+        lens = torch.empty(ns, dtype=torch.int64, device="cuda")
+        woffs = torch.empty(ns, dtype=torch.int64, device="cuda")
+        sst = torch.zeros(1, dtype=torch.int32, device="cuda")
+        o2 = torch.empty((ns * lt + 63) // 64, dtype=torch.int64, device="cuda")
+        tot2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        st2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+        def sample():
+            ctx.sample(x, n, ns, ssbh.SAMPLE_IID, key=c["sample_key"], l_ub=l_ub,
+                       sub=sub, sub_capacity=subcap, length=lens, word_off=woffs,
+                       status=sst)
+
+        def ours(kernel=ssbh.K_FFT):
+            sample()
+            ctx.hash_batch(sub, subcap, lens, woffs, ns, seeds, ns * S, lt,
+                           out_rule=ssbh.OUT_FIXED, out_a=lt, seed_stride=S,
+                           out=o2, out_capacity_bits=ns * lt, total=tot2,
+                           status=st2, reset_status=False, kernel=kernel)
+
+        ours()
+        torch.cuda.synchronize()
+        ms_ours = float(np.mean(time_events(ours, args.table1_reps)))
+        ms_samp = float(np.mean(time_events(sample, args.table1_reps)))
+        if int(sst.item()) != 0 or int(st2.item()) != 0:
+            raise RuntimeError(f"table1 row {k}: status {int(sst.item())}/"
+                               f"{int(st2.item())}")
+        row["ours"] = {"ms": round(ms_ours, 3), "sample_ms": round(ms_samp, 3),
+                       "out_bits_per_s": round(ns * lt / (ms_ours * 1e-3)),
+                       "in_gbps": round(n / (ms_ours * 1e-3) / 1e9, 3),
+                       "n_sub": ns, "sub_out_bits": lt, "l_ub": l_ub,
+                       "seed_stride": S, "schedule": ctx.last_schedule()}
+        if k == 0:
+            ref = o2.clone()
+            ours(ssbh.K_VALU)
+            torch.cuda.synchronize()
+            row["ours"]["fft_equals_valu"] = bool(
+                int(st2.item()) == 0 and torch.equal(ref, o2))
+        row["fpga_out_bits_per_s"] = {"traditional": c["fpga_traditional"],
+                                      "ours": c["fpga_ours"]}
+        row["gpu_ours_over_fpga_ours"] = round(
+            row["ours"]["out_bits_per_s"] / c["fpga_ours"])
+        row["ours_over_traditional_gpu"] = round(ms_trad / ms_ours, 2)
+        out_rows.append(row)
+        del x, seeds, sub, out, o2
+        torch.cuda.empty_cache()
+    return {"workload": "table1", "speed_unit": "output bits/s",
+            "kernel": "fft", "data": "uniform synthetic bits", "rows": out_rows}
 
 
 # -------------------------------------------------------------- contraction
@@ -568,12 +678,16 @@ def main() -> int:
     ap.add_argument("--skip-contraction", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--skip-table1", action="store_true")
+    ap.add_argument("--table1-rows", default=None,
+                    help="comma-separated Table I rows (default all five)")
+    ap.add_argument("--table1-reps", type=int, default=2)
     ap.add_argument("--serve-jobs", type=int, default=3000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-budget-mib", type=int, default=512)
     ap.add_argument("--mode", default="full",
                     choices=["full", "hash-batched", "hash-single", "copy",
-                             "contraction", "small", "serving"],
+                             "contraction", "small", "serving", "table1"],
                     help="full = the benchmark line; the others run one "
                          "part only, for profiler passes")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -602,6 +716,11 @@ def main() -> int:
         return 0
     ctx = ssbh.Context(0)
     peak = alu_peak_tbitops(ctx.num_cus)
+    if args.mode == "table1":
+        ctx = ssbh.Context(0)
+        print(json.dumps(run_table1(ctx, ssbh, args)), flush=True)
+        ctx.close()
+        return 0
     if args.mode == "hash-single":
         single = run_single(ctx, ssbh, args)
         print(json.dumps({"mode": args.mode, "ms_valu": single["ms_valu"],
@@ -710,6 +829,8 @@ def main() -> int:
         line["contraction"] = run_contraction(ctx, ssbh, args, peak)
     if not args.skip_small:
         line["small"] = run_small(ctx, ssbh, args)
+    if not args.skip_table1:
+        line["table1"] = run_table1(ctx, ssbh, args)
     ctx.close()
     if not args.skip_serving:
         line["serving"] = run_serving(ssbh, args)
