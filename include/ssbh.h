@@ -175,6 +175,41 @@ ssbh_status ssbh_sample_sifted(ssbh_ctx *ctx, const uint64_t *d_in,
                                uint64_t *d_word_off, int32_t *d_status,
                                void *stream);
 
+/* Key length of a GEAT-analysed protocol (host only): the generalised
+ * entropy accumulation bound (App. A) with the BBM92 min-tradeoff function
+ * of App. C, tangent to the entropy bound at e_tangent, for direct hashing
+ * (n_sub = 1) or for sampled sub-block hashing by Claim 1 (Sec. III.C): each
+ * of n_sub sub-protocols has f / n_sub and l / n_sub, eps_sec = n_sub eps' +
+ * eps_abort, and error-correction leakage and smoothing are split the same
+ * way.  The result is the total key length in bits (n_sub times the
+ * sub-protocol's), negative when no key can be extracted. */
+typedef struct {
+    double n_rounds;    /* N, rounds of the protocol                         */
+    double p_x;         /* testing probability p_X (p_Z = 1 - p_X)           */
+    double q_tol;       /* tolerated phase error rate                        */
+    double eta_tol;     /* tolerated detection probability                   */
+    double e_bit;       /* bit error rate (error-correction leakage)         */
+    double f_ec;        /* error-correction efficiency (>= 1)                */
+    double eps_sec;     /* secrecy of the whole protocol                     */
+    double eps_sm;      /* smoothing parameter of the whole protocol         */
+    double p_omega;     /* probability that the protocol passes              */
+    double d_x;         /* dimension of the output register X_i              */
+    double eps_abort;   /* abort chance eps_Omega' (sub-block method, else 0) */
+    uint32_t n_sub;     /* N_S; 1 = direct hashing                           */
+} ssbh_geat_params;
+
+/* Key length at a fixed Renyi parameter alpha in (1, 1.5) and tangent point
+ * e_tangent in (0, 0.5).  SSBH_E_INVAL for parameters outside their ranges
+ * (see the field comments; also 2 eps_sm < eps_sec - eps_abort). */
+ssbh_status ssbh_geat_key_length(const ssbh_geat_params *p, double alpha,
+                                 double e_tangent, double *key_bits);
+
+/* The largest key length over alpha and e_tangent (grid in log10(alpha - 1)
+ * and log10(e_tangent), then golden-section refinement); alpha and
+ * e_tangent (may be NULL) receive the maximiser. */
+ssbh_status ssbh_geat_optimise(const ssbh_geat_params *p, double *key_bits,
+                               double *alpha, double *e_tangent);
+
 /* Abort threshold L_S^UB (Sec. III.D), computed on the host.  A sifted
  * sub-block's length is Binomial(n_rounds, p_sift) (p_sift = chance that a
  * round is kept AND lands in that sub-block); the binomial tail bound of

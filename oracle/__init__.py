@@ -322,3 +322,89 @@ def hash_batch(sub, ln, wo, out_len, seed, seed_bits: int, stride: int,
     if rc < 0:
         raise ValueError("bad hash arguments")
     return out[: _nw(total)], int(rc)
+
+
+# ------------------------------------------- GEAT key length (App. A, C) ---
+#
+# Plain evaluation of the key length of App. C (BBM92, affine min-tradeoff
+# function tangent to the entropy bound at e_t) under the generalised EAT of
+# App. A, and its sub-block form by Claim 1 (Sec. III.C).  The figures of
+# Sec. IV need inputs the paper does not give (detection probability, error-
+# correction efficiency, d_X, p_Omega): parity with them is unpinned; the
+# formula is pinned by the properties in tests/test_oracle_pins.py.
+
+def _h2(x: float) -> float:
+    """Binary entropy in bits."""
+    if x <= 0.0 or x >= 1.0:
+        return 0.0
+    return -x * math.log2(x) - (1.0 - x) * math.log2(1.0 - x)
+
+
+def geat_g(eps: float) -> float:
+    """g(eps) = -log2(1 - sqrt(1 - eps^2)) (App. A), written as
+    -log2(eps^2 / (1 + sqrt(1 - eps^2))): the same number, without the
+    cancellation of 1 - sqrt(1 - eps^2) for small eps."""
+    return -math.log2(eps * eps / (1.0 + math.sqrt(1.0 - eps * eps)))
+
+
+def geat_terms(p: dict, e_t: float) -> dict:
+    """h, Max(f), Min(f), Var(f) of the App. C min-tradeoff function (the
+    sub-protocol's: f / N_S, Claim 1)."""
+    ns = float(p["n_sub"])
+    pz = 1.0 - p["p_x"]
+    base = pz * pz
+    h = base * p["eta_tol"] * (1.0 - _h2(e_t)
+                               - (p["q_tol"] - e_t) * math.log2(1.0 / e_t - 1.0))
+    fmax = base * (1.0 + math.log2(1.0 - e_t))
+    fmin = base * (1.0 + math.log2(e_t))
+    fvar = pz ** 4 / p["p_x"] ** 2 * (1.0 + math.log2(1.0 - e_t)) ** 2
+    return dict(h=h / ns, max=fmax / ns, min=fmin / ns, var=fvar / ns ** 2)
+
+
+def geat_key_length(p: dict, alpha: float, e_t: float) -> float:
+    """Total key length in bits: N_S times the sub-protocol's l~ (N_S = 1 is
+    direct hashing).  Per sub-protocol: eps' = (eps_sec - eps_abort) / N_S,
+    smoothing eps_sm / N_S and error-correction leakage / N_S."""
+    t = geat_terms(p, e_t)
+    ns = float(p["n_sub"])
+    N = p["n_rounds"]
+    dx = p["d_x"]
+    V = math.log2(2.0 * dx * dx + 1.0) + math.sqrt(2.0 + t["var"])
+    D = 2.0 * math.log2(dx) + t["max"] - t["min"]
+    a = alpha
+    kprime = ((2.0 - a) ** 3 / (6.0 * (3.0 - 2.0 * a) ** 3 * math.log(2.0))
+              * 2.0 ** ((a - 1.0) / (2.0 - a) * D)
+              * math.log(2.0 ** D + math.e ** 2) ** 3)
+    eps_sec = (p["eps_sec"] - p["eps_abort"]) / ns
+    eps_sm = p["eps_sm"] / ns
+    pz = 1.0 - p["p_x"]
+    leak = N * pz * pz * p["eta_tol"] * p["f_ec"] * _h2(p["e_bit"]) / ns
+    l_sub = (N * t["h"]
+             - N * (a - 1.0) * math.log(2.0) / (2.0 * (2.0 - a)) * V * V
+             - N * ((a - 1.0) / (2.0 - a)) ** 2 * kprime
+             - (geat_g(eps_sm) + a * math.log2(1.0 / p["p_omega"])) / (a - 1.0)
+             - leak + 1.0 - math.log2(1.0 / (eps_sec - 2.0 * eps_sm)))
+    return ns * l_sub
+
+
+def geat_optimise(p: dict) -> tuple[float, float, float]:
+    """Maximum of geat_key_length over alpha in (1, 1.5) and e_t in (0, 0.5):
+    a coarse grid in log10(alpha - 1) and log10(e_t), then Nelder-Mead from
+    the best grid point (scipy)."""
+    from scipy.optimize import minimize
+    ulo, uhi = -9.0, math.log10(0.5) - 1e-9
+    vlo, vhi = math.log10(p["q_tol"]) - 3.0, math.log10(0.5) - 1e-9
+
+    def neg(x):
+        u = min(max(x[0], ulo), uhi)
+        v = min(max(x[1], vlo), vhi)
+        return -geat_key_length(p, 1.0 + 10.0 ** u, 10.0 ** v)
+
+    grid = [(neg((u, v)), u, v) for u in np.linspace(ulo, uhi, 61)
+            for v in np.linspace(vlo, vhi, 61)]
+    _, u0, v0 = min(grid)
+    r = minimize(neg, [u0, v0], method="Nelder-Mead",
+                 options=dict(xatol=1e-10, fatol=1e-6, maxiter=4000))
+    u = min(max(r.x[0], ulo), uhi)
+    v = min(max(r.x[1], vlo), vhi)
+    return -neg((u, v)), 1.0 + 10.0 ** u, 10.0 ** v

@@ -109,6 +109,15 @@ def lib() -> ctypes.CDLL:
     L.ssbh_ub_threshold.argtypes = [_u64, ctypes.c_double, _u32,
                                     ctypes.c_double, ctypes.POINTER(_u64),
                                     ctypes.POINTER(ctypes.c_double)]
+    L.ssbh_geat_key_length.restype = _i32
+    L.ssbh_geat_key_length.argtypes = [ctypes.POINTER(GeatParams),
+                                       ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double)]
+    L.ssbh_geat_optimise.restype = _i32
+    L.ssbh_geat_optimise.argtypes = [ctypes.POINTER(GeatParams),
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     L.ssbh_hash_batch.restype = _i32
     L.ssbh_hash_batch.argtypes = [_vp, _vp, _u64, _vp, _vp, _u32, _u32, _u64,
                                   _u64, _vp, _vp, _u64, _u64, _u64, _u32, _vp,
@@ -468,6 +477,35 @@ def ub_threshold(n_rounds: int, p_sift: float, n_sub: int,
                                    float(eps), ctypes.byref(l_ub),
                                    ctypes.byref(at)))
     return int(l_ub.value), float(at.value)
+
+
+class GeatParams(ctypes.Structure):
+    """ssbh_geat_params."""
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "n_rounds", "p_x", "q_tol", "eta_tol", "e_bit", "f_ec", "eps_sec",
+        "eps_sm", "p_omega", "d_x", "eps_abort")] + [("n_sub", ctypes.c_uint32)]
+
+
+def _geat_params(params: dict) -> GeatParams:
+    return GeatParams(**{k: params[k] for k, _ in GeatParams._fields_})
+
+
+def geat_key_length(params: dict, alpha: float, e_tangent: float) -> float:
+    """ssbh_geat_key_length: total key length (bits) at fixed alpha, e_t."""
+    out = ctypes.c_double()
+    p = _geat_params(params)
+    _check(lib().ssbh_geat_key_length(ctypes.byref(p), float(alpha),
+                                      float(e_tangent), ctypes.byref(out)))
+    return float(out.value)
+
+
+def geat_optimise(params: dict) -> tuple[float, float, float]:
+    """ssbh_geat_optimise: (key length, alpha, e_tangent) at the maximum."""
+    kb, a, e = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    p = _geat_params(params)
+    _check(lib().ssbh_geat_optimise(ctypes.byref(p), ctypes.byref(kb),
+                                    ctypes.byref(a), ctypes.byref(e)))
+    return float(kb.value), float(a.value), float(e.value)
 
 
 def status_name(code: int) -> str:

@@ -494,3 +494,73 @@ def test_ub_threshold_is_the_smallest_valid_threshold(orc, n, p, ns, eps):
         assert ns * orc.ub_tail(n, p, L - 1) > eps
     # The union bound with the exact tail holds as well.
     assert ns * float(binom.sf(L, n, p)) <= eps
+
+
+# ------------------------------------------------ GEAT key length pins ---
+
+GEAT_BASE = dict(n_rounds=1e9, p_x=0.02, q_tol=0.0082, eta_tol=1.0, e_bit=0.058,
+                 f_ec=1.16, eps_sec=1e-6, eps_sm=1e-7, p_omega=1.0, d_x=3.0,
+                 eps_abort=0.0, n_sub=1)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-8, 1e-12, 1e-20])
+def test_geat_g_matches_high_precision(orc, eps):
+    """g(eps) = -log2(1 - sqrt(1 - eps^2)) (App. A) against an 80-digit
+    decimal evaluation of that very expression."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 80
+    e = Decimal(eps)
+    val = -(1 - (1 - e * e).sqrt()).ln() / Decimal(2).ln()
+    assert orc.geat_g(eps) == pytest.approx(float(val), rel=1e-13)
+
+
+@pytest.mark.parametrize("q", [0.005, 0.0082, 0.05, 0.2])
+def test_geat_tradeoff_is_tangent_below_the_entropy_bound(orc, q):
+    """App. C: the affine min-tradeoff function is the tangent, at e_t, of
+    the convex 1 - h2(e) at the tolerated error Q, so it never exceeds
+    pZ^2 eta (1 - h2(Q)) and meets it exactly at e_t = Q."""
+    p = dict(GEAT_BASE, q_tol=q, eta_tol=0.7)
+    bound = (1 - p["p_x"]) ** 2 * 0.7 * (1 - (-q * math.log2(q)
+                                              - (1 - q) * math.log2(1 - q)))
+    assert orc.geat_terms(p, q)["h"] == pytest.approx(bound, rel=1e-14)
+    for e in np.linspace(1e-4, 0.499, 200):
+        assert orc.geat_terms(p, float(e))["h"] <= bound * (1 + 1e-14)
+    assert orc.geat_terms(p, q * 0.9)["h"] < bound
+    assert orc.geat_terms(p, min(0.49, q * 1.1))["h"] < bound
+
+
+def test_geat_rate_tends_to_asymptotic_bbm92_rate(orc):
+    """As N grows, the optimised key rate l/N tends to the asymptotic rate
+    pZ^2 eta [1 - h2(Q) - f_EC h2(e_bit)] (the finite-size terms are
+    o(N)), from below."""
+    def h2(x):
+        return -x * math.log2(x) - (1 - x) * math.log2(1 - x)
+    p = dict(GEAT_BASE, eta_tol=0.9)
+    asym = (1 - p["p_x"]) ** 2 * 0.9 * (1 - h2(p["q_tol"]) - p["f_ec"] * h2(p["e_bit"]))
+    rates = []
+    for n in [1e8, 1e10, 1e12, 1e16]:
+        k, _, _ = orc.geat_optimise(dict(p, n_rounds=n))
+        rates.append(k / n)
+    assert all(r < asym for r in rates)
+    assert all(b > a for a, b in zip(rates, rates[1:]))
+    assert rates[-1] == pytest.approx(asym, rel=2e-3)
+
+
+def test_geat_diverges_at_both_ends_of_alpha(orc):
+    """App. A: the (g + alpha log2(1/p_Omega)) / (alpha - 1) term blows up as
+    alpha -> 1, K'(alpha) as alpha -> 3/2."""
+    best, a, e = orc.geat_optimise(GEAT_BASE)
+    assert best > 0 and 1 < a < 1.5 and 0 < e < 0.5
+    assert orc.geat_key_length(GEAT_BASE, 1 + 1e-13, e) < -1e10
+    assert orc.geat_key_length(GEAT_BASE, 1.5 - 1e-7, e) < -1e10
+
+
+def test_geat_sub_block_loss_is_small_and_grows_with_n_sub(orc):
+    """Claim 1 / Sec. IV: sampling into N_S sub-blocks costs key length,
+    more for more sub-blocks, but only a little at N_S = 20 (p_S = 0.05)."""
+    totals = []
+    for ns in [1, 2, 5, 10, 20, 50]:
+        p = dict(GEAT_BASE, n_sub=ns, eps_abort=1e-8 if ns > 1 else 0.0)
+        totals.append(orc.geat_optimise(p)[0])
+    assert all(b < a for a, b in zip(totals, totals[1:]))
+    assert totals[4] > 0.9 * totals[0]
