@@ -82,7 +82,7 @@ enum {
     SSBH_K_VALU = 1,          /* bit-sliced AND-XOR + popcount parity         */
     SSBH_K_MFMA_I8 = 2,       /* int8 matrix cores, int32 sums, then mod 2;
                                  only for a shared seed (seed_stride == 0)    */
-    SSBH_K_FFT = 3            /* middle product by double-precision FFTs,
+    SSBH_K_FFT = 3,           /* middle product by double-precision FFTs,
                                  every entry rounded and checked.  Shared
                                  seed of at most 2^31 bits: two sub-blocks
                                  per transform.  Seed stride S > 0 (at most
@@ -91,6 +91,11 @@ enum {
                                  n_j + m_cap - 1 <= the transform length of
                                  S (true when S >= n_max + m_cap - 1), else
                                  *d_status = SSBH_E_UNSUPPORTED              */
+    SSBH_K_MFMA_F4 = 4        /* fp4 (e2m1) matrix cores, 64 columns per
+                                 matrix op, fp32 sums (exact: the host
+                                 requires seed_bits + 1 - m_cap <= 2^24, so
+                                 every n_j <= 2^24), then mod 2; shared seed
+                                 only; schedules with an even MT            */
 };
 
 /* Limits of this build. */

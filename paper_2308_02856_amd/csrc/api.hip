@@ -236,7 +236,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         r.kernel = SSBH_K_VALU;
         return launch_hash_valu(ctx, ws, r, choose_valu(ctx, r), stream);
     }
-    if (q.kernel == SSBH_K_MFMA_I8) {
+    if (q.kernel == SSBH_K_MFMA_I8 || q.kernel == SSBH_K_MFMA_F4) {
         MfmaSchedule ms;
         if (ctx->forced_mfma[0]) {
             ms.mt = ctx->forced_mfma[0];
@@ -385,15 +385,20 @@ ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
                        n_sub, (unsigned long long)seed_stride);
     }
     if (seed_bits && !d_seed) SSBH_INVAL("d_seed is null");
-    if (kernel == SSBH_K_MFMA_I8 && seed_stride != 0)
-        SSBH_INVAL("the MFMA kernel needs a shared seed (seed_stride = 0)");
+    if ((kernel == SSBH_K_MFMA_I8 || kernel == SSBH_K_MFMA_F4) && seed_stride != 0)
+        SSBH_INVAL("the MFMA kernels need a shared seed (seed_stride = 0)");
+    if (kernel == SSBH_K_MFMA_F4 && seed_bits + 1 > (1ull << 24) + m_cap) {
+        set_error("the fp4 matrix kernel needs seed_bits + 1 - m_cap <= 2^24 "
+                  "(exact fp32 sums)");
+        return SSBH_E_UNSUPPORTED;
+    }
     if (kernel == SSBH_K_FFT &&
         fft_length(seed_stride ? seed_stride : seed_bits) > kMaxFftLength) {
         set_error("the FFT hash supports seeds (or seed strides) of at most "
                   "%llu bits", (unsigned long long)kMaxFftLength);
         return SSBH_E_UNSUPPORTED;
     }
-    if (kernel > SSBH_K_FFT) SSBH_INVAL("unknown kernel %u", kernel);
+    if (kernel > SSBH_K_MFMA_F4) SSBH_INVAL("unknown kernel %u", kernel);
     std::lock_guard<std::mutex> lk(ctx->mu);
     SSBH_CHECK_HIP(hipSetDevice(ctx->device));
     HashRequest q{d_sub, sub_capacity_words, d_len, d_word_off, n_sub,

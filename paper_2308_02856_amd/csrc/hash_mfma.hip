@@ -40,7 +40,9 @@ ssbh_status plan_only(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kKC = 2048;          // columns staged per chunk
 constexpr int kKCW = kKC / 32;     // 32-bit words per sub-block per chunk
@@ -313,6 +315,245 @@ void k_toeplitz_mfma(MfmaArgs a) {
     }
 }
 
+// fp4 variant (v_mfma_scale_f32_32x32x64_f8f6f4, e2m1 operands, unit
+// scales): 0 and 1 are exact e2m1 values (codes 0 and 2) and the fp32 sums
+// of 0/1 products stay exact integers below 2^24, so the low bit is the
+// parity for sub-blocks of fewer than 2^24 bits (checked on the host).  One
+// matrix op covers 64 columns: lane l (row or sub-block l%32) supplies the
+// 32 columns 32*(l/32) .. +31 of the step as nibbles of four registers.
+// Rows 32 apart at columns 32 apart share seed bits, so the A operand of
+// tile p at step s is the 32-bit seed window W(2s + h - p); a ring of MT
+// windows indexed by 2s - p (uniform across lanes) gets two new entries per
+// step, W(2s + h) and W(2s - 1 + h).
+__device__ __forceinline__ uint32_t spread8(uint32_t b) {   // bit i -> code 2
+    uint32_t t = b & 0xFFu;
+    t = (t | (t << 12)) & 0x000F000Fu;
+    t = (t | (t << 6)) & 0x03030303u;
+    t = (t | (t << 3)) & 0x11111111u;
+    return t << 1;
+}
+__device__ __forceinline__ v4i expand32_f4(uint32_t b) {
+    v4i r;
+    r.x = (int)spread8(b);
+    r.y = (int)spread8(b >> 8);
+    r.z = (int)spread8(b >> 16);
+    r.w = (int)spread8(b >> 24);
+    return r;
+}
+
+template <int MT, int NT, int WM, int OCC>
+__global__ __launch_bounds__(64 * WM) __attribute__((amdgpu_waves_per_eu(OCC)))
+void k_toeplitz_mfma_f4(MfmaArgs a) {
+    static_assert(MT % 2 == 0, "the window ring needs an even MT");
+    using TT = MfmaTile<MT, NT, WM>;
+    constexpr int BM = TT::BM, BN = TT::BN, NTH = TT::NTH, XS = TT::XS;
+    constexpr int WINW = TT::WINW, PFX = TT::PFX, PFW = TT::PFW;
+    constexpr int OBW = TT::OBW;
+    constexpr int U = MT / 2;                 // steps per ring turn
+    static_assert(BN * kKCW % NTH == 0, "staging must divide evenly");
+    static_assert(OBW <= XS, "epilogue image must fit the staging area");
+    __shared__ uint32_t xs[BN * XS];
+    __shared__ uint32_t win[WINW];
+    __shared__ uint64_t woff_s[BN], mlen_s[BN], ooff_s[BN];
+    __shared__ uint32_t nw_s[BN], tail_s[BN];
+    __shared__ uint64_t nmax_s, mmax_s;
+    if (*a.status) return;
+
+    const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t mt = t % a.m_tiles;
+    const uint32_t rest = t / a.m_tiles;
+    const uint32_t ks = rest % a.ksplit;
+    const uint32_t grp = rest / a.ksplit;
+    const int64_t R0 = (int64_t)mt * BM;
+    const uint32_t J0 = grp * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, li = lane & 31;
+
+    if (threadIdx.x == 0) { nmax_s = 0; mmax_s = 0; }
+    __syncthreads();
+    for (int jl = threadIdx.x; jl < BN; jl += NTH) {
+        const uint32_t j = J0 + jl;
+        uint64_t n = 0, m = 0, wo = 0, oo = 0;
+        if (j < a.ns) {
+            n = a.len[j]; m = a.mlen[j]; wo = a.woff[j]; oo = a.ooff[j];
+        }
+        woff_s[jl] = wo;
+        mlen_s[jl] = m;
+        ooff_s[jl] = oo;
+        nw_s[jl] = (uint32_t)((n + 31) / 32);
+        tail_s[jl] = (n & 31) ? ((1u << (n & 31)) - 1u) : ~0u;
+        if (n) atomicMax((unsigned long long *)&nmax_s, (unsigned long long)n);
+        if (m) atomicMax((unsigned long long *)&mmax_s, (unsigned long long)m);
+    }
+    __syncthreads();
+    const uint64_t nmax = nmax_s, mmax = mmax_s;
+    if (nmax == 0 || (uint64_t)R0 >= mmax) return;   // uniform
+    const uint32_t nwords = (uint32_t)((nmax + 31) / 32);
+    const uint32_t nchunks = (nwords + kKCW - 1) / kKCW;
+    const uint32_t c_lo = (uint32_t)((uint64_t)ks * nchunks / a.ksplit);
+    const uint32_t c_hi = (uint32_t)((uint64_t)(ks + 1) * nchunks / a.ksplit);
+    if (c_lo >= c_hi) return;                          // uniform
+    const uint32_t cw_begin = c_lo * kKCW;
+    const uint32_t cw_end = min(c_hi * (uint32_t)kKCW, nwords);
+    const int64_t R0w = R0 + (int64_t)wave * 32 * MT;
+
+    uint32_t pfx[PFX], pfw[PFW];
+    auto window_lo = [&](uint32_t cw0) -> int64_t {
+        const int64_t lo = 32 * (int64_t)cw0 - (R0 + BM - 1) + (int64_t)a.mcap -
+                           1 - (cw0 == cw_begin ? 32 * (MT - 1) : 0);
+        return lo >> 5;
+    };
+    auto prefetch = [&](uint32_t cw0) {
+#pragma unroll
+        for (int i = 0; i < PFX; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            const int jl = t / kKCW, w = t - jl * kKCW;
+            const uint32_t cw = cw0 + w;
+            uint32_t x = 0u;
+            if (cw < nw_s[jl]) {
+                x = a.sub32[2 * woff_s[jl] + cw];
+                if (cw == nw_s[jl] - 1) x &= tail_s[jl];
+            }
+            pfx[i] = x;
+        }
+        const int64_t lo_w = window_lo(cw0);
+#pragma unroll
+        for (int i = 0; i < PFW; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            const int64_t g = lo_w + t;
+            pfw[i] = (t < WINW && g >= 0 && g < a.seed_w32) ? a.seed32[g] : 0u;
+        }
+    };
+
+    v16f acc[MT][NT];
+#pragma unroll
+    for (int p = 0; p < MT; ++p)
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[p][q][r] = 0.0f;
+    v4i ring[MT];
+
+    prefetch(cw_begin);
+    for (uint32_t cw0 = cw_begin; cw0 < cw_end; cw0 += kKCW) {
+#pragma unroll
+        for (int i = 0; i < PFX; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            const int jl = t / kKCW, w = t - jl * kKCW;
+            xs[jl * XS + w] = pfx[i];
+        }
+#pragma unroll
+        for (int i = 0; i < PFW; ++i) {
+            const int t = threadIdx.x + i * NTH;
+            if (t < WINW) win[t] = pfw[i];
+        }
+        const int64_t lo_w = window_lo(cw0);
+        __syncthreads();
+        if (cw0 + kKCW < cw_end) prefetch(cw0 + kKCW);
+
+        // Seed window W(t) for this lane's row at tile 0: bits at column
+        // 32 cw0 + 32 t of the chunk.
+        const int64_t e = 32 * (int64_t)cw0 - (R0w + li) + (int64_t)a.mcap - 1 -
+                          (lo_w << 5);
+        const int qa = (int)(e >> 5);
+        const uint32_t sha = (uint32_t)(e & 31);
+        auto W = [&](int tt) {
+            return expand32_f4(__builtin_amdgcn_alignbit(win[qa + tt + 1],
+                                                         win[qa + tt], sha));
+        };
+        if (cw0 == cw_begin) {
+            // Slots -2 .. -(MT-1): W(h - p) for tiles p = 2 .. MT-1 at step 0.
+#pragma unroll
+            for (int p = 2; p < MT; ++p) ring[MT - p] = W(h - p);
+        }
+        const uint32_t words = min((uint32_t)kKCW, cw_end - cw0);
+        const uint32_t steps = ((words + 1) / 2 + U - 1) / U * U;
+        v4i a0_next, a1_next, b_next[NT];
+        auto build = [&](uint32_t s, v4i &a0, v4i &a1, v4i (&bn)[NT]) {
+            // Step s' <= steps - 1 keeps every LDS read inside its row; the
+            // operands built for the step after the last are never used.
+            const uint32_t sc = min(s, steps - 1);
+            a0 = W(2 * (int)sc + h);
+            a1 = W(2 * (int)sc - 1 + h);
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                bn[q] = expand32_f4(xs[(32 * q + li) * XS + 2 * sc + h]);
+        };
+        build(0, a0_next, a1_next, b_next);
+        for (uint32_t s0 = 0; s0 < steps; s0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t s = s0 + u;
+                ring[(2 * u) % MT] = a0_next;
+                ring[(2 * u - 1 + MT) % MT] = a1_next;
+                v4i bcur[NT];
+#pragma unroll
+                for (int q = 0; q < NT; ++q) bcur[q] = b_next[q];
+                build(s + 1, a0_next, a1_next, b_next);
+#pragma unroll
+                for (int p = 0; p < MT; ++p) {
+                    const v4i ar = ring[(2 * u - p + 2 * MT) % MT];
+                    v8i A8 = {ar.x, ar.y, ar.z, ar.w, 0, 0, 0, 0};
+#pragma unroll
+                    for (int q = 0; q < NT; ++q) {
+                        v8i B8 = {bcur[q].x, bcur[q].y, bcur[q].z, bcur[q].w,
+                                  0, 0, 0, 0};
+                        acc[p][q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            A8, B8, acc[p][q], 4, 4, 0, 127, 0, 127);
+                    }
+                }
+                __builtin_amdgcn_sched_group_barrier(0x100, 1 + NT, 0);
+#pragma unroll
+                for (int k = 0; k < MT * NT; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    uint32_t *ob = xs;
+#pragma unroll
+    for (int p = 0; p < MT; ++p) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            uint32_t mine = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                mine |= ((uint32_t)(int)acc[p][q][r] & 1u)
+                        << (8 * (r / 4) + 4 * h + (r % 4));
+            const uint32_t word = mine | (uint32_t)__shfl_xor((int)mine, 32, 64);
+            const int jl = 32 * q + li;
+            const int64_t nvalid = (int64_t)mlen_s[jl] - (R0w + 32 * p);
+            uint32_t v = nvalid > 0 ? word : 0u;
+            if (nvalid > 0 && nvalid < 32) v &= (1u << nvalid) - 1u;
+            if (h == 0) ob[jl * OBW + wave * MT + p] = v;
+        }
+    }
+    for (int jl = threadIdx.x; jl < BN; jl += NTH) ob[jl * OBW + OBW - 1] = 0u;
+    __syncthreads();
+    const bool owner = a.ksplit == 1;
+    for (int idx = threadIdx.x; idx < BN * OBW; idx += NTH) {
+        const int jl = idx / OBW, k = idx - jl * OBW;
+        const uint64_t m = mlen_s[jl];
+        if (m <= (uint64_t)R0) continue;
+        const uint64_t nb = min(m - (uint64_t)R0, (uint64_t)BM);
+        const uint64_t P = ooff_s[jl] + (uint64_t)R0;
+        const uint32_t sh = (uint32_t)(P & 31);
+        const uint64_t wq0 = P >> 5;
+        if ((uint64_t)k > ((P + nb - 1) >> 5) - wq0) continue;
+        const uint32_t *row = ob + jl * OBW;
+        uint32_t val = row[k];
+        if (sh) val = (val << sh) | (k ? row[k - 1] >> (32 - sh) : 0u);
+        const uint64_t wstart = 32 * (wq0 + (uint64_t)k);
+        if (owner && wstart >= P && wstart + 32 <= P + nb)
+            a.out32[wq0 + k] = val;
+        else if (val)
+            atomicXor(a.out32 + wq0 + k, val);
+    }
+}
+
 // K splits per tile: enough tiles in flight to fill every CU in whole
 // rounds (a short last round idles most of the chip), at least 8 K chunks
 // per split.
@@ -328,7 +569,7 @@ uint32_t choose_ksplit(uint64_t tiles, uint64_t slots, uint64_t nchunks) {
     return best;
 }
 
-template <int MT, int NT, int WM, int OCC>
+template <int MT, int NT, int WM, int OCC, bool F4>
 ssbh_status run_mfma(ssbh_ctx *ctx, const MfmaArgs &ma, uint32_t ksplit,
                      uint64_t ncap, hipStream_t stream) {
     using TT = MfmaTile<MT, NT, WM>;
@@ -346,8 +587,14 @@ ssbh_status run_mfma(ssbh_ctx *ctx, const MfmaArgs &ma, uint32_t ksplit,
         set_error("MFMA grid too large");
         return SSBH_E_UNSUPPORTED;
     }
-    hipLaunchKernelGGL((k_toeplitz_mfma<MT, NT, WM, OCC>), dim3((uint32_t)grid),
-                       dim3(64 * WM), 0, stream, m);
+    if constexpr (F4) {
+        if constexpr (MT % 2 == 0)
+            hipLaunchKernelGGL((k_toeplitz_mfma_f4<MT, NT, WM, OCC>),
+                               dim3((uint32_t)grid), dim3(64 * WM), 0, stream, m);
+    } else {
+        hipLaunchKernelGGL((k_toeplitz_mfma<MT, NT, WM, OCC>), dim3((uint32_t)grid),
+                           dim3(64 * WM), 0, stream, m);
+    }
     SSBH_CHECK_HIP(hipGetLastError());
     return SSBH_OK;
 }
@@ -363,8 +610,9 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
-    snprintf(ws.last_schedule, sizeof ws.last_schedule, "mfma:%d:%d:%d:%d",
-             s.mt, s.nt, s.wm, s.ksplit);
+    const bool f4 = q.kernel == SSBH_K_MFMA_F4;
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "%s:%d:%d:%d:%d",
+             f4 ? "mfma4" : "mfma", s.mt, s.nt, s.wm, s.ksplit);
     if (!q.n_sub) return st;
     MfmaArgs ma{};
     uint64_t *plan = ws.plan.as<uint64_t>();
@@ -383,10 +631,18 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
     // Mean sub-block length from the buffer capacity: the split count only
     // needs an estimate of the K chunks per tile.
     const uint64_t ncap = 64ull * q.sub_cap / q.n_sub + 64;
-    TimedLaunch timed(ws.timer, "k_toeplitz_mfma", stream);
+    if (f4 && (s.mt % 2 != 0)) {
+        set_error("the fp4 matrix kernel needs an even MT");
+        return SSBH_E_UNSUPPORTED;
+    }
+    TimedLaunch timed(ws.timer, f4 ? "k_toeplitz_mfma_f4" : "k_toeplitz_mfma",
+                      stream);
 #define SSBH_MFMA_CASE(A, B, C, O)                                            \
     if (s.mt == A && s.nt == B && s.wm == C)                                  \
-        return run_mfma<A, B, C, O>(ctx, ma, (uint32_t)s.ksplit, ncap, stream);
+        return f4 ? run_mfma<A, B, C, O, true>(ctx, ma, (uint32_t)s.ksplit,  \
+                                               ncap, stream)                  \
+                  : run_mfma<A, B, C, O, false>(ctx, ma, (uint32_t)s.ksplit, \
+                                                ncap, stream);
     SSBH_MFMA_CASE(8, 2, 4, 1)
     SSBH_MFMA_CASE(4, 4, 4, 1)
     SSBH_MFMA_CASE(4, 2, 4, 2)

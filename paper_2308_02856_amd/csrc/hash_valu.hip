@@ -493,7 +493,7 @@ ScratchSizes hash_scratch(const ssbh_ctx *ctx, const HashRequest &q) {
     ScratchSizes z;
     z.plan = (size_t)q.n_sub * 3 * 8 + 64;
     z.counters = 64;
-    if (q.kernel == SSBH_K_MFMA_I8) {
+    if (q.kernel == SSBH_K_MFMA_I8 || q.kernel == SSBH_K_MFMA_F4) {
         z.tiles = 64;
         return z;
     }

@@ -25,7 +25,7 @@ E_INVAL, E_ABORT_OVERSIZE, E_NOMEM, E_DEVICE, E_UNKNOWN_JOB, E_UNSUPPORTED = (
 E_PRECISION = -7
 SAMPLE_IID, SAMPLE_PERMUTE, SAMPLE_EXPLICIT = 0, 1, 2
 OUT_FIXED, OUT_RATIO, OUT_EXPLICIT = 0, 1, 2
-K_AUTO, K_VALU, K_MFMA_I8, K_FFT = 0, 1, 2, 3
+K_AUTO, K_VALU, K_MFMA_I8, K_FFT, K_MFMA_F4 = 0, 1, 2, 3, 4
 
 _STATUS_NAMES = {OK: "OK", PENDING: "PENDING", E_INVAL: "E_INVAL",
                  E_ABORT_OVERSIZE: "E_ABORT_OVERSIZE", E_NOMEM: "E_NOMEM",
