@@ -37,6 +37,7 @@ CLOCK_GHZ = 2.4          # MI355X peak engine clock
 LANES_PER_CU_CLK = 128   # 32-bit VALU lanes retired per CU per clock
 BITOPS_PER_LANE_OP = 32  # v_bitop3_b32: 32 AND-XOR bit-products per lane
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak (TOP/s)
+FP4_PEAK_TFLOPS = 10100.0  # MI355X dense fp4 matrix peak (TFLOP/s)
 HBM_PEAK_GBS = 8000.0    # MI355X HBM3E peak (GB/s)
 
 KERNEL_SOURCES = {"k_toeplitz_valu": "hash_valu.hip",
@@ -394,20 +395,24 @@ def run_contraction(ctx, ssbh, args, peak_alu):
                        out_capacity_bits=ns * m, total=tot, status=st,
                        reset_status=False, kernel=kern)
 
+    out4 = torch.empty_like(out)
     sample()
     hash_(ssbh.K_MFMA_I8, out)
     hash_(ssbh.K_VALU, outv)
     hash_(ssbh.K_FFT, outf)
+    hash_(ssbh.K_MFMA_F4, out4)
     torch.cuda.synchronize()
     same = bool(torch.equal(out, outv)) and int(st.item()) == 0
     same_fft = bool(torch.equal(out, outf))
+    same_f4 = bool(torch.equal(out, out4))
     g_ms = float(np.mean(time_events(sample, 3)))
     mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
     mfma_sched = ctx.last_schedule()
+    f4_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_F4, out4), 3)))
     va_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
     ff_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_FFT, outf), 3)))
     prods = L * m * ns
-    del d_in, perm, sub, out, outv, outf
+    del d_in, perm, sub, out, outv, outf, out4
     torch.cuda.empty_cache()
     return {
         "workload": "contraction", "n_bits": n, "n_sub": ns, "sub_bits": L,
@@ -422,8 +427,12 @@ def run_contraction(ctx, ssbh, args, peak_alu):
         "fft_ms": round(ff_ms, 3),
         "gbps_step_fft": round(n / ((g_ms + ff_ms) * 1e-3) / 1e9, 3),
         "gbps_hash_fft": round(n / (ff_ms * 1e-3) / 1e9, 3),
+        "mfma_f4_ms": round(f4_ms, 3),
+        "mfma_f4_tops": round(2 * prods / (f4_ms * 1e-3) / 1e12, 1),
+        "mfma_f4_frac": round(2 * prods / (f4_ms * 1e-3) / 1e12 / FP4_PEAK_TFLOPS, 4),
         "mfma_equals_valu": same,
         "fft_equals_mfma": same_fft,
+        "mfma_f4_equals_int8": same_f4,
         "mfma_traffic": load_traffic("k_toeplitz_mfma", "contraction",
                                      mfma_sched),
     }
