@@ -235,63 +235,6 @@ __device__ __forceinline__ int lds_addr(int f, int e) {
     else return e ^ ((e >> 3) & 7);
 }
 
-// Twiddles w^r, r < R, of w = w_N^base from the table of w_N^k (conjugated
-// for the inverse): the powers w^(2^b) from the table, every other power as
-// a product of them (r = 2^b + rest: w^r = w^(2^b) w^rest).
-template <int R, bool INV>
-__device__ __forceinline__ void twiddle(double2 (&v)[R], int base,
-                                        const double2 *tw) {
-    auto ld = [&](int k) { double2 w = tw[k]; return INV ? conj2(w) : w; };
-    double2 p2[4];
-#pragma unroll
-    for (int b = 0; (1 << b) < R; ++b) p2[b] = ld((1 << b) * base);
-    double2 wr[R];
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-        const int hb = ilog2c(r);
-        const int rest = r - (1 << hb);
-        wr[r] = rest ? cmul(p2[hb], wr[rest]) : p2[hb];
-        v[r] = cmul(v[r], wr[r]);
-    }
-}
-
-// One radix-R Stockham stage over F FFTs of length N.  Group j of an FFT
-// takes elements j + r N/R (from `ld`), twiddles them by w_{Ns R}^(r (j mod
-// Ns)), transforms, and hands element (j / Ns) Ns R + (j mod Ns) + r Ns to
-// `st`.  MID: barrier between all loads and all stores (they share the LDS
-// buffer); END: barrier after the stores (the next stage reads them).
-template <int N, int R, int F, bool INV, bool MID, bool END, class Ld, class St>
-__device__ __forceinline__ void fft_stage(int span, const double2 *tw, Ld ld,
-                                          St st) {
-    constexpr int G = N / R;
-    constexpr int TOTAL = F * G;
-    constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
-    double2 v[PER][R];
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int g = threadIdx.x + kThreads * p;
-        if (TOTAL % kThreads == 0 || g < TOTAL) {
-            const int f = g % F, j = g / F;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[p][r] = ld(f, j + r * G);
-            if (span > 1) twiddle<R, INV>(v[p], (j % span) * (N / (span * R)), tw);
-            dftR<R, INV>(v[p]);
-        }
-    }
-    if (MID) __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int g = threadIdx.x + kThreads * p;
-        if (TOTAL % kThreads == 0 || g < TOTAL) {
-            const int f = g % F, j = g / F;
-            const int d = (j / span) * span * R + (j % span);
-#pragma unroll
-            for (int r = 0; r < R; ++r) st(f, d + r * span, v[p][r]);
-        }
-    }
-    if (END) __syncthreads();
-}
-
 // Stage radices of an N-point FFT, N = 2^a or 3 * 2^a: radix 8 while it
 // divides the power of two; the remaining 2 or 4 is merged with the 3 into
 // one radix-6 or radix-12 stage, or is a stage of its own when there is no 3.
@@ -304,36 +247,137 @@ constexpr int radix_of(int n, int s) {
     return s < pow2_bits(n) / 3 ? 8
          : (n % 3 == 0 ? 3 : 1) * (1 << (pow2_bits(n) % 3));
 }
+// Span (product of the radices before it) of stage s.
+constexpr int span_of(int n, int s) {
+    return s == 0 ? 1 : span_of(n, s - 1) * radix_of(n, s - 1);
+}
+// The powers w^(2^b), b < tw_bits(R), give every twiddle w^r with r < R.
+constexpr int tw_bits(int r) { return ilog2c(r - 1) + 1; }
+
+// Work of one stage: item g = threadIdx.x + kThreads * i (i < PER) is group
+// j = g / F of FFT f = g % F, if g < TOTAL.
+template <int N, int R, int F> struct StageShape {
+    static constexpr int G = N / R;
+    static constexpr int TOTAL = F * G;
+    static constexpr int PER = (TOTAL + kThreads - 1) / kThreads;
+    static constexpr bool active(int g) { return TOTAL % kThreads == 0 || g < TOTAL; }
+};
+
+__device__ __forceinline__ double2 csq(double2 a) {
+    return make_double2(fma(a.x, a.x, -a.y * a.y), 2.0 * a.x * a.y);
+}
+
+// Twiddles of stage S (S >= 1) for group j: v[r] *= w^r, r < R, with
+// w = w_(SPAN R)^(j mod SPAN) = w_N^base, base = (j mod SPAN) N / (SPAN R),
+// from the table of w_N^k (conjugated for the inverse).  One table read per
+// group: w^(2^b) by repeated squaring, every other power as w^(2^b) w^rest
+// (r = 2^b + rest); a few roundings more than reading every power, and one
+// vector-memory instruction instead of several.  With F >= 64 interleaved
+// FFTs j is the same on a whole wavefront.
+template <int N, int F, int S, bool INV, int R>
+__device__ __forceinline__ void twiddle(double2 (&v)[R], int j,
+                                        const double2 *tw) {
+    constexpr int SPAN = span_of(N, S);
+    int base = (j % SPAN) * (N / (SPAN * R));
+    if constexpr (F % 64 == 0) base = __builtin_amdgcn_readfirstlane(base);
+    double2 pw[tw_bits(R)];
+    pw[0] = tw[base];
+    if (INV) pw[0] = conj2(pw[0]);
+#pragma unroll
+    for (int b = 1; b < tw_bits(R); ++b) pw[b] = csq(pw[b - 1]);
+    double2 wr[R];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const int hb = ilog2c(r);
+        const int rest = r - (1 << hb);
+        wr[r] = rest ? cmul(pw[hb], wr[rest]) : pw[hb];
+        v[r] = cmul(v[r], wr[r]);
+    }
+}
+
+// Stage S (radix R, span Ns) of F Stockham FFTs of length N.  Group j of an
+// FFT takes elements j + r N/R (from `ld`), twiddles them by w_{Ns R}^(r (j
+// mod Ns)), transforms, and hands its R results to `st(f, d, Ns, v)`: v[r]
+// is element d + r Ns, d = (j / Ns) Ns R + (j mod Ns).  Barrier between all
+// loads and all stores (they share the LDS buffer); END: barrier after the
+// stores (the next stage reads them).
+template <int N, int F, bool INV, int S, bool END, class Ld, class St>
+__device__ __forceinline__ void fft_stage(const double2 *tw, Ld ld, St st) {
+    constexpr int R = radix_of(N, S), SPAN = span_of(N, S);
+    using SH = StageShape<N, R, F>;
+    double2 v[SH::PER][R];
+#pragma unroll
+    for (int i = 0; i < SH::PER; ++i) {
+        const int g = threadIdx.x + kThreads * i;
+        if (SH::active(g)) {
+            const int f = g % F, j = g / F;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = ld(f, j + r * SH::G);
+            if constexpr (S > 0) twiddle<N, F, S, INV>(v[i], j, tw);
+            dftR<R, INV>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SH::PER; ++i) {
+        const int g = threadIdx.x + kThreads * i;
+        if (SH::active(g)) {
+            const int f = g % F, j = g / F;
+            st(f, (j / SPAN) * SPAN * R + (j % SPAN), SPAN, v[i]);
+        }
+    }
+    if (END) __syncthreads();
+}
 
 template <int N, int F, bool INV, int S, class Ld, class St, class LL, class LS>
-__device__ __forceinline__ void fft_stages(int span, const double2 *tw,
-                                           Ld first_ld, St last_st, LL lds_ld,
-                                           LS lds_st) {
+__device__ __forceinline__ void fft_stages(const double2 *tw, Ld first_ld,
+                                           St last_st, LL lds_ld, LS lds_st) {
     constexpr int NST = num_stages(N);
-    constexpr int R = radix_of(N, S);
-    if constexpr (S == 0)
-        fft_stage<N, R, F, INV, true, true>(span, tw, first_ld, lds_st);
-    else if constexpr (S == NST - 1)
-        fft_stage<N, R, F, INV, true, false>(span, tw, lds_ld, last_st);
-    else
-        fft_stage<N, R, F, INV, true, true>(span, tw, lds_ld, lds_st);
-    if constexpr (S + 1 < NST)
-        fft_stages<N, F, INV, S + 1>(span * R, tw, first_ld, last_st, lds_ld,
-                                     lds_st);
+    if constexpr (S == NST - 1) {
+        fft_stage<N, F, INV, S, false>(tw, lds_ld, last_st);
+    } else {
+        if constexpr (S == 0)
+            fft_stage<N, F, INV, S, true>(tw, first_ld, lds_st);
+        else
+            fft_stage<N, F, INV, S, true>(tw, lds_ld, lds_st);
+        fft_stages<N, F, INV, S + 1>(tw, first_ld, last_st, lds_ld, lds_st);
+    }
+}
+
+// Number of elements of a group handed to a store functor.
+template <class V> constexpr int group_size(const V &) {
+    return sizeof(V) / sizeof(double2);
 }
 
 // A whole FFT of length N (2^a or 3 * 2^a, N >= 64) over F transforms, with
 // the twiddle table of w_N^k: the first stage reads with `first_ld`, the last
-// stage writes with `last_st`, the stages between go through the LDS buffer.
-// Every stage has a barrier between its loads and stores (first_ld and
-// last_st may touch the same buffer) and the inner ones one after the stores.
+// stage writes its groups with `last_st`, the stages between go through the
+// LDS buffer.  Every stage has a barrier between its loads and stores
+// (first_ld and last_st may touch the same buffer) and the inner ones one
+// after the stores.
 template <int N, int F, bool INV, class Ld, class St>
 __device__ __forceinline__ void fft_run(double2 *buf, const double2 *tw,
                                         Ld first_ld, St last_st) {
     static_assert(num_stages(N) >= 2, "at least two stages");
     auto lds_ld = [&](int f, int e) { return buf[lds_addr<F>(f, e)]; };
-    auto lds_st = [&](int f, int e, double2 x) { buf[lds_addr<F>(f, e)] = x; };
-    fft_stages<N, F, INV, 0>(1, tw, first_ld, last_st, lds_ld, lds_st);
+    auto lds_st = [&](int f, int d, int span, auto &v) {
+#pragma unroll
+        for (int r = 0; r < group_size(v); ++r)
+            buf[lds_addr<F>(f, d + r * span)] = v[r];
+    };
+    fft_stages<N, F, INV, 0>(tw, first_ld, last_st, lds_ld, lds_st);
+}
+
+// Hands v[r] w0 w^r to put(r, .) for the group's r = 0, 1, ..: the powers of
+// w by repeated multiplication (at most 11 factors, a few roundings).
+template <int R, class Put>
+__device__ __forceinline__ void twiddle_run(const double2 (&v)[R], double2 w0,
+                                            double2 w, Put put) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        put(r, cmul(v[r], w0));
+        if (r + 1 < R) w0 = cmul(w0, w);
+    }
 }
 
 __device__ __forceinline__ double2 omega_l(const FftArgs &a, uint64_t e) {
@@ -406,9 +450,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
         return make_double2((double)((win[0][e] >> f) & 1ull),
                             (double)((win[1][e] >> f) & 1ull));
     };
-    auto st = [&](int f, int k1, double2 x) {
+    // Output k1 of column n2i = c0 + f gets w_L^(n2i k1); a group's outputs
+    // k1 = k0 + r span take w_L^(n2i k0) (w_L^(n2i span))^r.
+    auto st = [&](int f, int k0, int span, auto &v) {
         const uint64_t n2i = c0 + f;
-        y[(size_t)k1 * n2 + n2i] = cmul(x, omega_l(a, n2i * k1));
+        twiddle_run(v, omega_l(a, n2i * k0), omega_l(a, n2i * span),
+                    [&](int r, double2 x) { y[(size_t)(k0 + r * span) * n2 + n2i] = x; });
     };
     fft_run<kN1, kN1, false>(buf, a.tw64, ld, st);
 }
@@ -418,8 +465,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
 // w_(64 N2)^(-e (row mod 64)) -- the inverse of the twiddle of the column
 // pass that made the row (k_fft_cols with two levels, the last k_fft_mid
 // with three or four).
+// Waves per SIMD that the LDS of an N2-point row allows (three workgroups of
+// eight waves at most, 160 KiB per CU); the register budget follows from it.
+constexpr int rows_waves(int n2) {
+    return 2 * std::min(3, (160 * 1024) / (n2 * 16));
+}
 template <int N2, bool SPEC>
-__global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(rows_waves(N2)))) void k_fft_rows(FftArgs a) {
     __shared__ double2 buf[N2];
     if (*a.status) return;
     const uint32_t row = blockIdx.x;
@@ -430,18 +483,29 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(FftArgs a) {
     auto gl_ld = [&](int, int e) { return y[e]; };
     auto lds_ld = [&](int, int e) { return buf[lds_addr<1>(0, e)]; };
     if (SPEC) {
-        auto spec_st = [&](int, int e, double2 x) { sp[e] = x; };
+        auto spec_st = [&](int, int e0, int span, auto &v) {
+#pragma unroll
+            for (int r = 0; r < group_size(v); ++r) sp[e0 + r * span] = v[r];
+        };
         fft_run<N2, 1, false>(buf, a.twr, gl_ld, spec_st);
         return;
     }
     // Forward, the spectrum product fused into the last stage's stores.
-    auto mul_st = [&](int, int e, double2 x) {
-        buf[lds_addr<1>(0, e)] = cmul(x, sp[e]);
+    auto mul_st = [&](int, int e0, int span, auto &v) {
+#pragma unroll
+        for (int r = 0; r < group_size(v); ++r) {
+            const int e = e0 + r * span;
+            buf[lds_addr<1>(0, e)] = cmul(v[r], sp[e]);
+        }
     };
     fft_run<N2, 1, false>(buf, a.twr, gl_ld, mul_st);
     __syncthreads();
-    auto out_st = [&](int, int e, double2 x) {
-        y[e] = cmul(x, conj2(omega_r(a, (uint64_t)e * k1)));
+    // Element e = e0 + r span takes conj(w^(e0 k1)) conj(w^(span k1))^r,
+    // w = w_(64 N2).
+    auto out_st = [&](int, int e0, int span, auto &v) {
+        twiddle_run(v, conj2(omega_r(a, (uint64_t)e0 * k1)),
+                    conj2(omega_r(a, (uint64_t)span * k1)),
+                    [&](int r, double2 x) { y[e0 + r * span] = x; });
     };
     fft_run<N2, 1, true>(buf, a.twr, lds_ld, out_st);
 }
@@ -472,11 +536,17 @@ __global__ __launch_bounds__(kThreads) void k_fft_mid(FftArgs a) {
     const uint32_t pl = blockIdx.z;
     double2 *y = a.work + (size_t)pl * a.L + (size_t)p * P;
     auto ld = [&](int f, int e) { return y[(size_t)e * C + c0 + f]; };
-    auto st = [&](int f, int k, double2 x) {
+    // A group's outputs k = k0 + r span: the twiddle's exponent grows by a
+    // fixed step per r, so it is a running product.
+    auto st = [&](int f, int k0, int span, auto &v) {
         const uint64_t m = c0 + f;
-        const double2 w = INV ? conj2(omega_d(a, d - 1, ((uint64_t)k * C + m) * kp))
-                              : omega_d(a, d, m * (uint64_t)k);
-        y[(size_t)k * C + m] = cmul(x, w);
+        const double2 w0 = INV ? conj2(omega_d(a, d - 1, ((uint64_t)k0 * C + m) * kp))
+                               : omega_d(a, d, m * (uint64_t)k0);
+        const double2 ws = INV ? conj2(omega_d(a, d - 1, (uint64_t)span * C * kp))
+                               : omega_d(a, d, m * (uint64_t)span);
+        twiddle_run(v, w0, ws, [&](int r, double2 x) {
+            y[(size_t)(k0 + r * span) * C + m] = x;
+        });
     };
     fft_run<kN1, kN1, INV>(buf, a.tw64, ld, st);
 }
@@ -525,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     bool bad = false;
     auto ld = [&](int f, int e) { return w[(size_t)e * n2 + c0 + f]; };
     // Called with the same row n1 on all 64 lanes (f = lane).
-    auto st = [&](int f, int n1, double2 x) {
+    auto st1 = [&](int f, int n1, double2 x) {
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
             if (!has[part]) continue;                        // uniform
@@ -543,6 +613,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
             const uint64_t word = __brevll(ballot64(bit));  // bit t = row rlo + t
             if (lane == 0) put_rows(a.out, o[part], rlo, word);
         }
+    };
+    auto st = [&](int f, int n0, int span, auto &v) {
+#pragma unroll
+        for (int r = 0; r < group_size(v); ++r) st1(f, n0 + r * span, v[r]);
     };
     fft_run<kN1, kN1, true>(buf, a.tw64, ld, st);
     if (bad) atomicCAS(a.status, 0, (int32_t)SSBH_E_PRECISION);
