@@ -27,15 +27,17 @@
 //                (64 x 64 x 64 x L/2^18, L > 3 * 2^23), forward and inverse.
 //   k_fft_rows   row FFT (64 .. 8192 points), times the seed spectrum,
 //                inverse FFT, times the inverse of the row's twiddle, store
-//                (one pass over the data).
+//                (one pass over the data; radix-16 stages, the last forward
+//                stage and the first inverse one share registers).
 //   k_fft_out    inverse 64-point FFTs down the columns, 1/L, round, parity;
 //                64 consecutive output rows per wavefront ballot.
 // The seed spectrum comes from the same forward passes.  LDS FFTs are
-// Stockham autosort stages with radix-8 butterflies in registers (then one
-// radix 2, 3, 4, 6 or 12 stage for the rest), twiddles from tables of w_N^k;
-// the first stage of each pass reads global memory (or bits) and the last
-// one writes its result straight out (spectrum product, twiddle, or parity
-// ballot fused in).
+// Stockham autosort stages with radix-8 (columns) or radix-16 (rows)
+// butterflies in registers, then one smaller stage for the rest of the
+// length; one twiddle-table read per butterfly group, the other powers by
+// squaring and products.  The first stage of each pass reads global memory
+// (or bits) and the last one writes its result straight out (spectrum
+// product, twiddle, or parity ballot fused in).
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -187,9 +189,33 @@ __device__ __forceinline__ double2 mul_w12(double2 x, int q) {
     return cmul(x, make_double2(cs[q], INV ? sn[q] : -sn[q]));
 }
 
-// R1 * R2-point DFT (R1 R2 divides 12), natural order in and out, by one
-// Cooley-Tukey split: R2 DFTs of R1 points on the stride-R2 subsequences,
-// the constant twiddles w_R^(n2 k1), then R1 DFTs of R2 points.
+// x * w_16^q (q taken mod 16), as mul_w12: cos and sin of multiples of
+// 22.5 degrees.
+template <bool INV>
+__device__ __forceinline__ double2 mul_w16(double2 x, int q) {
+    const double c1 = 0.92387953251128675613;  // cos 22.5 deg
+    const double s1 = 0.38268343236508977173;  // sin 22.5 deg
+    const double h = 0.70710678118654752440;   // cos 45 deg
+    q %= 16;
+    if (q == 0) return x;
+    if (q == 4) return rot90<INV>(x);
+    if (q == 8) return make_double2(-x.x, -x.y);
+    if (q == 12) return rot90<!INV>(x);
+    const double cs[16] = {1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1, -h, -s1, 0, s1, h, c1};
+    const double sn[16] = {0, s1, h, c1, 1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1, -h, -s1};
+    return cmul(x, make_double2(cs[q], INV ? sn[q] : -sn[q]));
+}
+
+// x * w_R^q for R dividing 12 or R = 16.
+template <int R, bool INV>
+__device__ __forceinline__ double2 mul_wR(double2 x, int q) {
+    if constexpr (R == 16) return mul_w16<INV>(x, q);
+    else return mul_w12<INV>(x, q * (12 / R));
+}
+
+// R1 * R2-point DFT (R1 R2 divides 12, or is 16), natural order in and out,
+// by one Cooley-Tukey split: R2 DFTs of R1 points on the stride-R2
+// subsequences, the constant twiddles w_R^(n2 k1), then R1 DFTs of R2 points.
 template <int R1, int R2, bool INV>
 __device__ __forceinline__ void dft_ct(double2 (&v)[R1 * R2]) {
     constexpr int R = R1 * R2;
@@ -202,7 +228,7 @@ __device__ __forceinline__ void dft_ct(double2 (&v)[R1 * R2]) {
         dftR<R1, INV>(t);
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1)
-            u[n2][k1] = mul_w12<INV>(t[k1], n2 * k1 * (12 / R));
+            u[n2][k1] = mul_wR<R, INV>(t[k1], n2 * k1);
     }
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) {
@@ -222,6 +248,7 @@ __device__ __forceinline__ void dftR(double2 (&v)[R]) {
     else if constexpr (R == 3) dft3<INV>(v);
     else if constexpr (R == 6) dft_ct<2, 3, INV>(v);
     else if constexpr (R == 12) dft_ct<4, 3, INV>(v);
+    else if constexpr (R == 16) dft_ct<4, 4, INV>(v);
     else dft2<INV>(v);
 }
 
@@ -460,54 +487,216 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     fft_run<kN1, kN1, false>(buf, a.tw64, ld, st);
 }
 
+// ------------------------------------------------------------ row pass ---
+//
+// One workgroup of kRowThreads per row of N2 points (64 .. 8192).  Stages
+// of radix 16 while four or more factors of two remain, then the rest of the
+// power of two with the 3 merged in (3, 6 or 12; 4 then 6 when eight and a 3
+// remain).  The last forward stage keeps its results in registers: they are
+// multiplied by the seed spectrum there and fed straight into the inverse,
+// which runs the forward stages in reverse order, each as its exact inverse
+// (read where the forward stage wrote, inverse DFT, conjugate twiddles, write
+// where it read).  Per row that is 2 S - 2 LDS writes and as many reads for
+// S stages, and one LDS round trip and its barriers fewer than a second
+// forward-style pass.
+constexpr int kRowThreads = 256;
+
+constexpr int rp_tail(int n) {       // stages after the radix-16 ones
+    return n % 3 == 0 ? (pow2_bits(n) % 4 == 3 ? 2 : 1) : (pow2_bits(n) % 4 ? 1 : 0);
+}
+constexpr int rp_stages(int n) { return pow2_bits(n) / 4 + rp_tail(n); }
+constexpr int rp_radix(int n, int s) {
+    return s < pow2_bits(n) / 4 ? 16
+         : n % 3 != 0 ? 1 << (pow2_bits(n) % 4)
+         : pow2_bits(n) % 4 == 3 ? (s == pow2_bits(n) / 4 ? 4 : 6)
+         : 3 << (pow2_bits(n) % 4);
+}
+constexpr int rp_span(int n, int s) {
+    return s == 0 ? 1 : rp_span(n, s - 1) * rp_radix(n, s - 1);
+}
+
+// Stage S of the row plan: group j < G reads elements in(j, k) = j + k G
+// (k < R) and writes out(j, r) = (j / span) span R + (j mod span) + r span.
+template <int N, int S> struct RowStage {
+    static constexpr int R = rp_radix(N, S), SPAN = rp_span(N, S), G = N / R;
+    static constexpr int PER = (G + kRowThreads - 1) / kRowThreads;
+    static __device__ bool active(int g) { return G % kRowThreads == 0 || g < G; }
+    static __device__ int in(int j, int k) { return j + k * G; }
+    static __device__ int out(int j, int r) {
+        return (j / SPAN) * SPAN * R + (j % SPAN) + r * SPAN;
+    }
+    static __device__ int base(int j) { return (j % SPAN) * (N / (SPAN * R)); }
+};
+
+// LDS address of row element e: the index XOR-swizzled inside blocks of 8
+// by bits 4..6, so that stride-16 accesses (the radix-16 first stage) and
+// contiguous ones of 8 lanes both touch every bank once.
+__device__ __forceinline__ int rsw(int e) { return e ^ ((e >> 4) & 7); }
+
+// w^r, r < R, from w (wr[0] = 1): w^(2^b) by squaring, the others as
+// w^(2^b) w^rest.
+template <int R>
+__device__ __forceinline__ void tw_powers(double2 (&wr)[R], double2 w) {
+    double2 pw[tw_bits(R)];
+    pw[0] = w;
+#pragma unroll
+    for (int b = 1; b < tw_bits(R); ++b) pw[b] = csq(pw[b - 1]);
+    wr[0] = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const int hb = ilog2c(r);
+        const int rest = r - (1 << hb);
+        wr[r] = rest ? cmul(pw[hb], wr[rest]) : pw[hb];
+    }
+}
+
+// Forward stage S < last: read (global `ld` for S = 0, else LDS), twiddle,
+// DFT, write LDS.  Barrier before the writes (S > 0: other groups may still
+// read those places) and after them.
+template <int N, int S, class Ld>
+__device__ __forceinline__ void row_fwd(double2 *buf, const double2 *tw, Ld ld) {
+    using T = RowStage<N, S>;
+    double2 v[T::PER][T::R];
+#pragma unroll
+    for (int i = 0; i < T::PER; ++i) {
+        const int g = threadIdx.x + kRowThreads * i;
+        if (T::active(g)) {
+#pragma unroll
+            for (int k = 0; k < T::R; ++k)
+                v[i][k] = S == 0 ? ld(T::in(g, k)) : buf[rsw(T::in(g, k))];
+            if constexpr (S > 0) {
+                double2 wr[T::R];
+                tw_powers(wr, tw[T::base(g)]);
+#pragma unroll
+                for (int k = 1; k < T::R; ++k) v[i][k] = cmul(v[i][k], wr[k]);
+            }
+            dftR<T::R, false>(v[i]);
+        }
+    }
+    if constexpr (S > 0) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < T::PER; ++i) {
+        const int g = threadIdx.x + kRowThreads * i;
+        if (T::active(g)) {
+#pragma unroll
+            for (int r = 0; r < T::R; ++r) buf[rsw(T::out(g, r))] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Inverse of forward stage S (0 < S < last): read LDS where it wrote,
+// inverse DFT, conjugate twiddles, write where it read.
+template <int N, int S>
+__device__ __forceinline__ void row_inv(double2 *buf, const double2 *tw) {
+    using T = RowStage<N, S>;
+    double2 v[T::PER][T::R];
+#pragma unroll
+    for (int i = 0; i < T::PER; ++i) {
+        const int g = threadIdx.x + kRowThreads * i;
+        if (T::active(g)) {
+#pragma unroll
+            for (int r = 0; r < T::R; ++r) v[i][r] = buf[rsw(T::out(g, r))];
+            dftR<T::R, true>(v[i]);
+            double2 wr[T::R];
+            tw_powers(wr, conj2(tw[T::base(g)]));
+#pragma unroll
+            for (int k = 1; k < T::R; ++k) v[i][k] = cmul(v[i][k], wr[k]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < T::PER; ++i) {
+        const int g = threadIdx.x + kRowThreads * i;
+        if (T::active(g)) {
+#pragma unroll
+            for (int k = 0; k < T::R; ++k) buf[rsw(T::in(g, k))] = v[i][k];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int S, class Ld>
+__device__ __forceinline__ void row_fwd_all(double2 *buf, const double2 *tw, Ld ld) {
+    if constexpr (S + 1 < rp_stages(N)) {
+        row_fwd<N, S>(buf, tw, ld);
+        row_fwd_all<N, S + 1>(buf, tw, ld);
+    }
+}
+template <int N, int S>
+__device__ __forceinline__ void row_inv_all(double2 *buf, const double2 *tw) {
+    if constexpr (S >= 1) {
+        row_inv<N, S>(buf, tw);
+        row_inv_all<N, S - 1>(buf, tw);
+    }
+}
+
 // Row pass over rows of N2 (= nr) points.  SPEC: forward only, the result is
 // the seed spectrum; else forward, times the spectrum, inverse, times
 // w_(64 N2)^(-e (row mod 64)) -- the inverse of the twiddle of the column
 // pass that made the row (k_fft_cols with two levels, the last k_fft_mid
 // with three or four).
-// Waves per SIMD that the LDS of an N2-point row allows (three workgroups of
-// eight waves at most, 160 KiB per CU); the register budget follows from it.
-constexpr int rows_waves(int n2) {
-    return 2 * std::min(3, (160 * 1024) / (n2 * 16));
-}
 template <int N2, bool SPEC>
-__global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(rows_waves(N2)))) void k_fft_rows(FftArgs a) {
+__global__ __launch_bounds__(kRowThreads) void k_fft_rows(FftArgs a) {
     __shared__ double2 buf[N2];
     if (*a.status) return;
+    constexpr int NS = rp_stages(N2);
+    static_assert(NS >= 2, "at least two stages");
+    using TL = RowStage<N2, NS - 1>;
+    using T0 = RowStage<N2, 0>;
     const uint32_t row = blockIdx.x;
-    const uint32_t pl = blockIdx.y;
+    const uint32_t pl = SPEC ? 0u : blockIdx.y;
     const uint64_t k1 = row & 63u;
     double2 *y = a.work + (size_t)pl * a.L + (size_t)row * N2;
     double2 *sp = a.spec + (size_t)row * N2;
-    auto gl_ld = [&](int, int e) { return y[e]; };
-    auto lds_ld = [&](int, int e) { return buf[lds_addr<1>(0, e)]; };
-    if (SPEC) {
-        auto spec_st = [&](int, int e0, int span, auto &v) {
+    const double2 *tw = a.twr;
+    row_fwd_all<N2, 0>(buf, tw, [&](int e) { return y[e]; });
+
+    // Last stage: forward DFT in registers, spectrum product, inverse DFT.
+    double2 v[TL::PER][TL::R], wr[TL::PER][TL::R];
 #pragma unroll
-            for (int r = 0; r < group_size(v); ++r) sp[e0 + r * span] = v[r];
-        };
-        fft_run<N2, 1, false>(buf, a.twr, gl_ld, spec_st);
-        return;
-    }
-    // Forward, the spectrum product fused into the last stage's stores.
-    auto mul_st = [&](int, int e0, int span, auto &v) {
+    for (int i = 0; i < TL::PER; ++i) {
+        const int g = threadIdx.x + kRowThreads * i;
+        if (TL::active(g)) {
 #pragma unroll
-        for (int r = 0; r < group_size(v); ++r) {
-            const int e = e0 + r * span;
-            buf[lds_addr<1>(0, e)] = cmul(v[r], sp[e]);
+            for (int k = 0; k < TL::R; ++k) v[i][k] = buf[rsw(TL::in(g, k))];
+            tw_powers(wr[i], tw[TL::base(g)]);
+#pragma unroll
+            for (int k = 1; k < TL::R; ++k) v[i][k] = cmul(v[i][k], wr[i][k]);
+            dftR<TL::R, false>(v[i]);
+            if (SPEC) {
+#pragma unroll
+                for (int r = 0; r < TL::R; ++r) sp[TL::out(g, r)] = v[i][r];
+                continue;
+            }
+#pragma unroll
+            for (int r = 0; r < TL::R; ++r) v[i][r] = cmul(v[i][r], sp[TL::out(g, r)]);
+            dftR<TL::R, true>(v[i]);
+            // The same group's places: no other thread reads them, no barrier.
+#pragma unroll
+            for (int k = 0; k < TL::R; ++k)
+                buf[rsw(TL::in(g, k))] = k ? cmul(v[i][k], conj2(wr[i][k])) : v[i][k];
         }
-    };
-    fft_run<N2, 1, false>(buf, a.twr, gl_ld, mul_st);
+    }
+    if (SPEC) return;
     __syncthreads();
-    // Element e = e0 + r span takes conj(w^(e0 k1)) conj(w^(span k1))^r,
-    // w = w_(64 N2).
-    auto out_st = [&](int, int e0, int span, auto &v) {
-        twiddle_run(v, conj2(omega_r(a, (uint64_t)e0 * k1)),
-                    conj2(omega_r(a, (uint64_t)span * k1)),
-                    [&](int r, double2 x) { y[e0 + r * span] = x; });
-    };
-    fft_run<N2, 1, true>(buf, a.twr, lds_ld, out_st);
+    row_inv_all<N2, NS - 2>(buf, tw);
+
+    // Inverse of stage 0 (no twiddle), element e = g + k G0 times
+    // conj(w^(g k1)) conj(w^(G0 k1))^k, w = w_(64 N2), to global memory.
+    double2 u[T0::PER][T0::R];
+#pragma unroll
+    for (int i = 0; i < T0::PER; ++i) {
+        const int g = threadIdx.x + kRowThreads * i;
+        if (T0::active(g)) {
+#pragma unroll
+            for (int r = 0; r < T0::R; ++r) u[i][r] = buf[rsw(T0::out(g, r))];
+            dftR<T0::R, true>(u[i]);
+            twiddle_run(u[i], conj2(omega_r(a, (uint64_t)g * k1)),
+                        conj2(omega_r(a, (uint64_t)T0::G * k1)),
+                        [&](int k, double2 x) { y[T0::in(g, k)] = x; });
+        }
+    }
 }
 
 __device__ __forceinline__ double2 omega_d(const FftArgs &a, int d, uint64_t e) {
@@ -694,11 +883,11 @@ void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
                  hipStream_t stream) {
     const uint32_t rows = (uint32_t)(a.L / N2);
     if (spec)
-        hipLaunchKernelGGL((k_fft_rows<N2, true>), dim3(rows, 1), dim3(kThreads),
-                           0, stream, a);
+        hipLaunchKernelGGL((k_fft_rows<N2, true>), dim3(rows, 1),
+                           dim3(kRowThreads), 0, stream, a);
     else
         hipLaunchKernelGGL((k_fft_rows<N2, false>), dim3(rows, pairs),
-                           dim3(kThreads), 0, stream, a);
+                           dim3(kRowThreads), 0, stream, a);
 }
 
 void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
