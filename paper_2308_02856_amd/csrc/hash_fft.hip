@@ -489,38 +489,70 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
 
 // ------------------------------------------------------------ row pass ---
 //
-// One workgroup of kRowThreads per row of N2 points (64 .. 8192).  Stages
-// of radix 16 while four or more factors of two remain, then the rest of the
-// power of two with the 3 merged in (3, 6 or 12; 4 then 6 when eight and a 3
-// remain).  The last forward stage keeps its results in registers: they are
-// multiplied by the seed spectrum there and fed straight into the inverse,
-// which runs the forward stages in reverse order, each as its exact inverse
-// (read where the forward stage wrote, inverse DFT, conjugate twiddles, write
-// where it read).  Per row that is 2 S - 2 LDS writes and as many reads for
-// S stages, and one LDS round trip and its barriers fewer than a second
-// forward-style pass.
-constexpr int kRowThreads = 256;
+// Stockham stages with radix-16 butterflies where the length allows.  The
+// last forward stage keeps its results in registers: they are multiplied by
+// the seed spectrum there and fed straight into the inverse, which runs the
+// forward stages in reverse order, each as its exact inverse (read where the
+// forward stage wrote, inverse DFT, conjugate twiddles, write where it
+// read).  Per row that is 2 S - 2 LDS writes and as many reads for S stages,
+// one LDS round trip and its barriers fewer than a second forward-style pass.
+//
+// A workgroup holds RPW rows of TPR threads each: TPR covers the widest
+// stage (groups beyond it loop), and short rows are packed so that the
+// workgroup has up to 256 threads and at most 48 KiB of LDS.
 
-constexpr int rp_tail(int n) {       // stages after the radix-16 ones
-    return n % 3 == 0 ? (pow2_bits(n) % 4 == 3 ? 2 : 1) : (pow2_bits(n) % 4 ? 1 : 0);
+struct RowPlan {
+    int ns;        // stages
+    int r[4];      // radices, first to last
+};
+// Radix plan per row length: few stages, and for short rows stages whose
+// group counts are alike (idle threads are what packing cannot recover).
+constexpr RowPlan rp_plan(int n) {
+    switch (n) {
+    case 64: return {2, {8, 8, 0, 0}};
+    case 128: return {2, {16, 8, 0, 0}};
+    case 192: return {2, {16, 12, 0, 0}};
+    case 256: return {2, {16, 16, 0, 0}};
+    case 384: return {3, {8, 8, 6, 0}};
+    case 512: return {3, {8, 8, 8, 0}};
+    case 768: return {3, {16, 8, 6, 0}};
+    case 1024: return {3, {16, 8, 8, 0}};
+    case 1536: return {3, {16, 16, 6, 0}};
+    case 2048: return {3, {16, 16, 8, 0}};
+    case 3072: return {3, {16, 16, 12, 0}};
+    case 4096: return {3, {16, 16, 16, 0}};
+    case 6144: return {4, {16, 16, 4, 6}};
+    default: return {4, {2, 16, 16, 16}};   // 8192
+    }
 }
-constexpr int rp_stages(int n) { return pow2_bits(n) / 4 + rp_tail(n); }
-constexpr int rp_radix(int n, int s) {
-    return s < pow2_bits(n) / 4 ? 16
-         : n % 3 != 0 ? 1 << (pow2_bits(n) % 4)
-         : pow2_bits(n) % 4 == 3 ? (s == pow2_bits(n) / 4 ? 4 : 6)
-         : 3 << (pow2_bits(n) % 4);
-}
+constexpr int rp_stages(int n) { return rp_plan(n).ns; }
+constexpr int rp_radix(int n, int s) { return rp_plan(n).r[s]; }
 constexpr int rp_span(int n, int s) {
     return s == 0 ? 1 : rp_span(n, s - 1) * rp_radix(n, s - 1);
 }
+constexpr int rp_maxg(int n, int s = 0) {
+    return s == rp_stages(n) ? 0 : std::max(n / rp_radix(n, s), rp_maxg(n, s + 1));
+}
+constexpr int pow2_ceil(int x) { return x <= 1 ? 1 : 2 * pow2_ceil((x + 1) / 2); }
+constexpr int pow2_floor(int x) { return x <= 1 ? 1 : 2 * pow2_floor(x / 2); }
+// Threads per row and rows per workgroup.
+constexpr int rp_tpr(int n) {
+    return n >= 6144 ? 512 : std::min(256, pow2_ceil(rp_maxg(n)));
+}
+constexpr int rp_rpw(int n) {
+    return pow2_floor(std::max(1, std::min(256 / std::min(256, rp_tpr(n)),
+                                           (48 * 1024) / (16 * n))));
+}
+constexpr int rp_threads(int n) { return rp_tpr(n) * rp_rpw(n); }
 
 // Stage S of the row plan: group j < G reads elements in(j, k) = j + k G
 // (k < R) and writes out(j, r) = (j / span) span R + (j mod span) + r span.
+// Group j = lt + TPR i (i < PER) belongs to the row's thread lt.
 template <int N, int S> struct RowStage {
     static constexpr int R = rp_radix(N, S), SPAN = rp_span(N, S), G = N / R;
-    static constexpr int PER = (G + kRowThreads - 1) / kRowThreads;
-    static __device__ bool active(int g) { return G % kRowThreads == 0 || g < G; }
+    static constexpr int TPR = rp_tpr(N);
+    static constexpr int PER = (G + TPR - 1) / TPR;
+    static __device__ bool active(int g) { return G % TPR == 0 || g < G; }
     static __device__ int in(int j, int k) { return j + k * G; }
     static __device__ int out(int j, int r) {
         return (j / SPAN) * SPAN * R + (j % SPAN) + r * SPAN;
@@ -529,7 +561,7 @@ template <int N, int S> struct RowStage {
 };
 
 // LDS address of row element e: the index XOR-swizzled inside blocks of 8
-// by bits 4..6, so that stride-16 accesses (the radix-16 first stage) and
+// by bits 4..6, so that stride-16 accesses (a radix-16 first stage) and
 // contiguous ones of 8 lanes both touch every bank once.
 __device__ __forceinline__ int rsw(int e) { return e ^ ((e >> 4) & 7); }
 
@@ -550,16 +582,18 @@ __device__ __forceinline__ void tw_powers(double2 (&wr)[R], double2 w) {
     }
 }
 
-// Forward stage S < last: read (global `ld` for S = 0, else LDS), twiddle,
-// DFT, write LDS.  Barrier before the writes (S > 0: other groups may still
-// read those places) and after them.
+// Forward stage S < last of the row at `buf` (thread lt of the row): read
+// (global `ld` for S = 0, else LDS), twiddle, DFT, write LDS.  Barrier
+// before the writes (S > 0: other groups may still read those places) and
+// after them.
 template <int N, int S, class Ld>
-__device__ __forceinline__ void row_fwd(double2 *buf, const double2 *tw, Ld ld) {
+__device__ __forceinline__ void row_fwd(double2 *buf, const double2 *tw, int lt,
+                                        Ld ld) {
     using T = RowStage<N, S>;
     double2 v[T::PER][T::R];
 #pragma unroll
     for (int i = 0; i < T::PER; ++i) {
-        const int g = threadIdx.x + kRowThreads * i;
+        const int g = lt + T::TPR * i;
         if (T::active(g)) {
 #pragma unroll
             for (int k = 0; k < T::R; ++k)
@@ -576,7 +610,7 @@ __device__ __forceinline__ void row_fwd(double2 *buf, const double2 *tw, Ld ld) 
     if constexpr (S > 0) __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::PER; ++i) {
-        const int g = threadIdx.x + kRowThreads * i;
+        const int g = lt + T::TPR * i;
         if (T::active(g)) {
 #pragma unroll
             for (int r = 0; r < T::R; ++r) buf[rsw(T::out(g, r))] = v[i][r];
@@ -588,12 +622,12 @@ __device__ __forceinline__ void row_fwd(double2 *buf, const double2 *tw, Ld ld) 
 // Inverse of forward stage S (0 < S < last): read LDS where it wrote,
 // inverse DFT, conjugate twiddles, write where it read.
 template <int N, int S>
-__device__ __forceinline__ void row_inv(double2 *buf, const double2 *tw) {
+__device__ __forceinline__ void row_inv(double2 *buf, const double2 *tw, int lt) {
     using T = RowStage<N, S>;
     double2 v[T::PER][T::R];
 #pragma unroll
     for (int i = 0; i < T::PER; ++i) {
-        const int g = threadIdx.x + kRowThreads * i;
+        const int g = lt + T::TPR * i;
         if (T::active(g)) {
 #pragma unroll
             for (int r = 0; r < T::R; ++r) v[i][r] = buf[rsw(T::out(g, r))];
@@ -607,7 +641,7 @@ __device__ __forceinline__ void row_inv(double2 *buf, const double2 *tw) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < T::PER; ++i) {
-        const int g = threadIdx.x + kRowThreads * i;
+        const int g = lt + T::TPR * i;
         if (T::active(g)) {
 #pragma unroll
             for (int k = 0; k < T::R; ++k) buf[rsw(T::in(g, k))] = v[i][k];
@@ -617,17 +651,18 @@ __device__ __forceinline__ void row_inv(double2 *buf, const double2 *tw) {
 }
 
 template <int N, int S, class Ld>
-__device__ __forceinline__ void row_fwd_all(double2 *buf, const double2 *tw, Ld ld) {
+__device__ __forceinline__ void row_fwd_all(double2 *buf, const double2 *tw,
+                                            int lt, Ld ld) {
     if constexpr (S + 1 < rp_stages(N)) {
-        row_fwd<N, S>(buf, tw, ld);
-        row_fwd_all<N, S + 1>(buf, tw, ld);
+        row_fwd<N, S>(buf, tw, lt, ld);
+        row_fwd_all<N, S + 1>(buf, tw, lt, ld);
     }
 }
 template <int N, int S>
-__device__ __forceinline__ void row_inv_all(double2 *buf, const double2 *tw) {
+__device__ __forceinline__ void row_inv_all(double2 *buf, const double2 *tw, int lt) {
     if constexpr (S >= 1) {
-        row_inv<N, S>(buf, tw);
-        row_inv_all<N, S - 1>(buf, tw);
+        row_inv<N, S>(buf, tw, lt);
+        row_inv_all<N, S - 1>(buf, tw, lt);
     }
 }
 
@@ -635,28 +670,31 @@ __device__ __forceinline__ void row_inv_all(double2 *buf, const double2 *tw) {
 // the seed spectrum; else forward, times the spectrum, inverse, times
 // w_(64 N2)^(-e (row mod 64)) -- the inverse of the twiddle of the column
 // pass that made the row (k_fft_cols with two levels, the last k_fft_mid
-// with three or four).
+// with three or four).  Workgroup x holds rows x RPW .. x RPW + RPW - 1.
 template <int N2, bool SPEC>
-__global__ __launch_bounds__(kRowThreads) void k_fft_rows(FftArgs a) {
-    __shared__ double2 buf[N2];
+__global__ __launch_bounds__(rp_threads(N2)) void k_fft_rows(FftArgs a) {
+    constexpr int TPR = rp_tpr(N2), RPW = rp_rpw(N2);
+    __shared__ double2 lds[N2 * RPW];
     if (*a.status) return;
     constexpr int NS = rp_stages(N2);
     static_assert(NS >= 2, "at least two stages");
     using TL = RowStage<N2, NS - 1>;
     using T0 = RowStage<N2, 0>;
-    const uint32_t row = blockIdx.x;
+    const int lt = threadIdx.x % TPR;
+    const uint32_t row = blockIdx.x * RPW + threadIdx.x / TPR;
     const uint32_t pl = SPEC ? 0u : blockIdx.y;
     const uint64_t k1 = row & 63u;
+    double2 *buf = lds + (threadIdx.x / TPR) * N2;
     double2 *y = a.work + (size_t)pl * a.L + (size_t)row * N2;
     double2 *sp = a.spec + (size_t)row * N2;
     const double2 *tw = a.twr;
-    row_fwd_all<N2, 0>(buf, tw, [&](int e) { return y[e]; });
+    row_fwd_all<N2, 0>(buf, tw, lt, [&](int e) { return y[e]; });
 
     // Last stage: forward DFT in registers, spectrum product, inverse DFT.
     double2 v[TL::PER][TL::R], wr[TL::PER][TL::R];
 #pragma unroll
     for (int i = 0; i < TL::PER; ++i) {
-        const int g = threadIdx.x + kRowThreads * i;
+        const int g = lt + TPR * i;
         if (TL::active(g)) {
 #pragma unroll
             for (int k = 0; k < TL::R; ++k) v[i][k] = buf[rsw(TL::in(g, k))];
@@ -680,14 +718,14 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows(FftArgs a) {
     }
     if (SPEC) return;
     __syncthreads();
-    row_inv_all<N2, NS - 2>(buf, tw);
+    row_inv_all<N2, NS - 2>(buf, tw, lt);
 
     // Inverse of stage 0 (no twiddle), element e = g + k G0 times
     // conj(w^(g k1)) conj(w^(G0 k1))^k, w = w_(64 N2), to global memory.
     double2 u[T0::PER][T0::R];
 #pragma unroll
     for (int i = 0; i < T0::PER; ++i) {
-        const int g = threadIdx.x + kRowThreads * i;
+        const int g = lt + TPR * i;
         if (T0::active(g)) {
 #pragma unroll
             for (int r = 0; r < T0::R; ++r) u[i][r] = buf[rsw(T0::out(g, r))];
@@ -881,13 +919,17 @@ ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
 template <int N2>
 void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
                  hipStream_t stream) {
+    // Rows per transform (64, 4096 or 2^18) are a multiple of the rows per
+    // workgroup (a power of two up to 32).
     const uint32_t rows = (uint32_t)(a.L / N2);
+    static_assert(64 % rp_rpw(N2) == 0, "rows per workgroup divide 64");
+    const dim3 grid(rows / rp_rpw(N2), spec ? 1u : pairs);
     if (spec)
-        hipLaunchKernelGGL((k_fft_rows<N2, true>), dim3(rows, 1),
-                           dim3(kRowThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_fft_rows<N2, true>), grid, dim3(rp_threads(N2)),
+                           0, stream, a);
     else
-        hipLaunchKernelGGL((k_fft_rows<N2, false>), dim3(rows, pairs),
-                           dim3(kRowThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_fft_rows<N2, false>), grid, dim3(rp_threads(N2)),
+                           0, stream, a);
 }
 
 void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
