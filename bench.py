@@ -210,7 +210,6 @@ def run_batched(ctx, ssbh, args):
                schedule=schedule, tune_report=tune_report, l_ub=l_ub,
                hash_kernels=hash_kernels, sample_kernels=sample_kernels,
                timed_calls=reps,
-               pairs=(ns + 1) // 2,
                sift_ms=float(np.mean(sift_ms)), l_ub_sifted=l_ub2)
     return res
 
@@ -680,7 +679,7 @@ def main() -> int:
                     help="hash kernel of the batched step (auto = tuned)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--fft-chunk", type=int, default=0,
-                    help="force the FFT hash's pairs per chunk (0 = tuned)")
+                    help="force the FFT hash's transforms per chunk (0 = tuned)")
     ap.add_argument("--cpu-subblocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
@@ -757,13 +756,16 @@ def main() -> int:
     hk = res["hash_kernels"]
     if res["schedule"].startswith("fft"):
         # Dominant kernel: the row pass.  Per launch it reads and writes the
-        # transforms of its chunk of sub-block pairs (L complex doubles per
-        # pair each way) and reads the seed spectrum once.
+        # transforms of its chunk (L complex doubles per transform each way;
+        # a transform holds 2 or 4 sub-blocks, "x<k>" in the schedule) and
+        # reads the seed spectrum once.
         kern = "k_fft_rows"
         n_l, ms = hk[kern]
         L = int(res["schedule"].split(":L")[1])   # transform length
-        per_pair = 2 * L * 16
-        total_bytes = (res["timed_calls"] * res["pairs"] * per_pair +
+        per = int(res["schedule"].split(":x")[1].split(":")[0])
+        transforms = (res["ns"] + per - 1) // per
+        per_transform = 2 * L * 16
+        total_bytes = (res["timed_calls"] * transforms * per_transform +
                        n_l * L * 16)
         achieved = total_bytes / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": kern, "schedule": res["schedule"],

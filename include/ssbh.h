@@ -85,7 +85,10 @@ enum {
     SSBH_K_FFT = 3,           /* middle product by double-precision FFTs,
                                  every entry rounded and checked.  Shared
                                  seed of at most 2^31 bits: two sub-blocks
-                                 per transform.  Seed stride S > 0 (at most
+                                 per transform, four (x_lo + 2^18 x_hi per
+                                 part) when seed_bits + 1 - m_cap < 2^18 and
+                                 the transform length is at most 2^20
+                                 (ssbh_set_fft_packing).  Seed stride S > 0 (at most
                                  2^31): one transform per sub-block with the
                                  spectrum of its own seed; needs every
                                  n_j + m_cap - 1 <= the transform length of
@@ -443,10 +446,19 @@ ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len);
  * on it. */
 ssbh_status ssbh_set_sample_path(ssbh_ctx *ctx, int path);
 
-/* Force the FFT hash's chunk: sub-block pairs transformed per pass (each
- * pair holds 2^18 complex doubles of scratch at the largest length; 0 =
- * library choice).  The output bits do not depend on it. */
+/* Force the FFT hash's chunk: transforms per pass (each holds two or four
+ * sub-blocks with a shared seed and takes L complex doubles of scratch, at
+ * most 512 MiB per pass; 0 = library choice).  The output bits do not
+ * depend on it. */
 ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs);
+
+/* Force how many sub-blocks share each real and imaginary part of an FFT
+ * transform with a shared seed: 1 (two per transform), 2 (four: the second
+ * scaled by 2^18, needs seed_bits + 1 - m_cap < 2^18 and a transform
+ * length of at most 2^20, else the hash returns SSBH_E_UNSUPPORTED), or 0 =
+ * library choice (2 when allowed).  For tests and tuning; the output bits
+ * do not depend on it. */
+ssbh_status ssbh_set_fft_packing(ssbh_ctx *ctx, int per_part);
 
 /* Where the VALU hash kernel reads the 32-bit column words of the sub-blocks
  * from: 0 = staged in LDS with the seed window, 1 = through the scalar data

@@ -179,16 +179,18 @@ std::string tune_bucket(const HashRequest &q) {
 
 // Untuned choice between the FFT and the quadratic kernels for a shared
 // seed.  Per sub-block the quadratic kernels do about n * m bit-products at
-// roughly 2.5e15 per second; the FFT does half a transform pair, about
-// L log2 L points at roughly 1e-12 s per point-level (both measured on
-// MI355X).  The FFT is taken when n * m >= 1024 L log2 L, n estimated from
-// the seed length (n_max + m_cap - 1 bits).
+// roughly 2.5e15 per second; the FFT does a share (1/2, or 1/4 when four
+// sub-blocks ride in a transform) of a forward and inverse transform, about
+// L log2 L points at roughly 1e-12 s per point-level each (both measured on
+// MI355X).  The FFT is taken when n * m >= 2048 L log2 L / (sub-blocks per
+// transform), n estimated from the seed length (n_max + m_cap - 1 bits).
 bool fft_pays(const HashRequest &q) {
     const uint64_t L = fft_length(q.seed_bits);
     if (L > kMaxFftLength || q.seed_bits + 1 <= q.m_cap) return false;
     const double n = (double)(q.seed_bits + 1 - q.m_cap);
     const double m = (double)q.m_cap;
-    return n * m >= 1024.0 * (double)L * std::log2((double)L);
+    const double per = fft_can_pack(q, L) ? 4.0 : 2.0;
+    return n * m >= 2048.0 / per * (double)L * std::log2((double)L);
 }
 
 ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
@@ -474,6 +476,15 @@ ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs) {
     if (!ctx) SSBH_INVAL("ctx is null");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->forced_fft_chunk = chunk_pairs;
+    return SSBH_OK;
+}
+
+ssbh_status ssbh_set_fft_packing(ssbh_ctx *ctx, int per_part) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (per_part < 0 || per_part > 2) SSBH_INVAL("per_part must be 0, 1 or 2");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->forced_fft_pack = per_part;
     return SSBH_OK;
 }
 

@@ -79,8 +79,10 @@ struct FftArgs {
                                // row: w_L, w_(L/64) or w_(L/4096))
     const double2 *wlo[3], *whi[3];  // w_(L/64^d)^e for level d, same split
     int lvl;                   // level of a middle pass (1 or 2)
-    int solo;                  // independent seeds: "pair" pair0 + p is the
-                               // one sub-block pair0 + p (imaginary part 0)
+    int per;                   // sub-blocks per transform: 1 (independent
+                               // seeds: transform t is sub-block t alone),
+                               // 2 (real, imaginary part) or 4 (two per
+                               // part, x_lo + 2^18 x_hi)
     uint64_t seed_off;         // first seed bit of the spectrum's seed
     uint64_t *out;
     int32_t *status;
@@ -428,29 +430,40 @@ __device__ __forceinline__ uint64_t window64(const uint64_t *w, int64_t nbits,
     return v;
 }
 
-// Sub-block in part `part` (0 real, 1 imaginary) of transform pl of the
-// chunk; a.ns when there is none.
-__device__ __forceinline__ uint64_t sub_of(const FftArgs &a, uint32_t pl, int part) {
-    if (a.solo) return part ? (uint64_t)a.ns : (uint64_t)a.pair0 + pl;
-    return 2ull * (a.pair0 + pl) + part;
+// Scale of the high sub-block of a part when four share a transform: the
+// middle product of a low sub-block is at most its length n_j < 2^18 (the
+// largest sub-block length the library accepts is far below), so the part's
+// integer result lo + 2^18 hi gives both back.
+constexpr double kPackScale = 262144.0;
+constexpr int kPackBits = 18;
+
+// Sub-block in slot `slot` of transform pl of the chunk; a.ns when there is
+// none.  Slots: per = 1: 0 only; per = 2: 0 real, 1 imaginary; per = 4: 0 / 1
+// the low / high sub-block of the real part, 2 / 3 of the imaginary part.
+__device__ __forceinline__ uint64_t sub_of(const FftArgs &a, uint32_t pl, int slot) {
+    if (slot >= a.per) return a.ns;
+    const uint64_t j = (uint64_t)a.per * (a.pair0 + pl) + (uint64_t)slot;
+    return j < a.ns ? j : (uint64_t)a.ns;
 }
 
 // Forward column pass.  SEED: the input is the seed from bit seed_off on
-// (u[q] = s[seed_off + q], real); else pair p's two reversed sub-blocks
-// (real, imaginary).  The first stage reads bits, the last stage stores
-// times w_L^(n2 k1).  A sub-block whose n_j + m_cap - 1 exceeds L (possible
-// only with a seed stride below n_max + m_cap - 1) sets SSBH_E_UNSUPPORTED.
-template <bool SEED>
+// (u[q] = s[seed_off + q], real); else transform p's reversed sub-blocks
+// (PACK: xr_0 + 2^18 xr_1 real, xr_2 + 2^18 xr_3 imaginary; else xr_0 real,
+// xr_1 imaginary).  The first stage reads bits, the last stage stores times
+// w_L^(n2 k1).  A sub-block whose n_j + m_cap - 1 exceeds L (possible only
+// with a seed stride below n_max + m_cap - 1) sets SSBH_E_UNSUPPORTED.
+template <bool SEED, bool PACK>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
+    constexpr int SLOTS = PACK ? 4 : 2;
     __shared__ double2 buf[kN1 * kN1];
-    __shared__ uint64_t win[2][kN1];
+    __shared__ uint64_t win[SLOTS][kN1];
     if (*a.status) return;
     const uint32_t n2 = a.n2;
     const uint32_t c0 = blockIdx.x * kN1;
     const uint32_t pl = blockIdx.y;
     const int t = threadIdx.x;
-    // 64-bit windows: thread (n1, part) for the 64 columns of this tile.
-    if (t < 2 * kN1) {
+    // 64-bit windows: thread (n1, slot) for the 64 columns of this tile.
+    if (t < SLOTS * kN1) {
         const int n1 = t & (kN1 - 1), part = t >> 6;
         uint64_t v = 0ull;
         if (SEED) {
@@ -461,7 +474,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
             const uint64_t j = sub_of(a, pl, part);
             if (j < a.ns) {
                 const int64_t n = (int64_t)a.len[j];
-                if (n1 == 0 && blockIdx.x == 0 && (uint64_t)n + a.mcap - 1 > a.L)
+                if (n1 == 0 && blockIdx.x == 0 &&
+                    ((uint64_t)n + a.mcap - 1 > a.L || (PACK && n >> kPackBits)))
                     atomicCAS(a.status, 0, (int32_t)SSBH_E_UNSUPPORTED);
                 // xr[q] = x[n-1-q] for q = n2*n1 + c0 + i, i < 64.
                 const int64_t b0 = n - 1 - ((int64_t)n2 * n1 + c0) - 63;
@@ -474,8 +488,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     double2 *y = a.work + (size_t)pl * a.L;
     // Element (column i = f, row n1 = e).
     auto ld = [&](int f, int e) {
-        return make_double2((double)((win[0][e] >> f) & 1ull),
-                            (double)((win[1][e] >> f) & 1ull));
+        const double b0 = (double)((win[0][e] >> f) & 1ull);
+        const double b1 = (double)((win[1][e] >> f) & 1ull);
+        if constexpr (PACK)
+            return make_double2(fma(kPackScale, b1, b0),
+                                fma(kPackScale, (double)((win[3][e] >> f) & 1ull),
+                                    (double)((win[2][e] >> f) & 1ull)));
+        else
+            return make_double2(b0, b1);
     };
     // Output k1 of column n2i = c0 + f gets w_L^(n2i k1); a group's outputs
     // k1 = k0 + r span take w_L^(n2i k0) (w_L^(n2i span))^r.
@@ -798,8 +818,13 @@ __device__ __forceinline__ void put_rows(uint64_t *out, uint64_t o, int64_t rlo,
 
 // Inverse column pass and output.  The last stage hands the wavefront the 64
 // columns of one row n1 (lane = column), so the parities of 64 consecutive
-// output rows come out of one ballot.
+// output rows come out of one ballot per sub-block.  PACK: a part's integer
+// is lo + 2^18 hi, the low sub-block's parity is its bit 0 and the high
+// one's its bit 18.
+template <bool PACK>
 __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
+    constexpr int SLOTS = PACK ? 4 : 2;
+    constexpr int PER_PART = SLOTS / 2;
     __shared__ double2 buf[kN1 * kN1];
     if (*a.status) return;
     const uint32_t n2 = a.n2;
@@ -808,16 +833,16 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     const double2 *w = a.work + (size_t)pl * a.L;
     const int lane = threadIdx.x & 63;
     const double scale = 1.0 / (double)a.L;
-    int64_t n[2], m[2];
-    uint64_t o[2];
-    bool has[2];
+    int64_t n[SLOTS], m[SLOTS];
+    uint64_t o[SLOTS];
+    bool has[SLOTS];
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
-        const uint64_t j = sub_of(a, pl, part);
-        has[part] = j < a.ns;
-        n[part] = has[part] ? (int64_t)a.len[j] : 0;
-        m[part] = has[part] ? (int64_t)a.mlen[j] : 0;
-        o[part] = has[part] ? a.ooff[j] : 0;
+    for (int slot = 0; slot < SLOTS; ++slot) {
+        const uint64_t j = sub_of(a, pl, slot);
+        has[slot] = j < a.ns;
+        n[slot] = has[slot] ? (int64_t)a.len[j] : 0;
+        m[slot] = has[slot] ? (int64_t)a.mlen[j] : 0;
+        o[slot] = has[slot] ? a.ooff[j] : 0;
     }
     bool bad = false;
     auto ld = [&](int f, int e) { return w[(size_t)e * n2 + c0 + f]; };
@@ -825,20 +850,26 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     auto st1 = [&](int f, int n1, double2 x) {
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
-            if (!has[part]) continue;                        // uniform
-            // Lane i holds q = n2*n1 + c0 + i, i.e. row r = rhi - i.
-            const int64_t rhi = n[part] + (int64_t)a.mcap - 2 -
-                                ((int64_t)n2 * n1 + c0);
-            const int64_t rlo = rhi - 63;
-            if (rhi < 0 || rlo >= m[part]) continue;         // uniform
             const double v = (part ? x.y : x.x) * scale;
             const double rv = rint(v);
-            const int64_t r = rhi - f;
-            const bool need = r >= 0 && r < m[part];
-            if (need && (fabs(v - rv) > 0.25 || rv < -0.25)) bad = true;
-            const bool bit = need && (((int64_t)rv) & 1);
-            const uint64_t word = __brevll(ballot64(bit));  // bit t = row rlo + t
-            if (lane == 0) put_rows(a.out, o[part], rlo, word);
+            const int64_t iv = (int64_t)rv;
+            const bool off = fabs(v - rv) > 0.25 || rv < -0.25;
+#pragma unroll
+            for (int h = 0; h < PER_PART; ++h) {
+                const int slot = PER_PART * part + h;
+                if (!has[slot]) continue;                    // uniform
+                // Lane i holds q = n2*n1 + c0 + i, i.e. row r = rhi - i.
+                const int64_t rhi = n[slot] + (int64_t)a.mcap - 2 -
+                                    ((int64_t)n2 * n1 + c0);
+                const int64_t rlo = rhi - 63;
+                if (rhi < 0 || rlo >= m[slot]) continue;     // uniform
+                const int64_t r = rhi - f;
+                const bool need = r >= 0 && r < m[slot];
+                if (need && off) bad = true;
+                const bool bit = need && ((iv >> (h * kPackBits)) & 1);
+                const uint64_t word = __brevll(ballot64(bit));  // bit t = row rlo + t
+                if (lane == 0) put_rows(a.out, o[slot], rlo, word);
+            }
         }
     };
     auto st = [&](int f, int n0, int span, auto &v) {
@@ -967,6 +998,23 @@ uint64_t fft_length(uint64_t seed_bits) {
     return kMaxFftLength + 1;
 }
 
+// Sub-blocks per transform with a shared seed: four (two per part, the high
+// one scaled by 2^18) when every sub-block is shorter than 2^18 bits (the
+// plan rejects n_j > seed_bits + 1 - m_cap) and L <= 2^20, else two.  The
+// scale multiplies the inputs' norm by 2^18; the usual bound on the
+// rounding error of an FFT convolution, a few eps log2(L) |x|_2 |s|_2
+// (Percival, Math. Comp. 72, 2003), stays below 1/100 for such L even for
+// all-one inputs, against the 1/4 every output is checked for.
+bool fft_can_pack(const HashRequest &q, uint64_t L) {
+    return q.stride == 0 && q.seed_bits + 1 < q.m_cap + (1ull << kPackBits) &&
+           L <= (1ull << 20);
+}
+int fft_per_transform(const ssbh_ctx *ctx, const HashRequest &q, uint64_t L) {
+    if (q.stride) return 1;
+    if (ctx->forced_fft_pack) return 2 * ctx->forced_fft_pack;
+    return fft_can_pack(q, L) ? 4 : 2;
+}
+
 ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                             const FftSchedule &s, hipStream_t stream) {
     // Transform length: the whole seed when it is shared, one stride of it
@@ -983,13 +1031,21 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
-    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u:L%llu",
-             s.chunk_pairs, (unsigned long long)L);
+    const bool solo = q.stride != 0;
+    const int per = fft_per_transform(ctx, q, L);
+    if (per == 4 && !fft_can_pack(q, L)) {
+        set_error("four sub-blocks per transform need a shared seed, "
+                  "seed_bits + 1 - m_cap < 2^18 and L <= 2^20");
+        return SSBH_E_UNSUPPORTED;
+    }
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u:x%d:L%llu",
+             s.chunk_pairs, per, (unsigned long long)L);
     if (!q.n_sub) return SSBH_OK;
     FftTables *tab = nullptr;
     if ((st = get_tables(ctx->device, L, &tab)) != SSBH_OK) return st;
-    const bool solo = q.stride != 0;
-    const uint64_t pairs = solo ? q.n_sub : (q.n_sub + 1ull) / 2;
+    // Transforms ("pairs"): one per sub-block with independent seeds, else
+    // one per two or four sub-blocks.
+    const uint64_t pairs = (q.n_sub + per - 1ull) / per;
     const uint32_t cp = solo ? 1u : (uint32_t)std::min<uint64_t>(pairs, chunk);
     if ((st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK) return st;
     if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
@@ -1031,15 +1087,15 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.out = q.out;
     a.status = q.status;
     const uint32_t tiles = a.n2 / kN1;
-    a.solo = solo ? 1 : 0;
+    a.per = per;
     // Seed spectrum: once for a shared seed; with a seed stride, the
     // spectrum of sub-block j's seed before each of its transforms.
     auto spectrum = [&](uint64_t seed_off) {
         a.pair0 = 0;
         a.seed_off = seed_off;
         TimedLaunch timed(ws.timer, "k_fft_spectrum", stream);
-        hipLaunchKernelGGL(k_fft_cols<true>, dim3(tiles, 1), dim3(kThreads), 0,
-                           stream, a);
+        hipLaunchKernelGGL((k_fft_cols<true, false>), dim3(tiles, 1),
+                           dim3(kThreads), 0, stream, a);
         mids(false, 1);
         rows(a, 1, true, stream);
     };
@@ -1050,8 +1106,12 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         a.pair0 = (uint32_t)p0;
         {
             TimedLaunch timed(ws.timer, "k_fft_cols", stream);
-            hipLaunchKernelGGL(k_fft_cols<false>, dim3(tiles, np),
-                               dim3(kThreads), 0, stream, a);
+            if (per == 4)
+                hipLaunchKernelGGL((k_fft_cols<false, true>), dim3(tiles, np),
+                                   dim3(kThreads), 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_fft_cols<false, false>), dim3(tiles, np),
+                                   dim3(kThreads), 0, stream, a);
         }
         if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
@@ -1067,8 +1127,12 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         }
         {
             TimedLaunch timed(ws.timer, "k_fft_out", stream);
-            hipLaunchKernelGGL(k_fft_out, dim3(tiles, np), dim3(kThreads), 0,
-                               stream, a);
+            if (per == 4)
+                hipLaunchKernelGGL(k_fft_out<true>, dim3(tiles, np),
+                                   dim3(kThreads), 0, stream, a);
+            else
+                hipLaunchKernelGGL(k_fft_out<false>, dim3(tiles, np),
+                                   dim3(kThreads), 0, stream, a);
         }
     }
     SSBH_CHECK_HIP(hipGetLastError());

@@ -127,6 +127,7 @@ struct ssbh_ctx {
     int forced_scalar_x = -1;      // -1 = library choice
     int forced_mfma[4] = {0, 0, 0, 0};
     uint32_t forced_fft_chunk = 0;
+    int forced_fft_pack = 0;       // 0 = library choice, 1 / 2 sub-blocks per part
     int forced_scatter = 0;        // 0 = library choice, 1 = one wave per segment
 };
 
@@ -174,6 +175,8 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
 ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                             const FftSchedule &s, hipStream_t stream);
 uint64_t fft_length(uint64_t seed_bits);
+bool fft_can_pack(const HashRequest &q, uint64_t L);
+int fft_per_transform(const ssbh_ctx *ctx, const HashRequest &q, uint64_t L);
 
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
                         hipStream_t stream);

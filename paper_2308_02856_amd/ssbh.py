@@ -152,6 +152,8 @@ def lib() -> ctypes.CDLL:
     L.ssbh_timing_report.argtypes = [_vp, ctypes.c_char_p, _u64]
     L.ssbh_set_fft_schedule.restype = _i32
     L.ssbh_set_fft_schedule.argtypes = [_vp, _u32]
+    L.ssbh_set_fft_packing.restype = _i32
+    L.ssbh_set_fft_packing.argtypes = [_vp, ctypes.c_int]
     L.ssbh_set_column_path.restype = _i32
     L.ssbh_set_column_path.argtypes = [_vp, ctypes.c_int]
     L.ssbh_job_out_words.restype = _u64
@@ -426,8 +428,13 @@ class Context:
         return out
 
     def set_fft_schedule(self, chunk_pairs: int = 0):
-        """Force the FFT hash's chunk of sub-block pairs (0 = library)."""
+        """Force the FFT hash's chunk of transforms (0 = library)."""
         _check(lib().ssbh_set_fft_schedule(self._h, int(chunk_pairs)))
+
+    def set_fft_packing(self, per_part: int = 0):
+        """Sub-blocks per transform part: 1, 2 (x_lo + 2^18 x_hi) or 0 =
+        library choice."""
+        _check(lib().ssbh_set_fft_packing(self._h, int(per_part)))
 
     def set_column_path(self, scalar_x: int = -1):
         """Column words via LDS (0), scalar loads (1) or library choice (-1)."""
