@@ -139,6 +139,7 @@ void Workspace::release() {
     counters.release();
     fft_spec.release();
     fft_work.release();
+    fft_qbuf.release();
     delete timer;
     timer = nullptr;
 }

@@ -84,6 +84,8 @@ struct FftArgs {
                                // 2 (real, imaginary part) or 4 (two per
                                // part, x_lo + 2^18 x_hi)
     uint64_t seed_off;         // first seed bit of the spectrum's seed
+    uint64_t *qbuf;            // parity words by transform index q (k_fft_out
+                               // writes, k_fft_emit reorders into `out`)
     uint64_t *out;
     int32_t *status;
 };
@@ -798,29 +800,32 @@ __global__ __launch_bounds__(kThreads) void k_fft_mid(FftArgs a) {
     fft_run<kN1, kN1, INV>(buf, a.tw64, ld, st);
 }
 
-// XOR `bits` (bit t = output row rlo + t, already cleared outside [0, m))
-// into the output at bit offset o + rlo.
-__device__ __forceinline__ void put_rows(uint64_t *out, uint64_t o, int64_t rlo,
-                                         uint64_t bits) {
-    if (!bits) return;
-    if (rlo < 0) {
-        bits >>= (int)(-rlo);
-        rlo = 0;
-    }
-    const uint64_t p = o + (uint64_t)rlo;
-    const uint64_t wq = p >> 6;
-    const int sh = (int)(p & 63);
-    atomicXor((unsigned long long *)&out[wq], (unsigned long long)(bits << sh));
-    if (sh && (bits >> (64 - sh)))
-        atomicXor((unsigned long long *)&out[wq + 1],
-                  (unsigned long long)(bits >> (64 - sh)));
+// Where the parities of sub-block j go.  Output row r of the sub-block is
+// entry q = Q0 - r of its convolution, Q0 = n_j + m_cap - 2, so its m_j rows
+// are q in [qlo, Q0], qlo = Q0 - m_j + 1.  The words of that range (64
+// q values each, aligned to multiples of 64) sit at qbuf[qoff + q / 64 -
+// qlo / 64], qoff = ooff_j / 64 + 3 j: the regions of consecutive sub-blocks
+// do not overlap, and all of them fit out_cap_bits / 64 + 3 n_sub words.
+struct QRange {
+    int64_t q0, qlo;     // needed entries [qlo, q0]; q0 = -1 when none
+    int64_t widx;        // qbuf index of entry 0's word: qoff - qlo / 64
+};
+__device__ __forceinline__ QRange q_range(const FftArgs &a, uint64_t j, int64_t n,
+                                          int64_t m, uint64_t o) {
+    if (n == 0 || m == 0) return QRange{-1, 0, 0};    // rows are all zero
+    QRange r;
+    r.q0 = n + (int64_t)a.mcap - 2;
+    r.qlo = r.q0 - m + 1;                             // >= n - 1 >= 0
+    r.widx = (int64_t)(o >> 6) + 3 * (int64_t)j - (r.qlo >> 6);
+    return r;
 }
 
-// Inverse column pass and output.  The last stage hands the wavefront the 64
-// columns of one row n1 (lane = column), so the parities of 64 consecutive
-// output rows come out of one ballot per sub-block.  PACK: a part's integer
-// is lo + 2^18 hi, the low sub-block's parity is its bit 0 and the high
-// one's its bit 18.
+// Inverse column pass.  The last stage hands the wavefront the 64 columns of
+// one row n1 (lane = column): 64 consecutive entries q, one aligned parity
+// word per sub-block (ballot), stored with a plain store (each word has one
+// writer); k_fft_emit then places them.  PACK: a part's integer is
+// lo + 2^18 hi, the low sub-block's parity is its bit 0, the high one's its
+// bit 18.
 template <bool PACK>
 __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     constexpr int SLOTS = PACK ? 4 : 2;
@@ -833,51 +838,86 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     const double2 *w = a.work + (size_t)pl * a.L;
     const int lane = threadIdx.x & 63;
     const double scale = 1.0 / (double)a.L;
-    int64_t n[SLOTS], m[SLOTS];
-    uint64_t o[SLOTS];
-    bool has[SLOTS];
+    QRange qr[SLOTS];
 #pragma unroll
     for (int slot = 0; slot < SLOTS; ++slot) {
         const uint64_t j = sub_of(a, pl, slot);
-        has[slot] = j < a.ns;
-        n[slot] = has[slot] ? (int64_t)a.len[j] : 0;
-        m[slot] = has[slot] ? (int64_t)a.mlen[j] : 0;
-        o[slot] = has[slot] ? a.ooff[j] : 0;
+        qr[slot] = j < a.ns ? q_range(a, j, (int64_t)a.len[j], (int64_t)a.mlen[j], a.ooff[j])
+                            : QRange{-1, 0, 0};
     }
     bool bad = false;
     auto ld = [&](int f, int e) { return w[(size_t)e * n2 + c0 + f]; };
-    // Called with the same row n1 on all 64 lanes (f = lane).
-    auto st1 = [&](int f, int n1, double2 x) {
+    // Parity of an integer-valued double below 2^53, exactly.
+    auto parity = [](double x) { return x != 2.0 * floor(0.5 * x); };
+    // Called with the same row n1 on all 64 lanes: entries q = qb + lane.
+    auto st1 = [&](int n1, double2 x) {
+        const int64_t qb = (int64_t)n2 * n1 + c0;
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
             const double v = (part ? x.y : x.x) * scale;
             const double rv = rint(v);
-            const int64_t iv = (int64_t)rv;
-            const bool off = fabs(v - rv) > 0.25 || rv < -0.25;
+            const uint64_t off = ballot64(fabs(v - rv) > 0.25 || rv < -0.25);
+            // PACK: rv = lo + 2^18 hi, lo < 2^18; parity(lo) = parity(rv).
+            const double hi = PACK ? floor(rv * (1.0 / kPackScale)) : 0.0;
 #pragma unroll
             for (int h = 0; h < PER_PART; ++h) {
-                const int slot = PER_PART * part + h;
-                if (!has[slot]) continue;                    // uniform
-                // Lane i holds q = n2*n1 + c0 + i, i.e. row r = rhi - i.
-                const int64_t rhi = n[slot] + (int64_t)a.mcap - 2 -
-                                    ((int64_t)n2 * n1 + c0);
-                const int64_t rlo = rhi - 63;
-                if (rhi < 0 || rlo >= m[slot]) continue;     // uniform
-                const int64_t r = rhi - f;
-                const bool need = r >= 0 && r < m[slot];
-                if (need && off) bad = true;
-                const bool bit = need && ((iv >> (h * kPackBits)) & 1);
-                const uint64_t word = __brevll(ballot64(bit));  // bit t = row rlo + t
-                if (lane == 0) put_rows(a.out, o[slot], rlo, word);
+                const QRange &r = qr[PER_PART * part + h];
+                if (qb > r.q0 || qb + 63 < r.qlo) continue;  // uniform
+                // Lanes whose entry is needed: [ilo, ihi].
+                const int64_t ilo = r.qlo > qb ? r.qlo - qb : 0;
+                const int64_t ihi = r.q0 - qb < 63 ? r.q0 - qb : 63;
+                const uint64_t need = (~0ull >> (63 - (ihi - ilo))) << ilo;
+                if (off & need) bad = true;
+                const uint64_t word = ballot64(parity(h ? hi : rv));
+                if (lane == 0) a.qbuf[r.widx + (qb >> 6)] = word;
             }
         }
     };
     auto st = [&](int f, int n0, int span, auto &v) {
+        (void)f;
 #pragma unroll
-        for (int r = 0; r < group_size(v); ++r) st1(f, n0 + r * span, v[r]);
+        for (int r = 0; r < group_size(v); ++r) st1(n0 + r * span, v[r]);
     };
     fft_run<kN1, kN1, true>(buf, a.tw64, ld, st);
-    if (bad) atomicCAS(a.status, 0, (int32_t)SSBH_E_PRECISION);
+    if (bad && lane == 0) atomicCAS(a.status, 0, (int32_t)SSBH_E_PRECISION);
+}
+
+// Output: sub-block j (blockIdx.x) writes its m_j rows at bit o_j of the
+// output.  Output word W holds rows R0 .. R0 + 63, R0 = 64 W - o_j, that is
+// entries q = Q0 - R0 - t: the 64-entry window from qa = Q0 - R0 - 63 taken
+// from its one or two parity words, bit-reversed.  Words wholly inside the
+// sub-block's range have no other writer (plain store); the two at its ends
+// are shared with the neighbours (atomic XOR into the zeroed output).
+__global__ __launch_bounds__(256) void k_fft_emit(FftArgs a) {
+    if (*a.status) return;
+    const uint64_t j = blockIdx.x;
+    const int64_t n = (int64_t)a.len[j], m = (int64_t)a.mlen[j];
+    if (n == 0 || m == 0) return;                   // all-zero rows
+    const uint64_t o = a.ooff[j];
+    const QRange r = q_range(a, j, n, m, o);
+    const uint64_t w0 = o >> 6, w1 = (o + (uint64_t)m - 1) >> 6;
+    for (uint64_t W = w0 + (uint64_t)blockIdx.y * 2048 + threadIdx.x;
+         W <= w1 && W < w0 + (uint64_t)(blockIdx.y + 1) * 2048; W += 256) {
+        const int64_t R0 = (int64_t)(64 * W) - (int64_t)o;
+        const int64_t tlo = R0 < 0 ? -R0 : 0;                  // first row bit
+        const int64_t thi = R0 + 63 < m ? 63 : m - 1 - R0;     // last row bit
+        // Needed entries of this word: q in [Q0 - R0 - thi, Q0 - R0 - tlo].
+        const int64_t qa = r.q0 - R0 - 63;
+        const int64_t qmin = r.q0 - R0 - thi, qmax = r.q0 - R0 - tlo;
+        const int64_t wa = qa >= 0 ? qa >> 6 : -1;
+        auto word_at = [&](int64_t qw) -> uint64_t {
+            return (qw >= (qmin >> 6) && qw <= (qmax >> 6)) ? a.qbuf[r.widx + qw] : 0ull;
+        };
+        const uint64_t lo = word_at(wa), hi = word_at(wa + 1);
+        const int sh = (int)(qa - 64 * wa);            // 0 .. 63
+        const uint64_t win = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+        // Bit k of win is entry qa + k, row R0 + 63 - k.
+        uint64_t bits = __brevll(win);                 // bit t = row R0 + t
+        bits &= (~0ull >> (63 - (thi - tlo))) << tlo;
+        if (tlo == 0 && thi == 63) a.out[W] = bits;
+        else if (bits) atomicXor((unsigned long long *)&a.out[W],
+                                 (unsigned long long)bits);
+    }
 }
 
 // Twiddle tables, computed once per transform length on the host in long
@@ -1050,6 +1090,10 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     if ((st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK) return st;
     if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
         return st;
+    // Parity words: the regions of q_range, out_cap_bits / 64 + 3 n_sub words.
+    if ((st = ws.fft_qbuf.reserve(((q.out_cap_bits >> 6) + 3ull * q.n_sub + 4) *
+                                  sizeof(uint64_t))) != SSBH_OK)
+        return st;
     FftArgs a{};
     uint64_t *plan = ws.plan.as<uint64_t>();
     a.sub = q.sub; a.len = q.len; a.woff = q.woff;
@@ -1085,6 +1129,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         }
     };
     a.out = q.out;
+    a.qbuf = ws.fft_qbuf.as<uint64_t>();
     a.status = q.status;
     const uint32_t tiles = a.n2 / kN1;
     a.per = per;
@@ -1134,6 +1179,14 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                 hipLaunchKernelGGL(k_fft_out<false>, dim3(tiles, np),
                                    dim3(kThreads), 0, stream, a);
         }
+    }
+    {
+        // Every sub-block's rows from the parity words, 2048 output words per
+        // workgroup (a sub-block spans at most m_cap / 64 + 2 of them).
+        TimedLaunch timed(ws.timer, "k_fft_emit", stream);
+        const uint64_t wmax = (q.m_cap >> 6) + 2;
+        hipLaunchKernelGGL(k_fft_emit, dim3(q.n_sub, (uint32_t)((wmax + 2047) / 2048)),
+                           dim3(256), 0, stream, a);
     }
     SSBH_CHECK_HIP(hipGetLastError());
     return SSBH_OK;

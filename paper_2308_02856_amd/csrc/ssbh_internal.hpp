@@ -78,6 +78,7 @@ struct Workspace {
     DevBuf counters;   // hashing: tile count, claim counter
     DevBuf fft_spec;   // FFT hash: seed spectrum (L complex doubles)
     DevBuf fft_work;   // FFT hash: transforms of a chunk of sub-block pairs
+    DevBuf fft_qbuf;   // FFT hash: parity words in transform order
     char last_schedule[48] = "";   // kernel and schedule of the last hash
     KernelTimer *timer = nullptr;  // per-kernel event timing (optional)
     void release();
