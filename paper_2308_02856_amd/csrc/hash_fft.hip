@@ -411,6 +411,39 @@ __device__ __forceinline__ void twiddle_run(const double2 (&v)[R], double2 w0,
     }
 }
 
+// 64-point FFTs down the 64 columns of a tile, 512 threads: column f =
+// lane, butterfly group j = wavefront.  Two radix-8 stages (the first's
+// group j writes elements 8j .. 8j+7, the second's group j reads j + 8k and
+// is twiddled by w_64^(k j)); the transposition between them goes through
+// LDS in two halves, real parts then imaginary parts, so `x` holds 64 x 64
+// doubles (32 KiB) instead of complex values.  `ld(f, e)` gives element e of
+// column f; `st(f, j, 8, v)` takes the second stage's group j (elements
+// j + 8r).
+template <bool INV, class Ld, class St>
+__device__ __forceinline__ void fft64_cols(double *x, const double2 *tw, Ld ld,
+                                           St st) {
+    const int f = threadIdx.x & 63, j = threadIdx.x >> 6;
+    double2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = ld(f, j + 8 * r);
+    dft8<INV>(v);
+    double2 u[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[(8 * j + r) * kN1 + f] = v[r].x;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k].x = x[(j + 8 * k) * kN1 + f];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[(8 * j + r) * kN1 + f] = v[r].y;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k].y = x[(j + 8 * k) * kN1 + f];
+    twiddle<kN1, kN1, 1, INV>(u, j, tw);
+    dft8<INV>(u);
+    st(f, j, 8, u);
+}
+
 __device__ __forceinline__ double2 omega_l(const FftArgs &a, uint64_t e) {
     return cmul(a.thi[e >> 9], a.tlo[e & 511]);
 }
@@ -457,7 +490,7 @@ __device__ __forceinline__ uint64_t sub_of(const FftArgs &a, uint32_t pl, int sl
 template <bool SEED, bool PACK>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     constexpr int SLOTS = PACK ? 4 : 2;
-    __shared__ double2 buf[kN1 * kN1];
+    __shared__ double buf[kN1 * kN1];
     __shared__ uint64_t win[SLOTS][kN1];
     if (*a.status) return;
     const uint32_t n2 = a.n2;
@@ -506,7 +539,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
         twiddle_run(v, omega_l(a, n2i * k0), omega_l(a, n2i * span),
                     [&](int r, double2 x) { y[(size_t)(k0 + r * span) * n2 + n2i] = x; });
     };
-    fft_run<kN1, kN1, false>(buf, a.tw64, ld, st);
+    fft64_cols<false>(buf, a.tw64, ld, st);
 }
 
 // ------------------------------------------------------------ row pass ---
@@ -774,7 +807,7 @@ __device__ __forceinline__ double2 omega_d(const FftArgs &a, int d, uint64_t e) 
 // this row.
 template <bool INV>
 __global__ __launch_bounds__(kThreads) void k_fft_mid(FftArgs a) {
-    __shared__ double2 buf[kN1 * kN1];
+    __shared__ double buf[kN1 * kN1];
     if (*a.status) return;
     const int d = a.lvl;
     const uint64_t P = a.L >> (6 * d);
@@ -797,7 +830,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_mid(FftArgs a) {
             y[(size_t)(k0 + r * span) * C + m] = x;
         });
     };
-    fft_run<kN1, kN1, INV>(buf, a.tw64, ld, st);
+    fft64_cols<INV>(buf, a.tw64, ld, st);
 }
 
 // Where the parities of sub-block j go.  Output row r of the sub-block is
@@ -838,12 +871,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     const double2 *w = a.work + (size_t)pl * a.L;
     const int lane = threadIdx.x & 63;
     const double scale = 1.0 / (double)a.L;
+    // The same for the whole workgroup: kept in scalar registers.
+    auto uni = [](int64_t x) {
+        const uint64_t u = (uint64_t)x;
+        return (int64_t)((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)u) |
+                         ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32));
+    };
     QRange qr[SLOTS];
 #pragma unroll
     for (int slot = 0; slot < SLOTS; ++slot) {
         const uint64_t j = sub_of(a, pl, slot);
-        qr[slot] = j < a.ns ? q_range(a, j, (int64_t)a.len[j], (int64_t)a.mlen[j], a.ooff[j])
-                            : QRange{-1, 0, 0};
+        const QRange r = j < a.ns ? q_range(a, j, (int64_t)a.len[j], (int64_t)a.mlen[j], a.ooff[j])
+                                  : QRange{-1, 0, 0};
+        qr[slot] = QRange{uni(r.q0), uni(r.qlo), uni(r.widx)};
     }
     bool bad = false;
     auto ld = [&](int f, int e) { return w[(size_t)e * n2 + c0 + f]; };
