@@ -124,3 +124,36 @@ def test_forced_packing_refused_for_long_sub_blocks(ctx):
     finally:
         ctx.set_fft_packing(0)
     assert e.value.status == ssbh.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("mode", ["two", "four", "stride"])
+def test_degenerate_sub_blocks_every_layout(ctx, orc, mode):
+    """Empty sub-blocks, m_j = 0, m_j = 1, m_j > n_j and outputs that start
+    and end inside a word, for two and four sub-blocks per transform and for
+    independent seeds (one per transform): the parity words go through the
+    scratch layout and the emit pass in every case."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    lens = np.array([0, 5, 64, 0, 1000, 3, 700, 65, 1, 130], dtype=np.uint64)
+    outl = np.array([4, 0, 100, 0, 333, 9, 1, 64, 1, 63], dtype=np.uint64)
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = uniform_bits(int(words.sum()) * 64, 12)
+    for j in range(len(lens)):          # clear the bits past n_j
+        r = int(lens[j]) % 64
+        if r and words[j]:
+            sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
+    ns = len(lens)
+    cap = int(outl.max())
+    stride = int(lens.max()) + cap - 1 + 7 if mode == "stride" else 0
+    seed_bits = stride * ns if stride else int(lens.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 13)
+    dl = torch.from_numpy(outl.view(np.int64)).cuda()
+    per_part = {"two": 1, "four": 2, "stride": 0}[mode]
+    got, tot, sched = fft_hash(ctx, per_part, to_dev(sub), to_dev(lens), to_dev(wo),
+                               ns, to_dev(seed), seed_bits, cap,
+                               out_rule=ssbh.OUT_EXPLICIT, out_len=dl, seed_stride=stride)
+    assert ":x%d:" % {"two": 2, "four": 4, "stride": 1}[mode] in sched, sched
+    want, wtot = orc.hash_batch(sub, lens, wo, outl, seed, seed_bits, stride, cap)
+    assert tot == wtot
+    assert np.array_equal(got[: want.size], want), first_diff(got[: want.size], want)
