@@ -1085,6 +1085,14 @@ uint64_t fft_length(uint64_t seed_bits) {
 // rounding error of an FFT convolution, a few eps log2(L) |x|_2 |s|_2
 // (Percival, Math. Comp. 72, 2003), stays below 1/100 for such L even for
 // all-one inputs, against the 1/4 every output is checked for.
+// Transforms of length L in `mib` MiB (at least one).  A chunk's transforms
+// are written by one pass and read by the next: below the 256 MB
+// last-level cache much of that traffic stays on chip (160 MiB measured
+// best at the batched length, 6 % less time per transform than 192 MiB).
+uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib) {
+    return (uint32_t)std::max<uint64_t>(1, (mib << 20) / (L * sizeof(double2)));
+}
+
 bool fft_can_pack(const HashRequest &q, uint64_t L) {
     return q.stride == 0 && q.seed_bits + 1 < q.m_cap + (1ull << kPackBits) &&
            L <= (1ull << 20);
@@ -1107,7 +1115,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
-    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : 32;
+    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : fft_chunk_of_bytes(L, 160);
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
@@ -1126,7 +1134,9 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     // Transforms ("pairs"): one per sub-block with independent seeds, else
     // one per two or four sub-blocks.
     const uint64_t pairs = (q.n_sub + per - 1ull) / per;
-    const uint32_t cp = solo ? 1u : (uint32_t)std::min<uint64_t>(pairs, chunk);
+    // Equal chunks of at most `chunk` transforms (no short last chunk).
+    const uint64_t nchunks = (pairs + chunk - 1) / chunk;
+    const uint32_t cp = solo ? 1u : (uint32_t)((pairs + nchunks - 1) / nchunks);
     if ((st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK) return st;
     if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
         return st;

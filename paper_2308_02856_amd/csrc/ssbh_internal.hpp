@@ -177,6 +177,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                             const FftSchedule &s, hipStream_t stream);
 uint64_t fft_length(uint64_t seed_bits);
 bool fft_can_pack(const HashRequest &q, uint64_t L);
+uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib);
 int fft_per_transform(const ssbh_ctx *ctx, const HashRequest &q, uint64_t L);
 
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,

@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "ssbh_internal.hpp"
 
 namespace ssbh {
@@ -47,7 +49,15 @@ std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
         c.push_back(k);
     }
     if (q.stride == 0 && fft_length(q.seed_bits) <= kMaxFftLength) {
-        for (uint32_t cp : {16u, 32u, 64u, 128u}) {
+        // Chunks of 64 .. 256 MiB of transforms (below, around and above the
+        // last-level cache), as transform counts at this length.
+        const uint64_t L = fft_length(q.seed_bits);
+        std::vector<uint32_t> cps;
+        for (uint64_t mib : {64ull, 128ull, 160ull, 192ull, 256ull}) {
+            const uint32_t cp = fft_chunk_of_bytes(L, mib);
+            if (std::find(cps.begin(), cps.end(), cp) == cps.end()) cps.push_back(cp);
+        }
+        for (uint32_t cp : cps) {
             Candidate k;
             k.mfma = false;
             k.fft = true;
