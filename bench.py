@@ -76,14 +76,15 @@ def kernel_source_digest(kernel: str) -> str:
 
 def load_traffic(kernel: str, workload: str, schedule: str):
     """HBM bytes per launch from committed PMC counters, if they were taken
-    on the same kernel source and schedule."""
+    on the same kernel source and schedule (one record per schedule the
+    tuner may pick)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as fh:
             data = json.load(fh)
-        rec = data.get(f"{kernel}:{workload}")
+        rec = data.get(f"{kernel}:{workload}:{schedule}")
         if not rec or rec.get("source_digest") != kernel_source_digest(kernel):
             return None
         if rec.get("schedule") != schedule:
