@@ -76,17 +76,25 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+hipEvent_t KernelTimer::take() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) { e = pool.back(); pool.pop_back(); }
+    else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    return e;
+}
+
 int KernelTimer::begin(const char *name, hipStream_t stream) {
-    auto take = [&]() {
-        hipEvent_t e = nullptr;
-        if (!pool.empty()) { e = pool.back(); pool.pop_back(); }
-        else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
-        return e;
-    };
     Rec r{name, take(), take()};
     if (r.start) (void)hipEventRecord(r.start, stream);
     recs.push_back(r);
     return (int)recs.size() - 1;
+}
+
+void KernelTimer::begin_ext(const char *name, hipEvent_t *start, hipEvent_t *stop) {
+    Rec r{name, take(), take()};
+    recs.push_back(r);
+    *start = r.start;
+    *stop = r.stop;
 }
 
 void KernelTimer::end(int idx, hipStream_t stream) {

@@ -46,6 +46,8 @@
 
 #include <stdio.h>
 
+#include <hip/hip_ext.h>
+
 #include "ssbh_internal.hpp"
 
 namespace ssbh {
@@ -1027,9 +1029,23 @@ ssbh_status get_tables(int device, uint64_t L, FftTables **out) {
     return SSBH_OK;
 }
 
+// Launch `kernel`; with the workspace's timer on, through
+// hipExtLaunchKernelGGL so that its events mark the kernel's own start and
+// end (not the dispatch around it, as events recorded on the stream would).
+template <class K, class... A>
+void launch_timed(Workspace *ws, const char *name, K kernel, dim3 grid, dim3 block,
+                  hipStream_t stream, A... args) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ws && ws->timer) ws->timer->begin_ext(name, &e0, &e1);
+    if (e0 && e1)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, e0, e1, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+}
+
 template <int N2>
 void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
-                 hipStream_t stream) {
+                 hipStream_t stream, Workspace *ws) {
     // Rows per transform (64, 4096 or 2^18) are a multiple of the rows per
     // workgroup (a power of two up to 32).
     const uint32_t rows = (uint32_t)(a.L / N2);
@@ -1039,26 +1055,27 @@ void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
         hipLaunchKernelGGL((k_fft_rows<N2, true>), grid, dim3(rp_threads(N2)),
                            0, stream, a);
     else
-        hipLaunchKernelGGL((k_fft_rows<N2, false>), grid, dim3(rp_threads(N2)),
-                           0, stream, a);
+        launch_timed(ws, "k_fft_rows", k_fft_rows<N2, false>, grid,
+                     dim3(rp_threads(N2)), stream, a);
 }
 
-void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream) {
+void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream,
+          Workspace *ws = nullptr) {
     switch (a.nr) {
-    case 64: launch_rows<64>(a, pairs, spec, stream); break;
-    case 128: launch_rows<128>(a, pairs, spec, stream); break;
-    case 192: launch_rows<192>(a, pairs, spec, stream); break;
-    case 256: launch_rows<256>(a, pairs, spec, stream); break;
-    case 384: launch_rows<384>(a, pairs, spec, stream); break;
-    case 512: launch_rows<512>(a, pairs, spec, stream); break;
-    case 768: launch_rows<768>(a, pairs, spec, stream); break;
-    case 1024: launch_rows<1024>(a, pairs, spec, stream); break;
-    case 1536: launch_rows<1536>(a, pairs, spec, stream); break;
-    case 2048: launch_rows<2048>(a, pairs, spec, stream); break;
-    case 3072: launch_rows<3072>(a, pairs, spec, stream); break;
-    case 4096: launch_rows<4096>(a, pairs, spec, stream); break;
-    case 6144: launch_rows<6144>(a, pairs, spec, stream); break;
-    default: launch_rows<8192>(a, pairs, spec, stream); break;
+    case 64: launch_rows<64>(a, pairs, spec, stream, ws); break;
+    case 128: launch_rows<128>(a, pairs, spec, stream, ws); break;
+    case 192: launch_rows<192>(a, pairs, spec, stream, ws); break;
+    case 256: launch_rows<256>(a, pairs, spec, stream, ws); break;
+    case 384: launch_rows<384>(a, pairs, spec, stream, ws); break;
+    case 512: launch_rows<512>(a, pairs, spec, stream, ws); break;
+    case 768: launch_rows<768>(a, pairs, spec, stream, ws); break;
+    case 1024: launch_rows<1024>(a, pairs, spec, stream, ws); break;
+    case 1536: launch_rows<1536>(a, pairs, spec, stream, ws); break;
+    case 2048: launch_rows<2048>(a, pairs, spec, stream, ws); break;
+    case 3072: launch_rows<3072>(a, pairs, spec, stream, ws); break;
+    case 4096: launch_rows<4096>(a, pairs, spec, stream, ws); break;
+    case 6144: launch_rows<6144>(a, pairs, spec, stream, ws); break;
+    default: launch_rows<8192>(a, pairs, spec, stream, ws); break;
     }
 }
 
@@ -1199,44 +1216,35 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         const uint32_t np = (uint32_t)std::min<uint64_t>(cp, pairs - p0);
         if (solo) spectrum(p0 * q.stride);
         a.pair0 = (uint32_t)p0;
-        {
-            TimedLaunch timed(ws.timer, "k_fft_cols", stream);
-            if (per == 4)
-                hipLaunchKernelGGL((k_fft_cols<false, true>), dim3(tiles, np),
-                                   dim3(kThreads), 0, stream, a);
-            else
-                hipLaunchKernelGGL((k_fft_cols<false, false>), dim3(tiles, np),
-                                   dim3(kThreads), 0, stream, a);
-        }
+        if (per == 4)
+            launch_timed(&ws, "k_fft_cols", k_fft_cols<false, true>, dim3(tiles, np),
+                         dim3(kThreads), stream, a);
+        else
+            launch_timed(&ws, "k_fft_cols", k_fft_cols<false, false>, dim3(tiles, np),
+                         dim3(kThreads), stream, a);
         if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
             mids(false, np);
         }
-        {
-            TimedLaunch timed(ws.timer, "k_fft_rows", stream);
-            rows(a, np, false, stream);
-        }
+        rows(a, np, false, stream, &ws);
         if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
             mids(true, np);
         }
-        {
-            TimedLaunch timed(ws.timer, "k_fft_out", stream);
-            if (per == 4)
-                hipLaunchKernelGGL(k_fft_out<true>, dim3(tiles, np),
-                                   dim3(kThreads), 0, stream, a);
-            else
-                hipLaunchKernelGGL(k_fft_out<false>, dim3(tiles, np),
-                                   dim3(kThreads), 0, stream, a);
-        }
+        if (per == 4)
+            launch_timed(&ws, "k_fft_out", k_fft_out<true>, dim3(tiles, np),
+                         dim3(kThreads), stream, a);
+        else
+            launch_timed(&ws, "k_fft_out", k_fft_out<false>, dim3(tiles, np),
+                         dim3(kThreads), stream, a);
     }
     {
         // Every sub-block's rows from the parity words, 2048 output words per
         // workgroup (a sub-block spans at most m_cap / 64 + 2 of them).
-        TimedLaunch timed(ws.timer, "k_fft_emit", stream);
         const uint64_t wmax = (q.m_cap >> 6) + 2;
-        hipLaunchKernelGGL(k_fft_emit, dim3(q.n_sub, (uint32_t)((wmax + 2047) / 2048)),
-                           dim3(256), 0, stream, a);
+        launch_timed(&ws, "k_fft_emit", k_fft_emit,
+                     dim3(q.n_sub, (uint32_t)((wmax + 2047) / 2048)), dim3(256),
+                     stream, a);
     }
     SSBH_CHECK_HIP(hipGetLastError());
     return SSBH_OK;

@@ -56,8 +56,13 @@ struct KernelTimer {
     std::vector<hipEvent_t> pool;
     int begin(const char *name, hipStream_t stream);
     void end(int idx, hipStream_t stream);
+    // Events for a launch that records them itself (hipExtLaunchKernelGGL:
+    // the kernel's own start and end, without the dispatch around it).
+    void begin_ext(const char *name, hipEvent_t *start, hipEvent_t *stop);
     std::string report();          // waits, aggregates, clears
     ~KernelTimer();
+private:
+    hipEvent_t take();             // from the pool, else a new event
 };
 
 struct TimedLaunch {
