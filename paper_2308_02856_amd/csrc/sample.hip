@@ -193,6 +193,8 @@ __global__ __launch_bounds__(64) void k_scan_part(SampleArgs a) {
     if (j >= a.ns) return;
     const uint32_t s0 = c * kSegChunk, s1 = min(s0 + kSegChunk, a.nseg);
     uint32_t sum = 0;
+    // Unrolled so that a thread's loads are in flight together.
+#pragma unroll 16
     for (uint32_t s = s0; s < s1; ++s) sum += a.counts[(uint64_t)s * a.ns + j];
     a.part[(uint64_t)c * a.ns + j] = sum;
 }
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(64) void k_scan_mid(SampleArgs a) {
     const uint32_t j = blockIdx.x * 64 + threadIdx.x;
     if (j >= a.ns) return;
     uint64_t run = 0;
+#pragma unroll 16
     for (uint32_t c = 0; c < a.nchunk; ++c) {
         const uint32_t t = a.part[(uint64_t)c * a.ns + j];
         a.part[(uint64_t)c * a.ns + j] = (uint32_t)run;
@@ -217,6 +220,7 @@ __global__ __launch_bounds__(64) void k_scan_offs(SampleArgs a) {
     if (j >= a.ns) return;
     const uint32_t s0 = c * kSegChunk, s1 = min(s0 + kSegChunk, a.nseg);
     uint32_t run = a.part[(uint64_t)c * a.ns + j];
+#pragma unroll 16
     for (uint32_t s = s0; s < s1; ++s) {
         a.offs[(uint64_t)s * a.ns + j] = run;
         run += a.counts[(uint64_t)s * a.ns + j];
