@@ -176,8 +176,9 @@ def run_batched(ctx, ssbh, args):
     hash_ms = time_events(hash_, max(3, args.steps))
     schedule = ctx.last_schedule()
     samp_ms = time_events(sample, max(3, args.steps))
-    # Per-kernel durations: HIP events recorded by the library around each
-    # launch, on the launch stream.
+    # Per-kernel durations from the library's HIP events on the launch
+    # stream: the FFT passes' launches record their own start and end
+    # (hipExtLaunchKernelGGL), the other kernels are bracketed by events.
     ctx.set_timing(True)
     reps = max(3, args.steps)
     for _ in range(reps):

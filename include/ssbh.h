@@ -429,11 +429,13 @@ ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm,
                                    int ksplit);
 
 /* Per-kernel timing: with on = 1, the synchronous entry points of this
- * context record a HIP event before and after each launch of their main
- * kernels (k_hist, k_scatter, k_perm_gather, k_toeplitz_valu,
- * k_toeplitz_mfma, k_fft_spectrum, k_fft_cols, k_fft_rows, k_fft_out) on the
- * launch stream; on = 0 stops it and frees the events.  Graph pipelines and
- * serving jobs are never timed. */
+ * context time each launch of their main kernels (k_hist, k_scatter,
+ * k_perm_gather, k_toeplitz_valu, k_toeplitz_mfma, k_fft_spectrum, k_fft_cols,
+ * k_fft_rows, k_fft_out, k_fft_emit) with a pair of HIP events on the launch
+ * stream: k_fft_cols, k_fft_rows (not the spectrum's), k_fft_out and
+ * k_fft_emit record them in the launch itself (the kernel's start and end),
+ * the others are bracketed by them.  on = 0 stops it and frees the events.
+ * Graph pipelines and serving jobs are never timed. */
 ssbh_status ssbh_set_timing(ssbh_ctx *ctx, int on);
 
 /* Wait for the recorded launches and write one line per kernel,
