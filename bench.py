@@ -704,8 +704,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding of this path is described in DESIGN.md "
-              "and is not run.", file=sys.stderr)
+              "the path is not sharded over several GPUs.", file=sys.stderr)
         return 2
 
     import torch
