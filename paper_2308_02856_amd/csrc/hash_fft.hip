@@ -894,22 +894,20 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     // Called with the same row n1 on all 64 lanes: entries q = qb + lane.
     auto st1 = [&](int n1, double2 x) {
         const int64_t qb = (int64_t)n2 * n1 + c0;
+        const int64_t q = qb + lane;
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
             const double v = (part ? x.y : x.x) * scale;
             const double rv = rint(v);
-            const uint64_t off = ballot64(fabs(v - rv) > 0.25 || rv < -0.25);
+            const bool off = fabs(v - rv) > 0.25 || rv < -0.25;
             // PACK: rv = lo + 2^18 hi, lo < 2^18; parity(lo) = parity(rv).
             const double hi = PACK ? floor(rv * (1.0 / kPackScale)) : 0.0;
 #pragma unroll
             for (int h = 0; h < PER_PART; ++h) {
                 const QRange &r = qr[PER_PART * part + h];
                 if (qb > r.q0 || qb + 63 < r.qlo) continue;  // uniform
-                // Lanes whose entry is needed: [ilo, ihi].
-                const int64_t ilo = r.qlo > qb ? r.qlo - qb : 0;
-                const int64_t ihi = r.q0 - qb < 63 ? r.q0 - qb : 63;
-                const uint64_t need = (~0ull >> (63 - (ihi - ilo))) << ilo;
-                if (off & need) bad = true;
+                // Only the needed entries [qlo, q0] count as off.
+                if (off && q >= r.qlo && q <= r.q0) bad = true;
                 const uint64_t word = ballot64(parity(h ? hi : rv));
                 if (lane == 0) a.qbuf[r.widx + (qb >> 6)] = word;
             }
