@@ -204,11 +204,19 @@ __global__ __launch_bounds__(64) void k_scan_mid(SampleArgs a) {
     const uint32_t j = blockIdx.x * 64 + threadIdx.x;
     if (j >= a.ns) return;
     uint64_t run = 0;
-#pragma unroll 16
-    for (uint32_t c = 0; c < a.nchunk; ++c) {
-        const uint32_t t = a.part[(uint64_t)c * a.ns + j];
-        a.part[(uint64_t)c * a.ns + j] = (uint32_t)run;
-        run += t;
+    // 16 loads before their stores, so that they are in flight together
+    // (the stores could otherwise alias later loads).
+    for (uint32_t c0 = 0; c0 < a.nchunk; c0 += 16) {
+        uint32_t t[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            t[k] = c0 + k < a.nchunk ? a.part[(uint64_t)(c0 + k) * a.ns + j] : 0u;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (c0 + k < a.nchunk) {
+                a.part[(uint64_t)(c0 + k) * a.ns + j] = (uint32_t)run;
+                run += t[k];
+            }
     }
     a.len[j] = run;
 }
@@ -220,10 +228,18 @@ __global__ __launch_bounds__(64) void k_scan_offs(SampleArgs a) {
     if (j >= a.ns) return;
     const uint32_t s0 = c * kSegChunk, s1 = min(s0 + kSegChunk, a.nseg);
     uint32_t run = a.part[(uint64_t)c * a.ns + j];
-#pragma unroll 16
-    for (uint32_t s = s0; s < s1; ++s) {
-        a.offs[(uint64_t)s * a.ns + j] = run;
-        run += a.counts[(uint64_t)s * a.ns + j];
+    // 16 loads before their stores, as in k_scan_mid.
+    for (uint32_t b0 = s0; b0 < s1; b0 += 16) {
+        uint32_t cnt[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            cnt[k] = b0 + k < s1 ? a.counts[(uint64_t)(b0 + k) * a.ns + j] : 0u;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (b0 + k < s1) {
+                a.offs[(uint64_t)(b0 + k) * a.ns + j] = run;
+                run += cnt[k];
+            }
     }
 }
 
