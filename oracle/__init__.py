@@ -68,6 +68,10 @@ def _load():
         lib.ssbo_sift.restype = i32
         lib.ssbo_sift.argtypes = [U64P, U64P, U64P, U64P, u32, U64P, u64,
                                   U64P, U64P]
+        lib.ssbo_shuffle_choice.restype = u64
+        lib.ssbo_shuffle_choice.argtypes = [u64, u64, u64]
+        lib.ssbo_permutation.restype = i32
+        lib.ssbo_permutation.argtypes = [u64, u64, U32P]
         lib.ssbo_permute_split.restype = i32
         lib.ssbo_permute_split.argtypes = [U64P, u64, U32P, u32, U64P, U64P,
                                            U64P]
@@ -167,6 +171,20 @@ def partition(a, n: int, v, n_sub: int):
         raise ValueError("bad assignment")
     used = int(wo[n_sub - 1] + (ln[n_sub - 1] + 63) // 64) if n_sub else 0
     return sub[:used], ln[:n_sub], wo[:n_sub]
+
+
+def shuffle_choice(key: int, n: int, i: int) -> int:
+    """j_i of the keyed shuffle: the index exchanged with entry i."""
+    return int(_load().ssbo_shuffle_choice(key & (2**64 - 1), n, i))
+
+
+def permutation(n: int, key: int) -> np.ndarray:
+    """Keyed Durstenfeld shuffle of 0..n-1 (uint32), the permutation of
+    the permute-split mode."""
+    perm = np.zeros(max(1, n), dtype=np.uint32)
+    if _load().ssbo_permutation(key & (2**64 - 1), n, _p32(perm)):
+        raise ValueError("n > 2^32")
+    return perm[:n]
 
 
 def permute_split(a, n: int, perm, n_sub: int):

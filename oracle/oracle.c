@@ -161,6 +161,32 @@ int ssbo_sift(const uint64_t *sub, const uint64_t *keep_sub,
     return 0;
 }
 
+/* Keyed permutation of 0..n-1 (the permute-split sampling of the small and
+ * contraction workloads; not in the paper, which draws V_i i.i.d.).
+ * Durstenfeld's form of the Fisher-Yates shuffle (R. Durstenfeld, CACM 7(7),
+ * 1964, Algorithm 235): start from the identity and, for i = n-1 down to 1,
+ * exchange entries i and j_i, where j_i is uniform in [0, i].  Here j_i is
+ * the high word of the 128-bit product r_t * (i + 1), r_t = output
+ * t = n-1-i of the SplitMix64 stream of `key` (Lemire's multiply-shift map
+ * without the rejection step; its bias is below (i+1)/2^64).  Writes perm[],
+ * returns 0, or -1 for n > 2^32. */
+uint64_t ssbo_shuffle_choice(uint64_t key, uint64_t n, uint64_t i) {
+    uint64_t r = ssbo_splitmix64(key, n - 1 - i);
+    return (uint64_t)(((unsigned __int128)r * (i + 1)) >> 64);
+}
+
+int ssbo_permutation(uint64_t key, uint64_t n, uint32_t *perm) {
+    if (n > (1ull << 32)) return -1;
+    for (uint64_t k = 0; k < n; ++k) perm[k] = (uint32_t)k;
+    for (uint64_t i = n; i-- > 1;) {
+        uint64_t j = ssbo_shuffle_choice(key, n, i);
+        uint32_t t = perm[i];
+        perm[i] = perm[j];
+        perm[j] = t;
+    }
+    return 0;
+}
+
 /* Permutation then contiguous split: B[k] = A[perm[k]], sub-block j is
  * B[jL, (j+1)L) with L = n / n_sub, starting at word j*ceil(L/64).
  * Returns -1 when n_sub does not divide n or perm is out of range. */

@@ -118,6 +118,16 @@ def test_draw_v_range_and_uniformity(orc):
     assert chi2 < 30.0  # 6 dof; p ~ 4e-5
 
 
+@pytest.mark.parametrize("ns", [3, 7, 13, 1000, 2049, 12345])
+def test_draw_v_is_a_monotone_even_range_map(orc, ns):
+    """For any N_S (not only powers of two) V_i is a non-decreasing function
+    of u_i that spreads [0, 2^32) evenly over [0, N_S) (tests/pin_checks.py;
+    a reduction u mod N_S, also uniform, fails it)."""
+    from tests.pin_checks import check_v_map
+    check_v_map(orc.draw_v, orc.splitmix64, ns,
+                count=max(20000, 25 * ns) if ns < 5000 else 20000)
+
+
 def test_assign_iid_matches_single_draws(orc):
     v = orc.assign_iid(1001, 13, 5)
     assert all(int(v[i]) == orc.draw_v(5, i, 13) for i in range(1001))
@@ -189,6 +199,59 @@ def test_permute_split_equals_fancy_indexing(orc, n, ns):
         assert np.array_equal(got[:L], b[j * L:(j + 1) * L])
         assert not got[L:].any()
     assert np.all(ln == L)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 64, 1000, 65537])
+def test_keyed_permutation_is_a_permutation(orc, n):
+    for key in (0, 7, 2**64 - 1):
+        perm = orc.permutation(n, key)
+        assert perm.dtype == np.uint32 and perm.size == n
+        assert np.array_equal(np.sort(perm), np.arange(n, dtype=np.uint32))
+
+
+def test_keyed_permutation_choices(orc):
+    """The exchange index j_i of step i is uniform in [0, i]: it is a
+    non-decreasing function of the stream output r_{n-1-i} (pinned by the
+    published SplitMix64 values) with j_i / (i+1) within 1/(i+1) of
+    r / 2^64.  The last entry is set once, by the first step, so
+    perm[n-1] = j_{n-1}."""
+    n = 1000
+    for i in (1, 2, 5, 999):
+        rs, js = [], []
+        for key in range(3000):
+            r = orc.splitmix64(key, n - 1 - i)
+            j = orc.shuffle_choice(key, n, i)
+            assert 0 <= j <= i
+            assert abs(j / (i + 1) - r / 2.0 ** 64) <= 1.0 / (i + 1)
+            rs.append(r)
+            js.append(j)
+        order = np.argsort(np.array(rs, dtype=np.uint64), kind="stable")
+        assert np.all(np.diff(np.array(js)[order]) >= 0)
+    for key in range(200):
+        for m in (2, 3, 17, 1000):
+            assert int(orc.permutation(m, key)[m - 1]) == \
+                orc.shuffle_choice(key, m, m - 1)
+    # n = 2: the one step swaps exactly when j_1 = 0, i.e. r_0 < 2^63.
+    for key in range(200):
+        swapped = orc.permutation(2, key).tolist() == [1, 0]
+        assert swapped == (orc.splitmix64(key, 0) < 2 ** 63)
+
+
+@pytest.mark.parametrize("n,keys", [(3, 3000), (4, 6000), (5, 24000)])
+def test_keyed_permutation_is_uniform_over_all_orderings(orc, n, keys):
+    """Over many keys every one of the n! orderings appears, equally often
+    (chi-square; Sattolo's variant, which only makes cycles, or a biased
+    exchange index would fail)."""
+    counts = {}
+    for key in range(keys):
+        t = tuple(orc.permutation(n, 0x1000 + 7919 * key).tolist())
+        counts[t] = counts.get(t, 0) + 1
+    cells = math.factorial(n)
+    assert len(counts) == cells
+    e = keys / cells
+    chi2 = sum((c - e) ** 2 / e for c in counts.values())
+    dof = cells - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof) + 10, chi2
 
 
 def test_permute_split_rejects_indivisible(orc):
@@ -544,6 +607,25 @@ def test_geat_rate_tends_to_asymptotic_bbm92_rate(orc):
     assert all(r < asym for r in rates)
     assert all(b > a for a, b in zip(rates, rates[1:]))
     assert rates[-1] == pytest.approx(asym, rel=2e-3)
+
+
+def test_geat_bound_is_at_least_eq1_of_sec_ii(orc):
+    """Sec. II Eq. (1), H >= N h - v1 sqrt(N) - v0, is the App. A bound at
+    one particular alpha, bounded from below with xi, beta(eps), gamma(eps);
+    so the oracle's bound, maximised over alpha, can only be larger, and its
+    sqrt(N) coefficient is at most v1 (tests/pin_checks.py)."""
+    from tests.pin_checks import check_geat_eq1
+    check_geat_eq1(orc.geat_key_length)
+
+
+def test_geat_bound_has_the_closed_form_large_n_expansion(orc):
+    """N h - max_alpha bound = c1 sqrt(N) + c0 + o(1) with the closed forms
+    c1 = V sqrt(2 ln2 (g + L)) and c0 = g + 2L + 2 (g + L) K(0) / (ln2 V^2)
+    derived from App. A in tests/pin_checks.py; this fixes the V^2 term, the
+    squared (alpha - 1)/(2 - alpha) on K', d_X^2 inside V and the alpha
+    log2(1/p_Omega) term."""
+    from tests.pin_checks import check_geat_expansion
+    check_geat_expansion(orc.geat_key_length)
 
 
 def test_geat_diverges_at_both_ends_of_alpha(orc):
