@@ -98,6 +98,25 @@ def kernel_avgs(rep: dict) -> dict:
     return {k: round(ms * 1e3 / n, 2) for k, (n, ms) in rep.items()}
 
 
+DIGESTS = os.path.join(ROOT, "tests", "golden", "digests.json")
+
+
+def load_digests() -> dict:
+    """SHA-256 digests of the oracle's whole outputs on the benchmark's
+    inputs, written by tests/golden/make_digests.py (oracle only)."""
+    try:
+        with open(DIGESTS) as fh:
+            return json.load(fh)
+    except OSError:
+        return {}
+
+
+def words_digest(words: np.ndarray, bits: int) -> str:
+    nw = (int(bits) + 63) // 64
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64)[:nw])
+    return hashlib.sha256(w.astype("<u8").tobytes()).hexdigest()
+
+
 def time_events(fn, reps: int) -> list[float]:
     """Milliseconds of each call of fn, from HIP events on the current stream."""
     import torch
@@ -249,7 +268,18 @@ def run_single(ctx, ssbh, args):
         words[name] = out.clone()
     res["fft_equals_valu"] = bool(torch.equal(words["valu"], words["fft"]))
     res["ms"] = min(res["ms_valu"], res["ms_fft"])
+    res["oracle_digest_equal"] = digest_equal("single", words["fft"], m)
     return res
+
+
+def digest_equal(workload: str, out, bits: int):
+    """The whole output against the oracle's SHA-256 of it (None when the
+    digest file has no entry for the workload)."""
+    ref = load_digests().get(workload)
+    if not ref:
+        return None
+    return (int(bits) == ref["bits"] and
+            words_digest(to_host(out), bits) == ref["sha256"])
 
 
 # ------------------------------------------------------------------ Table I
@@ -368,12 +398,14 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     2^16 output bits each from one shared seed: the gather, then the hash on
     the int8 matrix cores and on the bit-sliced VALU kernel (same bits)."""
     import torch
-    from workloads import config, permutation_device, uniform_bits
+    from workloads import config, uniform_bits
     c = config("contraction")
     n, ns, L, m = c["n_bits"], c["n_sub"], c["sub_bits"], c["out_a"]
     log(f"contraction: {n} bits, permutation split into {ns} x {L}")
     d_in = to_dev(uniform_bits(n, c["input_seed"]))
-    perm = permutation_device(n, c["perm_seed"])
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    perm_ms = float(np.mean(time_events(
+        lambda: ctx.permutation(c["perm_key"], n, out=perm), 2)))
     seed_bits = L + m - 1
     seed = to_dev(uniform_bits(seed_bits, c["seed_seed"]))
     sub_cap = ns * (L // 64)
@@ -406,6 +438,7 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     same = bool(torch.equal(out, outv)) and int(st.item()) == 0
     same_fft = bool(torch.equal(out, outf))
     same_f4 = bool(torch.equal(out, out4))
+    oracle_equal = digest_equal("contraction", out, ns * m)
     g_ms = float(np.mean(time_events(sample, 3)))
     mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
     mfma_sched = ctx.last_schedule()
@@ -417,7 +450,8 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     torch.cuda.empty_cache()
     return {
         "workload": "contraction", "n_bits": n, "n_sub": ns, "sub_bits": L,
-        "m_bits": m, "gather_ms": round(g_ms, 3),
+        "m_bits": m, "permutation_ms": round(perm_ms, 3),
+        "gather_ms": round(g_ms, 3),
         "mfma_ms": round(mf_ms, 3), "valu_ms": round(va_ms, 3),
         "gbps_step_mfma": round(n / ((g_ms + mf_ms) * 1e-3) / 1e9, 3),
         "gbps_hash_mfma": round(n / (mf_ms * 1e-3) / 1e9, 3),
@@ -434,6 +468,7 @@ def run_contraction(ctx, ssbh, args, peak_alu):
         "mfma_equals_valu": same,
         "fft_equals_mfma": same_fft,
         "mfma_f4_equals_int8": same_f4,
+        "oracle_digest_equal": oracle_equal,
         "mfma_traffic": load_traffic("k_toeplitz_mfma", "contraction",
                                      mfma_sched),
     }
@@ -446,13 +481,13 @@ def run_small(ctx, ssbh, args):
     2^14 output bits each from independent seeds): eager calls against one
     replay of the captured HIP graph, per pass."""
     import torch
-    from workloads import config, permutation, uniform_bits
+    from workloads import config, uniform_bits
     c = config("small")
     n, ns, L, m = c["n_bits"], c["n_sub"], c["sub_bits"], c["out_a"]
     stride = L + m - 1
     seed_bits = ns * stride
     d_in = to_dev(uniform_bits(n, c["input_seed"]))
-    perm = torch.from_numpy(permutation(n, c["perm_seed"]).view(np.int32)).cuda()
+    perm = ctx.permutation(c["perm_key"], n)
     seed = to_dev(uniform_bits(seed_bits, c["seed_seed"]))
     sub_cap = ns * (L // 64)
     sub = torch.empty(sub_cap, dtype=torch.int64, device="cuda")
@@ -511,34 +546,32 @@ def run_serving(ssbh, args):
     threshold, independent seeds from the job's key, hash, concatenation),
     admitted FIFO under an HBM budget; latency = submit -> results ready."""
     import torch
-    from workloads import CONFIGS, serving_jobs, serving_pools
+    from workloads import (CONFIGS, serving_input_device, serving_jobs,
+                           serving_planes)
     cfg = CONFIGS["serving"]
     total = args.serve_jobs + args.serve_warmup
     jobs = serving_jobs(total, seed=cfg["stream_seed"], rate_hz=cfg["rate_hz"],
                         log2_n=cfg["log2_n"], log2_sub=cfg["log2_sub"],
                         q=cfg["q"], p=cfg["p"])
-    log(f"serving: input pools and {total} jobs")
-    ps, pools = serving_pools(levels=4, pool_bits=1 << 28, p=cfg["p"])
-    d_pools = [to_dev(pl) for pl in pools]
-    del pools
+    log(f"serving: {total} job inputs, each Bernoulli(p) with its own p")
+    d_planes = [to_dev(pl) for pl in serving_planes()]
     ctx = ssbh.Context(0, hbm_budget=args.serve_budget_mib << 20)
     made = []
     for jb in jobs:
-        k = int(np.argmin([abs(jb["p"] - pk) for pk in ps]))
-        nw = (jb["n_bits"] + 63) // 64
-        off = (jb["index"] * 7919) % max(1, d_pools[k].numel() - nw + 1)
-        job, out = ctx.make_job(d_pools[k][off:off + nw], jb["n_bits"],
-                                jb["n_sub"], jb["sample_key"], jb["seed_key"],
+        d_in = serving_input_device(jb, d_planes)
+        job, out = ctx.make_job(d_in, jb["n_bits"], jb["n_sub"],
+                                jb["sample_key"], jb["seed_key"],
                                 ssbh.OUT_RATIO, jb["ratio_num"],
                                 jb["ratio_den"])
-        made.append((jb, job, out))
+        made.append((jb, job, out, d_in))
+    del d_planes
     torch.cuda.synchronize()
     ids = [None] * len(made)
     log(f"serving: submitting {total} jobs at {cfg['rate_hz']:.0f}/s")
     t_start = time.perf_counter()
 
     def submitter():
-        for i, (jb, job, _) in enumerate(made):
+        for i, (jb, job, _, _) in enumerate(made):
             delay = t_start + jb["arrival_s"] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
@@ -567,6 +600,7 @@ def run_serving(ssbh, args):
         time.sleep(0.0005)
     th.join()
     ctx.close()
+    checked, equal = serving_digest_check(made, results)
     meas = range(args.serve_warmup, len(made))
     lat = np.array([(results[i].t_done - results[i].t_submit) * 1e3
                     for i in meas])
@@ -598,7 +632,29 @@ def run_serving(ssbh, args):
             "busy_frac": round(busy / (t1 - t0), 4),
             "ok": sum(1 for i in meas if results[i].status == 0),
             "aborted": sum(1 for i in meas if results[i].status == -2),
-            "errors": sum(1 for i in meas if results[i].status not in (0, -2))}
+            "errors": sum(1 for i in meas if results[i].status not in (0, -2)),
+            "oracle_checked_jobs": checked, "oracle_digests_equal": equal}
+
+
+def serving_digest_check(made, results):
+    """Every job of the stream that the oracle's digest file covers (all
+    jobs below 2^24 input bits and 20 larger ones) against the oracle's
+    SHA-256 of its whole output."""
+    ref = load_digests().get("serving")
+    if not ref or len(made) != ref["stream_jobs"]:
+        return 0, None
+    equal = True
+    for idx in ref["checked"]:
+        want = ref["jobs"].get(str(idx))
+        if want is None:
+            return 0, None
+        r = results[idx]
+        if want["status"] == "abort":
+            equal = equal and r.status == -2
+            continue
+        equal = (equal and r.status == 0 and r.out_bits == want["bits"] and
+                 words_digest(to_host(made[idx][2]), r.out_bits) == want["sha256"])
+    return len(ref["checked"]), equal
 
 
 # -------------------------------------------------------------- cpu oracle
@@ -825,6 +881,8 @@ def main() -> int:
         "kernel_avg_us": {**kernel_avgs(res["sample_kernels"]),
                           **kernel_avgs(res["hash_kernels"])},
         "tuning": res["tune_report"].strip().splitlines(),
+        "oracle_digest_equal": digest_equal("batched", res["out"],
+                                            int(res["mlen"].sum())),
     }
     if single is not None:
         sg = single["n"] / (single["ms"] * 1e-3) / 1e9
@@ -834,6 +892,7 @@ def main() -> int:
             "ms_valu": round(single["ms_valu"], 3),
             "ms_fft": round(single["ms_fft"], 3),
             "fft_equals_valu": single["fft_equals_valu"],
+            "oracle_digest_equal": single["oracle_digest_equal"],
             "valu_alu_frac": round(single["work"] / (single["ms_valu"] * 1e-3)
                                    / 1e12 / peak, 4)}
         line["speedup_vs_single_block"] = round(line["value"] / sg, 2)

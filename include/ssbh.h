@@ -143,10 +143,14 @@ int ssbh_num_cus(const ssbh_ctx *ctx);
  *                ascending i.  n_sub <= SSBH_MAX_SUB_LDS.
  *                SSBH_SAMPLE_EXPLICIT: the same, with V_i = d_assign[i]
  *                (uint32, every value < n_sub, else *d_status = SSBH_E_INVAL).
- *                SSBH_SAMPLE_PERMUTE: d_assign is a permutation pi of
- *                0..n_bits-1 (uint32); B[k] = A[pi[k]] and sub-block j is
+ *                SSBH_SAMPLE_PERMUTE: B[k] = A[pi[k]] and sub-block j is
  *                B[jL, (j+1)L) with L = n_bits / n_sub (n_sub must divide
- *                n_bits).  Entries >= n_bits give *d_status = SSBH_E_INVAL.
+ *                n_bits).  pi is d_assign (a permutation of 0..n_bits-1,
+ *                uint32; entries >= n_bits give *d_status = SSBH_E_INVAL)
+ *                or, when d_assign is NULL, the keyed permutation of
+ *                sample_key built on the device as ssbh_permutation does
+ *                (scratch of about 16 bytes per input bit, held by the
+ *                context).
  *  l_ub          L_S^UB; 0 disables the abort rule.  If some n_j > l_ub,
  *                *d_status = SSBH_E_ABORT_OVERSIZE.
  *  d_sub         output sub-blocks, sub_capacity_words words.  Needs
@@ -164,6 +168,22 @@ ssbh_status ssbh_sample(ssbh_ctx *ctx, const uint64_t *d_in, uint64_t n_bits,
                         uint64_t *d_sub, uint64_t sub_capacity_words,
                         uint64_t *d_len, uint64_t *d_word_off,
                         int32_t *d_status, void *stream);
+
+/* The keyed permutation of the permutation-split sampling mode (not in the
+ * paper, which draws V_i i.i.d.; used by workloads that cut a permuted block
+ * into equal sub-blocks): Durstenfeld's Fisher-Yates shuffle (CACM 7(7),
+ * 1964, Algorithm 235) of the identity 0..n-1, which for k = n-1 down to 1
+ * exchanges entries k and j_k, with j_k = floor(r_t * (k+1) / 2^64) and r_t
+ * output t = n-1-k of the SplitMix64 stream of `key` (the stream defined
+ * under ssbh_sample; multiply-shift without rejection, bias below
+ * (k+1)/2^64).  The result is computed by parallel passes, not by the
+ * sequential loop, and equals the loop's for every key.
+ *  d_perm   output, n uint32 (device, caller-owned).
+ *  n        at most SSBH_MAX_SAMPLE_BITS (else SSBH_E_UNSUPPORTED); 0 writes
+ *           nothing.
+ * Scratch: 12 bytes per entry, held by the context until ssbh_destroy. */
+ssbh_status ssbh_permutation(ssbh_ctx *ctx, uint64_t key, uint64_t n,
+                             uint32_t *d_perm, void *stream);
 
 /* Sampling followed by sifting inside every sub-block (Sec. III.B steps 1-2)
  * and the abort rule.  d_keep holds one flag per round (n_bits bits, same

@@ -148,6 +148,8 @@ void Workspace::release() {
     fft_spec.release();
     fft_work.release();
     fft_qbuf.release();
+    perm_tmp.release();
+    perm_pi.release();
     delete timer;
     timer = nullptr;
 }
@@ -266,6 +268,57 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     return launch_hash_valu(ctx, ws, q, choose_valu(ctx, q), stream);
 }
 
+// Host-visible argument checks of ssbh_hash_batch (and of its variant
+// without allocation).
+ssbh_status check_hash_request(const HashRequest &q) {
+    if (!q.len || !q.woff || !q.status || !q.out_total)
+        SSBH_INVAL("d_len, d_word_off, d_out_total_bits and d_status must be "
+                   "non-null");
+    if (q.n_sub && !q.sub) SSBH_INVAL("d_sub is null");
+    if (q.out_cap_bits && !q.out) SSBH_INVAL("d_out is null");
+    if (q.out_rule == SSBH_OUT_RATIO) {
+        if (q.out_b == 0) SSBH_INVAL("out_b must be > 0");
+        if (q.out_a >= (1ull << 24) || q.out_b >= (1ull << 24))
+            SSBH_INVAL("ratio terms must be below 2^24");
+    } else if (q.out_rule == SSBH_OUT_EXPLICIT) {
+        if (q.n_sub && !q.out_len) SSBH_INVAL("explicit lengths need d_out_len");
+    } else if (q.out_rule != SSBH_OUT_FIXED) {
+        SSBH_INVAL("unknown out_rule %u", q.out_rule);
+    }
+    if (q.m_cap == 0 && q.out_rule == SSBH_OUT_FIXED && q.out_a > 0)
+        SSBH_INVAL("m_cap must be >= out_a");
+    if (q.m_cap >= (1ull << 32)) {
+        set_error("m_cap must be below 2^32");
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (q.sub_cap >= (1ull << 36)) {
+        set_error("sub_capacity_words must be below 2^36");
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (q.n_sub > 1 && q.stride) {
+        const long double last = (long double)(q.n_sub - 1) * q.stride;
+        if (last > (long double)q.seed_bits)
+            SSBH_INVAL("seed too short for %u sub-blocks at stride %llu",
+                       q.n_sub, (unsigned long long)q.stride);
+    }
+    if (q.seed_bits && !q.seed) SSBH_INVAL("d_seed is null");
+    if ((q.kernel == SSBH_K_MFMA_I8 || q.kernel == SSBH_K_MFMA_F4) && q.stride != 0)
+        SSBH_INVAL("the MFMA kernels need a shared seed (seed_stride = 0)");
+    if (q.kernel == SSBH_K_MFMA_F4 && q.seed_bits + 1 > (1ull << 24) + q.m_cap) {
+        set_error("the fp4 matrix kernel needs seed_bits + 1 - m_cap <= 2^24 "
+                  "(exact fp32 sums)");
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (q.kernel == SSBH_K_FFT &&
+        fft_length(q.stride ? q.stride : q.seed_bits) > kMaxFftLength) {
+        set_error("the FFT hash supports seeds (or seed strides) of at most "
+                  "%llu bits", (unsigned long long)kMaxFftLength);
+        return SSBH_E_UNSUPPORTED;
+    }
+    if (q.kernel > SSBH_K_MFMA_F4) SSBH_INVAL("unknown kernel %u", q.kernel);
+    return SSBH_OK;
+}
+
 }  // namespace ssbh
 
 using namespace ssbh;
@@ -365,58 +418,25 @@ ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
                             void *stream) {
     clear_error();
     if (!ctx) SSBH_INVAL("ctx is null");
-    if (!d_len || !d_word_off || !d_status || !d_out_total_bits)
-        SSBH_INVAL("d_len, d_word_off, d_out_total_bits and d_status must be "
-                   "non-null");
-    if (n_sub && !d_sub) SSBH_INVAL("d_sub is null");
-    if (out_capacity_bits && !d_out) SSBH_INVAL("d_out is null");
-    if (out_rule == SSBH_OUT_RATIO) {
-        if (out_b == 0) SSBH_INVAL("out_b must be > 0");
-        if (out_a >= (1ull << 24) || out_b >= (1ull << 24))
-            SSBH_INVAL("ratio terms must be below 2^24");
-    } else if (out_rule == SSBH_OUT_EXPLICIT) {
-        if (n_sub && !d_out_len) SSBH_INVAL("explicit lengths need d_out_len");
-    } else if (out_rule != SSBH_OUT_FIXED) {
-        SSBH_INVAL("unknown out_rule %u", out_rule);
-    }
-    if (m_cap == 0 && out_rule == SSBH_OUT_FIXED && out_a > 0)
-        SSBH_INVAL("m_cap must be >= out_a");
-    if (m_cap >= (1ull << 32)) {
-        set_error("m_cap must be below 2^32");
-        return SSBH_E_UNSUPPORTED;
-    }
-    if (sub_capacity_words >= (1ull << 36)) {
-        set_error("sub_capacity_words must be below 2^36");
-        return SSBH_E_UNSUPPORTED;
-    }
-    if (n_sub > 1 && seed_stride) {
-        const long double last = (long double)(n_sub - 1) * seed_stride;
-        if (last > (long double)seed_bits)
-            SSBH_INVAL("seed too short for %u sub-blocks at stride %llu",
-                       n_sub, (unsigned long long)seed_stride);
-    }
-    if (seed_bits && !d_seed) SSBH_INVAL("d_seed is null");
-    if ((kernel == SSBH_K_MFMA_I8 || kernel == SSBH_K_MFMA_F4) && seed_stride != 0)
-        SSBH_INVAL("the MFMA kernels need a shared seed (seed_stride = 0)");
-    if (kernel == SSBH_K_MFMA_F4 && seed_bits + 1 > (1ull << 24) + m_cap) {
-        set_error("the fp4 matrix kernel needs seed_bits + 1 - m_cap <= 2^24 "
-                  "(exact fp32 sums)");
-        return SSBH_E_UNSUPPORTED;
-    }
-    if (kernel == SSBH_K_FFT &&
-        fft_length(seed_stride ? seed_stride : seed_bits) > kMaxFftLength) {
-        set_error("the FFT hash supports seeds (or seed strides) of at most "
-                  "%llu bits", (unsigned long long)kMaxFftLength);
-        return SSBH_E_UNSUPPORTED;
-    }
-    if (kernel > SSBH_K_MFMA_F4) SSBH_INVAL("unknown kernel %u", kernel);
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
     HashRequest q{d_sub, sub_capacity_words, d_len, d_word_off, n_sub,
                   out_rule, out_a, out_b, d_out_len, d_seed, seed_bits,
                   seed_stride, m_cap, kernel, d_out, out_capacity_bits,
                   d_out_total_bits, d_status};
+    ssbh_status st = check_hash_request(q);
+    if (st != SSBH_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
     return launch_hash(ctx, ctx->ws, q, (hipStream_t)stream);
+}
+
+ssbh_status ssbh_permutation(ssbh_ctx *ctx, uint64_t key, uint64_t n,
+                             uint32_t *d_perm, void *stream) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    SSBH_CHECK_HIP(hipSetDevice(ctx->device));
+    return launch_permutation(ctx, ctx->ws.perm_tmp, key, n, d_perm,
+                              (hipStream_t)stream);
 }
 
 ssbh_status ssbh_seed_from_key(ssbh_ctx *ctx, uint64_t seed_key,

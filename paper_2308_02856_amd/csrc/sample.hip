@@ -826,7 +826,6 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
 
     if (mode == SSBH_SAMPLE_PERMUTE) {
         if (d_keep) SSBH_INVAL("sifting flags need i.i.d. or explicit V");
-        if (!d_assign) SSBH_INVAL("permutation mode needs d_assign");
         if (n % ns) SSBH_INVAL("n_sub (%u) must divide n_bits (%llu)", ns,
                                (unsigned long long)n);
         const uint64_t L = n / ns, wl = (L + 63) / 64;
@@ -834,6 +833,15 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
             SSBH_INVAL("sub_capacity_words %llu < %llu",
                        (unsigned long long)sub_cap,
                        (unsigned long long)((uint64_t)ns * wl));
+        if (!d_assign && n) {
+            // The keyed permutation of sample_key, built in the workspace.
+            ssbh_status st = ws.perm_pi.reserve((size_t)n * sizeof(uint32_t));
+            if (st != SSBH_OK) return st;
+            st = launch_permutation(ctx, ws.perm_tmp, key, n,
+                                    ws.perm_pi.as<uint32_t>(), stream);
+            if (st != SSBH_OK) return st;
+            d_assign = ws.perm_pi.as<uint32_t>();
+        }
         hipLaunchKernelGGL(k_perm_meta, dim3((ns + 255) / 256), dim3(256), 0,
                            stream, ns, L, wl, l_ub, d_len, d_woff, d_status);
         const uint64_t total = (uint64_t)ns * wl;

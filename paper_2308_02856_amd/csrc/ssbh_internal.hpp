@@ -84,6 +84,8 @@ struct Workspace {
     DevBuf fft_spec;   // FFT hash: seed spectrum (L complex doubles)
     DevBuf fft_work;   // FFT hash: transforms of a chunk of sub-block pairs
     DevBuf fft_qbuf;   // FFT hash: parity words in transform order
+    DevBuf perm_tmp;   // keyed permutation: counts, groups, chain links
+    DevBuf perm_pi;    // keyed permutation built for permutation sampling
     char last_schedule[48] = "";   // kernel and schedule of the last hash
     KernelTimer *timer = nullptr;  // per-kernel event timing (optional)
     void release();
@@ -170,6 +172,7 @@ struct HashRequest {
 
 ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                         hipStream_t stream);
+ssbh_status check_hash_request(const HashRequest &q);
 
 ssbh_status launch_hash_valu(ssbh_ctx *ctx, Workspace &ws,
                              const HashRequest &q, const ValuSchedule &s,
@@ -187,6 +190,13 @@ int fft_per_transform(const ssbh_ctx *ctx, const HashRequest &q, uint64_t L);
 
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,
                         hipStream_t stream);
+
+// Keyed Durstenfeld permutation of 0..n-1 into d_perm (permute.hip);
+// `scratch` grows to permutation_scratch(n) bytes.
+ssbh_status launch_permutation(ssbh_ctx *ctx, DevBuf &scratch, uint64_t key,
+                               uint64_t n, uint32_t *d_perm,
+                               hipStream_t stream);
+size_t permutation_scratch(uint64_t n);
 
 // Scratch each launch layer will reserve for the given request (bytes per
 // Workspace buffer), so callers can lend pre-sized memory.

@@ -124,6 +124,8 @@ def lib() -> ctypes.CDLL:
                                   _u64, _vp, _vp, _vp]
     L.ssbh_seed_from_key.restype = _i32
     L.ssbh_seed_from_key.argtypes = [_vp, _u64, _vp, _u64, _vp]
+    L.ssbh_permutation.restype = _i32
+    L.ssbh_permutation.argtypes = [_vp, _u64, _u64, _vp, _vp]
     L.ssbh_set_schedule.restype = _i32
     L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32, _u32]
     L.ssbh_pipeline_create.restype = _i32
@@ -314,6 +316,16 @@ class Context:
         _check(lib().ssbh_seed_from_key(self._h, int(key) & (2**64 - 1),
                                         _ptr(out), int(seed_bits),
                                         _stream(stream)))
+        return out
+
+    def permutation(self, key: int, n: int, out=None, stream=None):
+        """ssbh_permutation: the keyed permutation of 0..n-1 (int32 tensor
+        holding uint32 values)."""
+        if out is None:
+            out = torch.empty(max(1, int(n)), dtype=torch.int32,
+                              device=self._dev())
+        _check(lib().ssbh_permutation(self._h, int(key) & (2**64 - 1), int(n),
+                                      _ptr(out), _stream(stream)))
         return out
 
     def tune(self, sub, sub_capacity: int, length, word_off, n_sub: int,

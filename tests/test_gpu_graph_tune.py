@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from tests.gpu_util import first_diff, to_dev, to_dev_u32, to_host
-from workloads import bernoulli_bits, config, permutation, uniform_bits
+from workloads import bernoulli_bits, config, uniform_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ def test_graph_replays_match_eager(ctx, orc):
     n, ns, L, m = c["n_bits"], c["n_sub"], c["sub_bits"], c["out_a"]
     stride = L + m - 1
     seed_bits = ns * stride
-    perm = permutation(n, c["perm_seed"])
+    perm = orc.permutation(n, c["perm_key"])
     seed = to_dev(uniform_bits(seed_bits, c["seed_seed"]))
     d_in = to_dev(uniform_bits(n, c["input_seed"]))
     d_perm = to_dev_u32(perm)

@@ -275,12 +275,13 @@ def test_small_workload_in_full(ctx, S, orc):
     c = config("small")
     n, ns, L, m = c["n_bits"], c["n_sub"], c["sub_bits"], c["out_a"]
     a = uniform_bits(n, c["input_seed"])
-    perm = permutation(n, c["perm_seed"])
+    perm = orc.permutation(n, c["perm_key"])
     stride = L + m - 1
     seed_bits = ns * stride
     seed = uniform_bits(seed_bits, c["seed_seed"])
+    # The permutation comes from the library's keyed shuffle (no d_assign).
     sub, ln, wo, st = ctx.sample(to_dev(a), n, ns, S.SAMPLE_PERMUTE,
-                                 assign=to_dev_u32(perm))
+                                 key=c["perm_key"])
     out, tot, st = ctx.hash_batch(sub, sub.numel(), ln, wo, ns, to_dev(seed),
                                   seed_bits, m, out_rule=S.OUT_FIXED, out_a=m,
                                   seed_stride=stride, status=st,

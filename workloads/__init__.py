@@ -14,11 +14,10 @@ from .gen import (  # noqa: F401
     bernoulli_bits,
     uniform_bits,
     permutation,
-    permutation_device,
     assignment,
     unpack_bits,
     pack_bits,
 )
 from .configs import (  # noqa: F401
-    CONFIGS, TABLE1, TABLE1_N_SUB, config, serving_jobs, serving_pools,
-    table1_instance)
+    CONFIGS, SERVING_P_BITS, TABLE1, TABLE1_N_SUB, config, serving_input,
+    serving_input_device, serving_jobs, serving_planes, table1_instance)

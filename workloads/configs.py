@@ -3,7 +3,8 @@
 Each workload is described by plain numbers; the keys are fixed so that every
 run (tests, benchmark, smoke check) sees the same synthetic data.
 
-* ``small``       N = 2^18 uniform bits, Fisher-Yates permutation then a
+* ``small``       N = 2^18 uniform bits, keyed Fisher-Yates permutation
+                  (Durstenfeld, SplitMix64 stream of perm_key) then a
                   contiguous split into 8 sub-blocks of 2^15 bits, each hashed
                   to 2^14 bits with its own seed of 2^15 + 2^14 - 1 bits.
 * ``single``      one block, n = 2^24 uniform bits hashed to m = 2^23 bits
@@ -11,10 +12,11 @@ run (tests, benchmark, smoke check) sees the same synthetic data.
 * ``batched``     N = 2^28 Bernoulli(0.3) bits, i.i.d. uniform assignment to
                   2048 sub-blocks, output floor(0.4 * n_j) bits each, one
                   shared seed of max n_j + max m_j - 1 bits.
-* ``contraction`` N = 2^30 uniform bits, permutation then split into 8192
+* ``contraction`` N = 2^30 uniform bits, keyed permutation then split into 8192
                   sub-blocks of 2^17 bits, shared seed, 2^16 output bits each.
 * ``serving``     a Poisson stream (mean 200 jobs/s) of jobs with block sizes
-                  log-uniform in 2^20..2^28, Bernoulli(p), p ~ U[0.2, 0.5],
+                  log-uniform in 2^20..2^28, Bernoulli(p), p ~ U[0.2, 0.5]
+                  realised per job as round(p 2^10)/2^10 (serving_input),
                   sub-block size log-uniform in 2^16..2^18, output ratio
                   q/1000 with q uniform in 200..600, fresh keys per job.
 * ``TABLE1``      the five input/output sizes of the paper's FPGA experiment
@@ -28,7 +30,7 @@ import math
 
 import numpy as np
 
-from .gen import bernoulli_bits
+from .gen import uniform_bits
 
 _KEY_BASE = 0x2308028560000000
 
@@ -37,7 +39,7 @@ CONFIGS = {
         name="small", n_bits=1 << 18, p=0.5, n_sub=8, sampling="permute",
         out_rule="fixed", out_a=1 << 14, out_b=1,
         seed_mode="independent", sub_bits=1 << 15,
-        input_seed=1, perm_seed=101, seed_seed=201,
+        input_seed=1, perm_key=_KEY_BASE + 0x101, seed_seed=201,
     ),
     "single": dict(
         name="single", n_bits=1 << 24, p=0.5, n_sub=1, sampling="none",
@@ -53,7 +55,7 @@ CONFIGS = {
         name="contraction", n_bits=1 << 30, p=0.5, n_sub=8192,
         sampling="permute", out_rule="fixed", out_a=1 << 16, out_b=1,
         seed_mode="shared", sub_bits=1 << 17,
-        input_seed=4, perm_seed=104, seed_seed=204,
+        input_seed=4, perm_key=_KEY_BASE + 0x104, seed_seed=204,
     ),
     "serving": dict(
         name="serving", rate_hz=200.0, log2_n=(20, 28), p=(0.2, 0.5),
@@ -133,27 +135,63 @@ def serving_jobs(count: int, seed: int = 5, rate_hz: float = 200.0,
     return jobs
 
 
-def serving_pools(levels: int = 8, pool_bits: int = 1 << 28, seed: int = 55,
-                  p=(0.2, 0.5)) -> tuple[list[float], list[np.ndarray]]:
-    """Input pools for the serving stream: one Bernoulli block per p level.
-
-    A job with parameter p reads a slice of the pool whose level is nearest
-    to p (levels are the midpoints of ``levels`` equal bins of [p0, p1]).
-    """
-    ps = [p[0] + (p[1] - p[0]) * (k + 0.5) / levels for k in range(levels)]
-    pools = [bernoulli_bits(pool_bits, pk, seed + k) for k, pk in enumerate(ps)]
-    return ps, pools
+SERVING_P_BITS = 10      # a job's p is realised as round(p * 2^10) / 2^10
+SERVING_POOL_BITS = 1 << 28
 
 
-def pool_slice(job: dict, ps: list[float], pools: list[np.ndarray]) -> np.ndarray:
-    """The packed input of one serving job (a word-aligned slice of a pool)."""
-    k = int(np.argmin([abs(job["p"] - pk) for pk in ps]))
-    pool = pools[k]
+def serving_planes(seed: int = 55, pool_bits: int = SERVING_POOL_BITS,
+                   planes: int = SERVING_P_BITS) -> list[np.ndarray]:
+    """Independent uniform bit pools (numpy PCG64), one per binary digit of
+    the serving jobs' Bernoulli threshold."""
+    return [uniform_bits(pool_bits, seed + k) for k in range(planes)]
+
+
+def _serving_layout(job: dict, pool_words: int) -> tuple[int, int, int]:
+    """(word offset, words, threshold) of one job's input."""
     nw = (job["n_bits"] + 63) // 64
-    total = pool.size
-    off = (job["index"] * 7919 * 64) % max(1, total - nw + 1)
-    words = pool[off: off + nw].copy()
+    off = (job["index"] * 7919) % max(1, pool_words - nw + 1)
+    thr = int(round(job["p"] * (1 << SERVING_P_BITS)))
+    return off, nw, thr
+
+
+def _below_threshold(planes, thr: int, ones, inv):
+    """Bits of [U < thr] word-parallel, U's binary digits taken from the
+    planes, most significant first (a comparator over bit slices).  `ones`
+    is an all-one word array, `inv` bitwise complement."""
+    lt = ones & 0
+    eq = ones
+    for b, x in enumerate(planes):
+        if (thr >> (SERVING_P_BITS - 1 - b)) & 1:
+            lt = lt | (eq & inv(x))
+            eq = eq & x
+        else:
+            eq = eq & inv(x)
+    return lt
+
+
+def serving_input(job: dict, planes: list[np.ndarray]) -> np.ndarray:
+    """The packed input of one serving job: n_bits i.i.d. Bernoulli(thr/2^10)
+    bits, thr = round(p 2^10), bit i = [U_i < thr] where the 10 binary digits
+    of U_i are bit i of a job-specific word slice of each plane pool."""
+    off, nw, thr = _serving_layout(job, planes[0].size)
+    sl = [pl[off: off + nw] for pl in planes]
+    ones = np.full(nw, np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+    words = _below_threshold(sl, thr, ones, np.invert).astype(np.uint64)
     r = job["n_bits"] % 64
     if r:
         words[-1] &= np.uint64((1 << r) - 1)
+    return words
+
+
+def serving_input_device(job: dict, d_planes: list):
+    """serving_input computed with torch on the planes' device copies
+    (int64 tensors holding the same words); bit-identical to the host."""
+    import torch
+    off, nw, thr = _serving_layout(job, d_planes[0].numel())
+    sl = [pl[off: off + nw] for pl in d_planes]
+    ones = torch.full((nw,), -1, dtype=torch.int64, device=d_planes[0].device)
+    words = _below_threshold(sl, thr, ones, torch.bitwise_not)
+    r = job["n_bits"] % 64
+    if r:
+        words[-1] &= (1 << r) - 1
     return words

@@ -91,14 +91,3 @@ def assignment(n: int, n_sub: int, seed: int) -> np.ndarray:
     """Explicit sampling variables: ``n`` values uniform in ``[0, n_sub)``."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(0, int(n_sub), size=int(n), dtype=np.uint32)
-
-
-def permutation_device(n: int, seed: int, device: str = "cuda"):
-    """A uniformly random permutation of ``0..n-1`` generated on the GPU by
-    torch's seeded generator, as int32 (values < 2^31) -- for sizes where a
-    host shuffle would take minutes.  Returned as a torch tensor."""
-    import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(int(seed))
-    return torch.randperm(int(n), generator=g, device=device,
-                          dtype=torch.int32)
