@@ -291,6 +291,38 @@ ssbh_status ssbh_hash_batch(ssbh_ctx *ctx, const uint64_t *d_sub,
                             uint64_t *d_out_total_bits, int32_t *d_status,
                             void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * ssbh_hash_batch with the same arguments, outputs and error behaviour, but
+ * without any device or host allocation.  The hashing plan, tile list and
+ * counters live in one fixed library-owned device array of
+ * SSBH_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.
+ *  kernel   SSBH_K_VALU, SSBH_K_MFMA_I8 or SSBH_K_MFMA_F4; SSBH_K_AUTO takes
+ *           the matrix cores for a shared seed and n_sub >= 64, else VALU
+ *           (no tuning table); SSBH_K_FFT gives SSBH_E_UNSUPPORTED (it needs
+ *           transform buffers).
+ * A request whose plan and tile list exceed the array (roughly
+ * 24 n_sub + 16 * tiles bytes; the VALU tiles are about
+ * n_sub * (m_cap / rows + 1)) returns SSBH_E_UNSUPPORTED before anything is
+ * enqueued.  Every call on one GPU shares the array, which keeps the last
+ * call's contents (the path rewrites all it reads): calls that overlap on one
+ * GPU -- other streams, other threads, other contexts -- race and must be
+ * serialised by the caller.  Schedules forced on ctx apply; ctx's own
+ * workspace is not used. */
+#define SSBH_NOALLOC_SCRATCH_BYTES (8u << 20)
+ssbh_status ssbh_hash_batch_noalloc(ssbh_ctx *ctx, const uint64_t *d_sub,
+                                    uint64_t sub_capacity_words,
+                                    const uint64_t *d_len,
+                                    const uint64_t *d_word_off, uint32_t n_sub,
+                                    uint32_t out_rule, uint64_t out_a,
+                                    uint64_t out_b, const uint64_t *d_out_len,
+                                    const uint64_t *d_seed, uint64_t seed_bits,
+                                    uint64_t seed_stride, uint64_t m_cap,
+                                    uint32_t kernel, uint64_t *d_out,
+                                    uint64_t out_capacity_bits,
+                                    uint64_t *d_out_total_bits,
+                                    int32_t *d_status, void *stream);
+
 /* Seed bits from a key, on the device: word t of d_seed is output t of the
  * SplitMix64 stream with key seed_key (the generator described at
  * ssbh_sample); bits past seed_bits are zero.  Used for the fresh per-job

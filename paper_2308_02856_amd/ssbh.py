@@ -125,6 +125,8 @@ def lib() -> ctypes.CDLL:
     L.ssbh_seed_from_key.restype = _i32
     L.ssbh_seed_from_key.argtypes = [_vp, _u64, _vp, _u64, _vp]
     L.ssbh_permutation.restype = _i32
+    L.ssbh_hash_batch_noalloc.restype = _i32
+    L.ssbh_hash_batch_noalloc.argtypes = L.ssbh_hash_batch.argtypes
     L.ssbh_permutation.argtypes = [_vp, _u64, _u64, _vp, _vp]
     L.ssbh_set_schedule.restype = _i32
     L.ssbh_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _u32, _u32]
@@ -302,6 +304,22 @@ class Context:
         elif reset_status:
             status.zero_()
         _check(lib().ssbh_hash_batch(
+            self._h, _ptr(sub), int(sub_capacity), _ptr(length),
+            _ptr(word_off), int(n_sub), int(out_rule), int(out_a), int(out_b),
+            _ptr(out_len), _ptr(seed), int(seed_bits), int(seed_stride),
+            int(m_cap), int(kernel), _ptr(out), int(out_capacity_bits),
+            _ptr(total), _ptr(status), _stream(stream)))
+        return out, total, status
+
+    def hash_batch_noalloc(self, sub, sub_capacity: int, length, word_off,
+                           n_sub: int, seed, seed_bits: int, m_cap: int,
+                           out, out_capacity_bits: int, total, status,
+                           out_rule: int = OUT_FIXED, out_a: int = 0,
+                           out_b: int = 1, out_len=None, seed_stride: int = 0,
+                           kernel: int = K_AUTO, stream=None):
+        """ssbh_hash_batch_noalloc: every buffer is the caller's (the
+        library allocates nothing)."""
+        _check(lib().ssbh_hash_batch_noalloc(
             self._h, _ptr(sub), int(sub_capacity), _ptr(length),
             _ptr(word_off), int(n_sub), int(out_rule), int(out_a), int(out_b),
             _ptr(out_len), _ptr(seed), int(seed_bits), int(seed_stride),
