@@ -89,8 +89,9 @@ enum {
                                  part) when seed_bits + 1 - m_cap < 2^18 and
                                  the transform length is at most 2^20
                                  (ssbh_set_fft_packing).  Seed stride S > 0 (at most
-                                 2^31): one transform per sub-block with the
-                                 spectrum of its own seed; needs every
+                                 2^31): one transform per sub-block carrying
+                                 its own seed window (real) and its bits
+                                 (imaginary), squared pointwise; needs every
                                  n_j + m_cap - 1 <= the transform length of
                                  S (true when S >= n_max + m_cap - 1), else
                                  *d_status = SSBH_E_UNSUPPORTED              */
@@ -380,7 +381,11 @@ void ssbh_pipeline_destroy(ssbh_pipeline *pipe);
  * l_ub = ceil(n/n_sub + 8*sqrt(n/n_sub)) + 64);  m_cap = the output rule
  * applied to n_cap;  seed stride S = n_cap + m_cap - 1;  seed length
  * n_sub * S bits (word t of the seed is output t of the SplitMix64 stream
- * keyed by seed_key, as in ssbh_seed_from_key). */
+ * keyed by seed_key, as in ssbh_seed_from_key).  The hash kernel is fixed at
+ * submission from these sizes: the FFT hash (one transform per sub-block,
+ * chunks of at most 48 MiB of transforms) when it pays by the rule stated
+ * under ssbh_tune, else the bit-sliced VALU kernel with the schedule the
+ * context would choose then; the bits are the same either way. */
 typedef struct {
     const uint64_t *in;      /* input bits A^N                               */
     int in_on_device;        /* 1: `in` is device memory, already written
@@ -429,16 +434,17 @@ ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
 /* ------------------------------------------------------------- tuning --- */
 
 /* Autotuner: run ssbh_hash_batch on the given (real) arguments once per
- * candidate kernel and schedule (bit-sliced VALU schedules; int8 matrix-core
- * schedules and FFT chunk sizes when the seed is shared), `reps` timed runs
- * each with HIP events,
+ * candidate kernel and schedule (bit-sliced VALU schedules, FFT chunks of
+ * 64 .. 256 MiB of transforms, and int8 matrix-core schedules when the seed
+ * is shared), `reps` timed runs each with HIP events,
  * and remember the fastest for the shape bucket of these arguments (seed
  * sharing, log2 of n_sub, m_cap and mean sub-block words).  Later calls with
  * kernel = SSBH_K_AUTO in the same bucket use it; without a tuned entry AUTO
- * picks, for a shared seed, the FFT when (seed_bits + 1 - m_cap) * m_cap >=
- * 1024 L log2 L (L the transform length, the quadratic work well above the
- * transform's), else the matrix cores when n_sub >= 64; the VALU kernel in
- * every other case.  Blocks until the stream is idle; d_out holds a valid result
+ * picks the FFT when n * m_cap >= 1024 L log2 L / k, with n = seed_bits + 1
+ * - m_cap (shared seed) or S + 1 - m_cap (seed stride S), L the transform
+ * length and k the sub-blocks per transform (4 or 2 for a shared seed, 1
+ * with a stride); else the matrix cores for a shared seed and n_sub >= 64;
+ * the VALU kernel in every other case.  Blocks until the stream is idle; d_out holds a valid result
  * afterwards.  If report is non-null, a text table of the timings is written
  * (truncated to report_len bytes). */
 ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,

@@ -188,20 +188,23 @@ std::string tune_bucket(const HashRequest &q) {
     return b;
 }
 
-// Untuned choice between the FFT and the quadratic kernels for a shared
-// seed.  Per sub-block the quadratic kernels do about n * m bit-products at
-// roughly 2.5e15 per second; the FFT does a share (1/2, or 1/4 when four
-// sub-blocks ride in a transform) of a forward and inverse transform, about
-// L log2 L points at roughly 1e-12 s per point-level each (both measured on
-// MI355X).  The FFT is taken when n * m >= 2048 L log2 L / (sub-blocks per
-// transform), n estimated from the seed length (n_max + m_cap - 1 bits).
+// Untuned choice between the FFT and the quadratic kernels.  Per sub-block
+// the quadratic kernels take about 7e-16 s per bit-product (n * m of them);
+// the FFT takes a share (1/2, or 1/4 when four sub-blocks ride in a
+// transform; all of it with independent seeds, where a transform carries one
+// sub-block and its seed) of a forward and inverse transform, about
+// 7e-13 s per point-level (L log2 L of them), both measured on MI355X at the
+// batched length: break-even near n * m = 1000 L log2 L per transform.  The
+// FFT is taken when n * m >= 1024 L log2 L / (sub-blocks per transform), n
+// estimated from the seed length (n_max + m_cap - 1 bits, or the stride).
 bool fft_pays(const HashRequest &q) {
-    const uint64_t L = fft_length(q.seed_bits);
-    if (L > kMaxFftLength || q.seed_bits + 1 <= q.m_cap) return false;
-    const double n = (double)(q.seed_bits + 1 - q.m_cap);
+    const uint64_t span = q.stride ? q.stride : q.seed_bits;
+    const uint64_t L = fft_length(span);
+    if (L > kMaxFftLength || span + 1 <= q.m_cap) return false;
+    const double n = (double)(span + 1 - q.m_cap);
     const double m = (double)q.m_cap;
-    const double per = fft_can_pack(q, L) ? 4.0 : 2.0;
-    return n * m >= 2048.0 / per * (double)L * std::log2((double)L);
+    const double per = q.stride ? 1.0 : fft_can_pack(q, L) ? 4.0 : 2.0;
+    return n * m >= 1024.0 / per * (double)L * std::log2((double)L);
 }
 
 ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
@@ -225,7 +228,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                 r.kernel = SSBH_K_MFMA_I8;
                 return launch_hash_mfma(ctx, ws, r, ms, stream);
             }
-            if (sscanf(choice.c_str(), "fft:%u", &d) == 1 && q.stride == 0) {
+            if (sscanf(choice.c_str(), "fft:%u", &d) == 1) {
                 FftSchedule fs;
                 fs.chunk_pairs = d;
                 r.kernel = SSBH_K_FFT;
@@ -238,7 +241,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                 return launch_hash_valu(ctx, ws, r, vs, stream);
             }
         }
-        if (q.stride == 0 && !ctx->forced_valu_r && fft_pays(q)) {
+        if (!ctx->forced_valu_r && fft_pays(q)) {
             r.kernel = SSBH_K_FFT;
             return launch_hash(ctx, ws, r, stream);
         }
@@ -459,6 +462,7 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
         SSBH_INVAL("waves must be 2, 4 or 8");
     if (chunk_cols && (chunk_cols % 32 || chunk_cols > 16384))
         SSBH_INVAL("chunk_cols must be a multiple of 32 and at most 16384");
+    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->forced_valu_r = r;
     ctx->forced_valu_waves = waves;
     ctx->forced_tile_cols = tile_cols;
@@ -535,6 +539,7 @@ ssbh_status ssbh_set_column_path(ssbh_ctx *ctx, int scalar_x) {
     clear_error();
     if (!ctx) SSBH_INVAL("ctx is null");
     if (scalar_x < -1 || scalar_x > 1) SSBH_INVAL("scalar_x must be -1, 0 or 1");
+    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->forced_scalar_x = scalar_x;
     return SSBH_OK;
 }

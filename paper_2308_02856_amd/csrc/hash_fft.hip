@@ -31,6 +31,13 @@
 //                stage and the first inverse one share registers).
 //   k_fft_out    inverse 64-point FFTs down the columns, 1/L, round, parity;
 //                64 consecutive output rows per wavefront ballot.
+// Independent seeds (seed stride S > 0): transform j carries z_j = s_j +
+// i xr_j, sub-block j's own seed window s_j[q] = s[jS + q] in the real part
+// and its reversed bits in the imaginary part.  For real u and v,
+//     (u + i v) (*) (u + i v) = u (*) u - v (*) v + 2 i (u (*) v),
+// so squaring the spectrum pointwise (no second spectrum, no pairing of the
+// frequencies k and L - k) and inverting gives 2 (s_j * xr_j) as the
+// imaginary part: one transform per sub-block, no separate seed spectra.
 // The seed spectrum comes from the same forward passes.  LDS FFTs are
 // Stockham autosort stages with radix-8 (columns) or radix-16 (rows)
 // butterflies in registers, then one smaller stage for the rest of the
@@ -86,6 +93,7 @@ struct FftArgs {
                                // 2 (real, imaginary part) or 4 (two per
                                // part, x_lo + 2^18 x_hi)
     uint64_t seed_off;         // first seed bit of the spectrum's seed
+    uint64_t stride;           // seed stride S (independent seeds)
     uint64_t *qbuf;            // parity words by transform index q (k_fft_out
                                // writes, k_fft_emit reorders into `out`)
     uint64_t *out;
@@ -484,12 +492,14 @@ __device__ __forceinline__ uint64_t sub_of(const FftArgs &a, uint32_t pl, int sl
 }
 
 // Forward column pass.  SEED: the input is the seed from bit seed_off on
-// (u[q] = s[seed_off + q], real); else transform p's reversed sub-blocks
-// (PACK: xr_0 + 2^18 xr_1 real, xr_2 + 2^18 xr_3 imaginary; else xr_0 real,
-// xr_1 imaginary).  The first stage reads bits, the last stage stores times
-// w_L^(n2 k1).  A sub-block whose n_j + m_cap - 1 exceeds L (possible only
-// with a seed stride below n_max + m_cap - 1) sets SSBH_E_UNSUPPORTED.
-template <bool SEED, bool PACK>
+// (u[q] = s[seed_off + q], real); JOINT: transform p is sub-block j = pair0 +
+// p with its own seed window s[jS + q] real and xr_j imaginary; else
+// transform p's reversed sub-blocks (PACK: xr_0 + 2^18 xr_1 real, xr_2 +
+// 2^18 xr_3 imaginary; else xr_0 real, xr_1 imaginary).  The first stage
+// reads bits, the last stage stores times w_L^(n2 k1).  A sub-block whose
+// n_j + m_cap - 1 exceeds L (possible only with a seed stride below n_max +
+// m_cap - 1) sets SSBH_E_UNSUPPORTED.
+template <bool SEED, bool PACK, bool JOINT = false>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     constexpr int SLOTS = PACK ? 4 : 2;
     __shared__ double buf[kN1 * kN1];
@@ -507,8 +517,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
             if (part == 0)
                 v = window64(a.seed, (int64_t)a.seed_bits,
                              (int64_t)(a.seed_off + (uint64_t)n2 * n1 + c0));
+        } else if (JOINT && part == 0) {
+            const uint64_t j = sub_of(a, pl, 0);
+            if (j < a.ns)
+                v = window64(a.seed, (int64_t)a.seed_bits,
+                             (int64_t)(j * a.stride + (uint64_t)n2 * n1 + c0));
         } else {
-            const uint64_t j = sub_of(a, pl, part);
+            const uint64_t j = sub_of(a, pl, JOINT ? 0 : part);
             if (j < a.ns) {
                 const int64_t n = (int64_t)a.len[j];
                 if (n1 == 0 && blockIdx.x == 0 &&
@@ -728,7 +743,9 @@ __device__ __forceinline__ void row_inv_all(double2 *buf, const double2 *tw, int
 // w_(64 N2)^(-e (row mod 64)) -- the inverse of the twiddle of the column
 // pass that made the row (k_fft_cols with two levels, the last k_fft_mid
 // with three or four).  Workgroup x holds rows x RPW .. x RPW + RPW - 1.
-template <int N2, bool SPEC>
+// SQ (independent seeds): the spectrum is squared instead (see the top of
+// the file); the seed spectrum is not read.
+template <int N2, bool SPEC, bool SQ = false>
 __global__ __launch_bounds__(rp_threads(N2)) void k_fft_rows(FftArgs a) {
     constexpr int TPR = rp_tpr(N2), RPW = rp_rpw(N2);
     __shared__ double2 lds[N2 * RPW];
@@ -764,8 +781,13 @@ __global__ __launch_bounds__(rp_threads(N2)) void k_fft_rows(FftArgs a) {
                 for (int r = 0; r < TL::R; ++r) sp[TL::out(g, r)] = v[i][r];
                 continue;
             }
+            if constexpr (SQ) {
 #pragma unroll
-            for (int r = 0; r < TL::R; ++r) v[i][r] = cmul(v[i][r], sp[TL::out(g, r)]);
+                for (int r = 0; r < TL::R; ++r) v[i][r] = csq(v[i][r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < TL::R; ++r) v[i][r] = cmul(v[i][r], sp[TL::out(g, r)]);
+            }
             dftR<TL::R, true>(v[i]);
             // The same group's places: no other thread reads them, no barrier.
 #pragma unroll
@@ -860,11 +882,12 @@ __device__ __forceinline__ QRange q_range(const FftArgs &a, uint64_t j, int64_t 
 // word per sub-block (ballot), stored with a plain store (each word has one
 // writer); k_fft_emit then places them.  PACK: a part's integer is
 // lo + 2^18 hi, the low sub-block's parity is its bit 0, the high one's its
-// bit 18.
-template <bool PACK>
+// bit 18.  JOINT: the imaginary part is 2 (s_j * xr_j), an even integer (an
+// odd one is flagged too), and the real part carries no sub-block.
+template <bool PACK, bool JOINT = false>
 __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
-    constexpr int SLOTS = PACK ? 4 : 2;
-    constexpr int PER_PART = SLOTS / 2;
+    constexpr int SLOTS = PACK ? 4 : JOINT ? 1 : 2;
+    constexpr int PER_PART = PACK ? 2 : 1;
     __shared__ double2 buf[kN1 * kN1];
     if (*a.status) return;
     const uint32_t n2 = a.n2;
@@ -896,15 +919,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
         const int64_t qb = (int64_t)n2 * n1 + c0;
         const int64_t q = qb + lane;
 #pragma unroll
-        for (int part = 0; part < 2; ++part) {
+        for (int part = JOINT ? 1 : 0; part < 2; ++part) {
             const double v = (part ? x.y : x.x) * scale;
-            const double rv = rint(v);
-            const bool off = fabs(v - rv) > 0.25 || rv < -0.25;
+            double rv = rint(v);
+            bool off = fabs(v - rv) > 0.25 || rv < -0.25;
+            if constexpr (JOINT) {              // rv = 2 c: c's parity is bit 1
+                off = off || parity(rv);
+                rv *= 0.5;
+            }
             // PACK: rv = lo + 2^18 hi, lo < 2^18; parity(lo) = parity(rv).
             const double hi = PACK ? floor(rv * (1.0 / kPackScale)) : 0.0;
 #pragma unroll
             for (int h = 0; h < PER_PART; ++h) {
-                const QRange &r = qr[PER_PART * part + h];
+                const QRange &r = qr[JOINT ? 0 : PER_PART * part + h];
                 if (qb > r.q0 || qb + 63 < r.qlo) continue;  // uniform
                 // Only the needed entries [qlo, q0] count as off.
                 if (off && q >= r.qlo && q <= r.q0) bad = true;
@@ -1042,7 +1069,7 @@ void launch_timed(Workspace *ws, const char *name, K kernel, dim3 grid, dim3 blo
 }
 
 template <int N2>
-void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
+void launch_rows(const FftArgs &a, uint32_t pairs, bool spec, bool sq,
                  hipStream_t stream, Workspace *ws) {
     // Rows per transform (64, 4096 or 2^18) are a multiple of the rows per
     // workgroup (a power of two up to 32).
@@ -1052,28 +1079,31 @@ void launch_rows(const FftArgs &a, uint32_t pairs, bool spec,
     if (spec)
         hipLaunchKernelGGL((k_fft_rows<N2, true>), grid, dim3(rp_threads(N2)),
                            0, stream, a);
+    else if (sq)
+        launch_timed(ws, "k_fft_rows", k_fft_rows<N2, false, true>, grid,
+                     dim3(rp_threads(N2)), stream, a);
     else
         launch_timed(ws, "k_fft_rows", k_fft_rows<N2, false>, grid,
                      dim3(rp_threads(N2)), stream, a);
 }
 
 void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream,
-          Workspace *ws = nullptr) {
+          Workspace *ws = nullptr, bool sq = false) {
     switch (a.nr) {
-    case 64: launch_rows<64>(a, pairs, spec, stream, ws); break;
-    case 128: launch_rows<128>(a, pairs, spec, stream, ws); break;
-    case 192: launch_rows<192>(a, pairs, spec, stream, ws); break;
-    case 256: launch_rows<256>(a, pairs, spec, stream, ws); break;
-    case 384: launch_rows<384>(a, pairs, spec, stream, ws); break;
-    case 512: launch_rows<512>(a, pairs, spec, stream, ws); break;
-    case 768: launch_rows<768>(a, pairs, spec, stream, ws); break;
-    case 1024: launch_rows<1024>(a, pairs, spec, stream, ws); break;
-    case 1536: launch_rows<1536>(a, pairs, spec, stream, ws); break;
-    case 2048: launch_rows<2048>(a, pairs, spec, stream, ws); break;
-    case 3072: launch_rows<3072>(a, pairs, spec, stream, ws); break;
-    case 4096: launch_rows<4096>(a, pairs, spec, stream, ws); break;
-    case 6144: launch_rows<6144>(a, pairs, spec, stream, ws); break;
-    default: launch_rows<8192>(a, pairs, spec, stream, ws); break;
+    case 64: launch_rows<64>(a, pairs, spec, sq, stream, ws); break;
+    case 128: launch_rows<128>(a, pairs, spec, sq, stream, ws); break;
+    case 192: launch_rows<192>(a, pairs, spec, sq, stream, ws); break;
+    case 256: launch_rows<256>(a, pairs, spec, sq, stream, ws); break;
+    case 384: launch_rows<384>(a, pairs, spec, sq, stream, ws); break;
+    case 512: launch_rows<512>(a, pairs, spec, sq, stream, ws); break;
+    case 768: launch_rows<768>(a, pairs, spec, sq, stream, ws); break;
+    case 1024: launch_rows<1024>(a, pairs, spec, sq, stream, ws); break;
+    case 1536: launch_rows<1536>(a, pairs, spec, sq, stream, ws); break;
+    case 2048: launch_rows<2048>(a, pairs, spec, sq, stream, ws); break;
+    case 3072: launch_rows<3072>(a, pairs, spec, sq, stream, ws); break;
+    case 4096: launch_rows<4096>(a, pairs, spec, sq, stream, ws); break;
+    case 6144: launch_rows<6144>(a, pairs, spec, sq, stream, ws); break;
+    default: launch_rows<8192>(a, pairs, spec, sq, stream, ws); break;
     }
 }
 
@@ -1134,7 +1164,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
-    const bool solo = q.stride != 0;
+    const bool joint = q.stride != 0;   // independent seeds: seed and data in one transform
     const int per = fft_per_transform(ctx, q, L);
     if (per == 4 && !fft_can_pack(q, L)) {
         set_error("four sub-blocks per transform need a shared seed, "
@@ -1151,8 +1181,9 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     const uint64_t pairs = (q.n_sub + per - 1ull) / per;
     // Equal chunks of at most `chunk` transforms (no short last chunk).
     const uint64_t nchunks = (pairs + chunk - 1) / chunk;
-    const uint32_t cp = solo ? 1u : (uint32_t)((pairs + nchunks - 1) / nchunks);
-    if ((st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK) return st;
+    const uint32_t cp = (uint32_t)((pairs + nchunks - 1) / nchunks);
+    if (!joint && (st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK)
+        return st;
     if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
         return st;
     // Parity words: the regions of q_range, out_cap_bits / 64 + 3 n_sub words.
@@ -1196,10 +1227,11 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.out = q.out;
     a.qbuf = ws.fft_qbuf.as<uint64_t>();
     a.status = q.status;
+    a.stride = q.stride;
     const uint32_t tiles = a.n2 / kN1;
     a.per = per;
-    // Seed spectrum: once for a shared seed; with a seed stride, the
-    // spectrum of sub-block j's seed before each of its transforms.
+    // Seed spectrum: once for a shared seed (with a seed stride every
+    // transform carries its own seed and is squared instead).
     auto spectrum = [&](uint64_t seed_off) {
         a.pair0 = 0;
         a.seed_off = seed_off;
@@ -1209,12 +1241,14 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         mids(false, 1);
         rows(a, 1, true, stream);
     };
-    if (!solo) spectrum(0);
+    if (!joint) spectrum(0);
     for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
         const uint32_t np = (uint32_t)std::min<uint64_t>(cp, pairs - p0);
-        if (solo) spectrum(p0 * q.stride);
         a.pair0 = (uint32_t)p0;
-        if (per == 4)
+        if (joint)
+            launch_timed(&ws, "k_fft_cols", k_fft_cols<false, false, true>,
+                         dim3(tiles, np), dim3(kThreads), stream, a);
+        else if (per == 4)
             launch_timed(&ws, "k_fft_cols", k_fft_cols<false, true>, dim3(tiles, np),
                          dim3(kThreads), stream, a);
         else
@@ -1224,12 +1258,15 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
             mids(false, np);
         }
-        rows(a, np, false, stream, &ws);
+        rows(a, np, false, stream, &ws, joint);
         if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", stream);
             mids(true, np);
         }
-        if (per == 4)
+        if (joint)
+            launch_timed(&ws, "k_fft_out", k_fft_out<false, true>, dim3(tiles, np),
+                         dim3(kThreads), stream, a);
+        else if (per == 4)
             launch_timed(&ws, "k_fft_out", k_fft_out<true>, dim3(tiles, np),
                          dim3(kThreads), stream, a);
         else

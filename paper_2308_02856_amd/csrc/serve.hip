@@ -93,6 +93,13 @@ struct JobPlan {
     uint64_t n = 0, l_ub = 0, n_cap = 0, m_cap = 0, stride = 0;
     uint64_t seed_bits = 0, out_words = 0, sub_cap = 0;
     ScratchSizes samp, hash;
+    // Hash kernel and schedule, fixed at submission (the footprint depends
+    // on them): the FFT hash (one transform per sub-block with its own seed)
+    // when it pays, else the bit-sliced VALU kernel.
+    bool fft = false;
+    ValuSchedule valu;
+    FftSchedule fsched;
+    size_t fft_work_b = 0, fft_qbuf_b = 0;
     size_t in_b = 0, sub_b = 0, len_b = 0, seed_b = 0, out_b = 0, misc_b = 256;
     size_t total = 0;
 };
@@ -134,6 +141,7 @@ struct ServeState {
 };
 
 static constexpr int kSlots = 6;
+static constexpr uint64_t kServeFftChunkMiB = 48;
 
 uint64_t job_out_words(const ssbh_job &j) {
     uint64_t cap;
@@ -175,8 +183,23 @@ static ssbh_status plan_job(const ssbh_ctx *ctx, const ssbh_job &j,
     q.n_sub = j.n_sub;
     q.sub_cap = p.sub_cap;
     q.m_cap = p.m_cap;
-    q.kernel = SSBH_K_VALU;
     q.stride = p.stride;
+    q.seed_bits = p.seed_bits;
+    q.out_cap_bits = p.out_words * 64;
+    p.fft = fft_pays(q);
+    if (p.fft) {
+        // Transforms of at most kServeFftChunkMiB per chunk: a job's share of
+        // the budget stays modest, so several jobs fit at once.
+        const uint64_t L = fft_length(p.stride);
+        p.fsched.chunk_pairs = fft_chunk_of_bytes(L, kServeFftChunkMiB);
+        const uint64_t cp = std::min<uint64_t>(p.fsched.chunk_pairs, j.n_sub);
+        p.fft_work_b = (size_t)cp * L * 16;
+        p.fft_qbuf_b = (size_t)(q.out_cap_bits / 64 + 3ull * j.n_sub + 4) * 8;
+        q.kernel = SSBH_K_FFT;
+    } else {
+        q.kernel = SSBH_K_VALU;
+        p.valu = choose_valu(ctx, q);
+    }
     p.hash = hash_scratch(ctx, q);
     p.in_b = j.in_on_device ? 0 : round256((j.n_bits + 63) / 64 * 8);
     p.sub_b = round256(p.sub_cap * 8);
@@ -186,7 +209,8 @@ static ssbh_status plan_job(const ssbh_ctx *ctx, const ssbh_job &j,
     p.total = p.in_b + p.sub_b + 2 * p.len_b + p.seed_b + p.out_b + p.misc_b +
               round256(p.samp.counts) + round256(p.samp.offs) +
               round256(p.samp.part) + round256(p.hash.plan) +
-              round256(p.hash.tiles) + round256(p.hash.counters);
+              round256(p.hash.tiles) + round256(p.hash.counters) +
+              round256(p.fft_work_b) + round256(p.fft_qbuf_b);
     return SSBH_OK;
 }
 
@@ -220,6 +244,10 @@ static ssbh_status enqueue_job(ssbh_ctx *ctx, ServeState &S, Job &job) {
     lend(ws.plan, p.hash.plan);
     lend(ws.tiles, p.hash.tiles);
     lend(ws.counters, p.hash.counters);
+    if (p.fft) {
+        lend(ws.fft_work, p.fft_work_b);
+        lend(ws.fft_qbuf, p.fft_qbuf_b);
+    }
 
     if (!j.in_on_device && p.n) {
         SSBH_CHECK_HIP(hipMemcpyAsync((void *)d_in, j.in, (p.n + 63) / 64 * 8,
@@ -233,9 +261,11 @@ static ssbh_status enqueue_job(ssbh_ctx *ctx, ServeState &S, Job &job) {
     if (rc != SSBH_OK) return rc;
     HashRequest q{d_sub, p.sub_cap, d_len, d_woff, j.n_sub, j.out_rule,
                   j.out_a, j.out_b, nullptr, d_seed, p.seed_bits, p.stride,
-                  p.m_cap, SSBH_K_VALU, d_out, p.out_words * 64, d_total,
-                  d_status};
-    rc = launch_hash(ctx, ws, q, st);
+                  p.m_cap, p.fft ? SSBH_K_FFT : SSBH_K_VALU, d_out,
+                  p.out_words * 64, d_total, d_status};
+    (void)hipGetLastError();   // clear errors left by earlier calls
+    rc = p.fft ? launch_hash_fft(ctx, ws, q, p.fsched, st)
+               : launch_hash_valu(ctx, ws, q, p.valu, st);
     if (rc != SSBH_OK) return rc;
     if (!j.out_on_device) {
         SSBH_CHECK_HIP(hipMemcpyAsync(j.out, d_out, p.out_words * 8,
@@ -360,12 +390,14 @@ ssbh_status ssbh_submit(ssbh_ctx *ctx, const ssbh_job *job, uint64_t *job_id) {
     SSBH_CHECK_HIP(hipSetDevice(ctx->device));
     auto j = std::make_unique<Job>();
     j->spec = *job;
-    ssbh_status rc = plan_job(ctx, *job, j->plan);
-    if (rc != SSBH_OK) return rc;
+    ssbh_status rc;
     {
+        // The plan reads the context's forced schedules: under its lock.
         std::lock_guard<std::mutex> g(ctx->mu);
-        if ((rc = serve_init(ctx)) != SSBH_OK) return rc;
+        rc = plan_job(ctx, *job, j->plan);
+        if (rc == SSBH_OK) rc = serve_init(ctx);
     }
+    if (rc != SSBH_OK) return rc;
     ServeState &S = *ctx->serve;
     if (round256(j->plan.total) > S.arena.size()) {
         set_error("job needs %zu bytes of device memory, budget is %zu",

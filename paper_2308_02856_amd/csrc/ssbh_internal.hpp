@@ -209,6 +209,7 @@ struct ScratchSizes {
 ScratchSizes sample_scratch(uint64_t n_bits, uint32_t n_sub, uint32_t mode);
 ScratchSizes hash_scratch(const ssbh_ctx *ctx, const HashRequest &q);
 ValuSchedule choose_valu(const ssbh_ctx *ctx, const HashRequest &q);
+bool fft_pays(const HashRequest &q);
 std::string tune_bucket(const HashRequest &q);
 
 // Allow `kernel` to take `bytes` of dynamic LDS (needed above 64 KiB).

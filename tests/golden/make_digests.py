@@ -12,6 +12,8 @@ ceil(bits / 64) words, tail bits zero) with its length in bits:
 * single       one block, 2^24 uniform bits -> 2^23 bits;
 * batched      2^28 Bernoulli(0.3) bits, i.i.d. over 2048 sub-blocks,
                floor(2 n_j / 5) bits each, one shared seed;
+* batched_independent  the same with an independent seed window per
+               sub-block (stride max n_j + max m_j - 1);
 * contraction  2^30 uniform bits, keyed permutation, 8192 x 2^17 -> 2^16;
 * serving      every job of the benchmark's 3200-job stream with fewer than
                2^24 input bits, plus 20 larger ones drawn with a fixed seed.
@@ -85,6 +87,28 @@ def batched() -> dict:
     return {"sha256": digest(out, total), "bits": total, "l_ub": l_ub,
             "seed_bits": seed_bits,
             "sub_sha256": digest(sub, 64 * int(sub.size))}
+
+
+def batched_independent() -> dict:
+    """The batched workload with the paper's independent seeds: sub-block
+    j's Toeplitz matrix comes from its own seed window at stride
+    S = max n_j + max m_j - 1 (Sec. III.B step 3)."""
+    c = config("batched")
+    n, ns, key = c["n_bits"], c["n_sub"], c["sample_key"]
+    a = bernoulli_bits(n, c["p"], c["input_seed"])
+    l_ub = oracle.ub_threshold(n, 1.0 / ns, ns, 1e-8)
+    sub, ln, wo, abort = oracle.sample(a, n, ns, oracle.SAMPLE_IID, key=key,
+                                       l_ub=l_ub)
+    assert not abort
+    om = oracle.out_lengths(ln, oracle.OUT_RATIO, c["out_a"], c["out_b"])
+    cap = int(om.max())
+    stride = int(ln.max()) + cap - 1
+    seed_bits = ns * stride
+    seed = uniform_bits(seed_bits, c["indep_seed_seed"])
+    out, total = oracle.hash_batch(sub, ln, wo, om, seed, seed_bits, stride,
+                                   cap)
+    return {"sha256": digest(out, total), "bits": total, "stride": stride,
+            "seed_bits": seed_bits}
 
 
 def contraction() -> dict:
@@ -172,10 +196,12 @@ def main(parts: list[str]) -> None:
                 json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
         else:
             data[part] = {"single": single, "batched": batched,
+                          "batched_independent": batched_independent,
                           "contraction": contraction}[part]()
             json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
         log(f"{part}: done in {time.time() - t0:.0f} s")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["single", "batched", "contraction", "serving"])
+    main(sys.argv[1:] or ["single", "batched", "batched_independent",
+                          "contraction", "serving"])

@@ -146,8 +146,8 @@ def test_rejects_long_seeds_and_short_strides(ctx):
                                           (4, 100000, 37000, 64), (7, 1000, 999, 3)])
 def test_independent_seeds_match_oracle_and_valu(ctx, orc, ns, n, m, extra):
     """Seed stride S = n_max + m - 1 + extra (the paper's independent seeds):
-    one transform per sub-block with its own seed spectrum; equal to the
-    oracle and to the VALU kernel on every bit."""
+    one transform per sub-block carrying its seed window and its bits; equal
+    to the oracle and to the VALU kernel on every bit."""
     import torch
     from paper_2308_02856_amd import ssbh
     N = n * ns + 333
@@ -356,12 +356,15 @@ def test_single_block_workload_three_levels(ctx, orc):
         assert ((int(got[r >> 6]) >> (r & 63)) & 1) == want, r
 
 
-@pytest.mark.parametrize("n,m,want_fft", [(1 << 16, 1 << 15, True),
-                                          (4000, 2000, False)])
-def test_untuned_auto_picks_fft_for_long_blocks(n, m, want_fft):
-    """Without a tuned entry, AUTO takes the FFT for a shared seed when the
-    quadratic work is far above the transform's (n m >= 1024 L log2 L), and
-    gives the VALU kernel's bits either way."""
+@pytest.mark.parametrize("n,m,want_fft,indep", [(1 << 16, 1 << 15, True, False),
+                                                (4000, 2000, False, False),
+                                                (1 << 16, 1 << 15, True, True),
+                                                (4000, 2000, False, True)])
+def test_untuned_auto_picks_fft_for_long_blocks(n, m, want_fft, indep):
+    """Without a tuned entry, AUTO takes the FFT when the quadratic work is
+    well above the transform's (n m >= 1024 L log2 L / sub-blocks per
+    transform), for a shared seed and for independent seeds alike, and gives
+    the VALU kernel's bits either way."""
     import torch
     from paper_2308_02856_amd import ssbh
     ctx = ssbh.Context(0)
@@ -371,11 +374,12 @@ def test_untuned_auto_picks_fft_for_long_blocks(n, m, want_fft):
         sub = uniform_bits(ns * words * 64, n)
         lens = np.full(ns, n, np.uint64)
         wo = (np.arange(ns) * words).astype(np.uint64)
-        seed_bits = n + m - 1
+        stride = n + m - 1 if indep else 0
+        seed_bits = (ns if indep else 1) * (n + m - 1)
         seed = to_dev(uniform_bits(seed_bits, m))
         args = (to_dev(sub), sub.size, to_dev(lens), to_dev(wo), ns, seed,
                 seed_bits, m)
-        kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m)
+        kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m, seed_stride=stride)
         out, tot, st = ctx.hash_batch(*args, kernel=ssbh.K_AUTO, **kw)
         torch.cuda.synchronize()
         assert int(st.item()) == 0
@@ -410,3 +414,46 @@ def test_four_level_single_block_960_mbit(ctx, orc):
     for r in [0, 1, 63, 64, m - 1] + [int(v) for v in rng.integers(0, m, 6)]:
         want = orc.toeplitz_rowwin(x, n, seed_h, seed_bits, 0, m, r)
         assert ((int(got[r >> 6]) >> (r & 63)) & 1) == want, r
+
+
+@pytest.mark.parametrize("L", LENGTHS)
+def test_every_transform_length_independent(ctx, orc, L):
+    """Independent seeds (stride S = L - 3 selects the length; sub-block j's
+    seed window starts at bit jS) with two, three and four levels: FFT ==
+    VALU kernel on every bit, and sampled rows == the oracle."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    ns = 5
+    S = L - 3
+    lens = np.array([S // 2 - 7 * j for j in range(ns)], dtype=np.uint64)
+    M = int(S - int(lens.max()) + 1)                   # n_max + M - 1 = S
+    outl = np.array([M - 11 * j for j in range(ns)], dtype=np.uint64)
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = uniform_bits(int(words.sum()) * 64, L + 5)
+    for j in range(ns):
+        r = int(lens[j]) % 64
+        if r:
+            sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
+    seed_bits = ns * S
+    seed = uniform_bits(seed_bits, L + 6)
+    dl = torch.from_numpy(outl.view(np.int64)).cuda()
+    args = (to_dev(sub), sub.size, to_dev(lens), to_dev(wo), ns, to_dev(seed),
+            seed_bits, M)
+    kw = dict(out_rule=ssbh.OUT_EXPLICIT, out_len=dl, seed_stride=S)
+    got, tot = fft_hash(ctx, args[0], args[2], args[3], ns, args[5],
+                        seed_bits, M, **kw)
+    assert ctx.last_schedule().endswith(":L%d" % L)
+    out, tot2, st = ctx.hash_batch(*args, kernel=ssbh.K_VALU, **kw)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and int(tot2.item()) == tot
+    assert np.array_equal(got, to_host(out)), first_diff(got, to_host(out))
+    ooff = np.concatenate([[0], np.cumsum(outl)[:-1]])
+    rng = np.random.default_rng(L + 1)
+    for _ in range(12):
+        j = int(rng.integers(0, ns))
+        r = int(rng.integers(0, int(outl[j])))
+        want = orc.toeplitz_rowwin(sub[int(wo[j]):], int(lens[j]), seed,
+                                   seed_bits, j * S, M, r)
+        k = int(ooff[j]) + r
+        assert ((int(got[k >> 6]) >> (k & 63)) & 1) == want, (j, r)

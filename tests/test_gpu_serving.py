@@ -162,8 +162,10 @@ def test_small_budget_admits_in_turn(orc):
         want, total = oracle_job(orc, bits, n, ns, 0x900 + k, 0xA00 + k, 1, 2, 5)
         assert res[jid].status == 0 and res[jid].out_bits == total
         assert np.array_equal(to_host(out)[: want.size], want)
-    big = bernoulli_bits(1 << 24, 0.5, 10)
-    job, _ = ctx.make_job(to_dev(big), 1 << 24, 64, 1, 2, 1, 2, 5)
+    # Two sub-blocks of 2^27 bits: the job's transforms alone (2^28 points)
+    # are far beyond the budget (its content does not matter).
+    big = torch.zeros(1 << 22, dtype=torch.int64, device="cuda")
+    job, _ = ctx.make_job(big, 1 << 28, 2, 1, 2, 1, 2, 5)
     with pytest.raises(ssbh.SsbhError) as e:
         ctx.submit(job)
     assert e.value.status == ssbh.E_NOMEM

@@ -11,7 +11,9 @@ run (tests, benchmark, smoke check) sees the same synthetic data.
                   with a seed of n + m - 1 bits (no sampling).
 * ``batched``     N = 2^28 Bernoulli(0.3) bits, i.i.d. uniform assignment to
                   2048 sub-blocks, output floor(0.4 * n_j) bits each, one
-                  shared seed of max n_j + max m_j - 1 bits.
+                  shared seed of max n_j + max m_j - 1 bits (or, as the
+                  paper's protocol has it, an independent seed window per
+                  sub-block at stride max n_j + max m_j - 1).
 * ``contraction`` N = 2^30 uniform bits, keyed permutation then split into 8192
                   sub-blocks of 2^17 bits, shared seed, 2^16 output bits each.
 * ``serving``     a Poisson stream (mean 200 jobs/s) of jobs with block sizes
@@ -50,6 +52,7 @@ CONFIGS = {
         name="batched", n_bits=1 << 28, p=0.3, n_sub=2048, sampling="iid",
         out_rule="ratio", out_a=2, out_b=5, seed_mode="shared",
         input_seed=3, sample_key=_KEY_BASE + 0x103, seed_seed=203,
+        indep_seed_seed=303,   # independent seeds: stride n_max + m_max - 1
     ),
     "contraction": dict(
         name="contraction", n_bits=1 << 30, p=0.5, n_sub=8192,
