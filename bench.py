@@ -227,12 +227,97 @@ def run_batched(ctx, ssbh, args):
     res = dict(n=n, ns=ns, lens=lens, mlen=mlen, cap=cap, seed_bits=seed_bits,
                work=work, ms_step=ms_step,
                hash_ms=float(np.mean(hash_ms)), sample_ms=float(np.mean(samp_ms)),
-               a=a, out=out, sub=sub, wo=wo, seed=seed, key=key, c=c,
+               a=a, out=out, sub=sub, ln=ln, wo=wo, st=st, seed=seed, key=key,
+               c=c, sample=sample,
                schedule=schedule, tune_report=tune_report, l_ub=l_ub,
                hash_kernels=hash_kernels, sample_kernels=sample_kernels,
                timed_calls=reps,
                sift_ms=float(np.mean(sift_ms)), l_ub_sifted=l_ub2)
     return res
+
+
+def run_batched_independent(ctx, ssbh, args, res):
+    """The batched step with the paper's independent seeds (Sec. III.B
+    step 3): sub-block j hashed with its own seed window at stride
+    S = max n_j + max m_j - 1 (seed of 2048 S bits).  The tuner picks among
+    the FFT (one transform per sub-block: seed window real, bits imaginary,
+    spectrum squared) at each chunk size and the VALU schedules."""
+    import torch
+    from workloads import uniform_bits
+    c, ns, lens, mlen, cap = res["c"], res["ns"], res["lens"], res["mlen"], res["cap"]
+    sub, ln, wo, st = res["sub"], res["ln"], res["wo"], res["st"]
+    stride = int(lens.max()) + cap - 1
+    seed_bits = ns * stride
+    seed = to_dev(uniform_bits(seed_bits, c["indep_seed_seed"]))
+    out_cap = int(mlen.sum())
+    out = torch.empty((out_cap + 63) // 64, dtype=torch.int64, device="cuda")
+    outv = torch.empty_like(out)
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def hash_(kern, o):
+        ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, seed_bits, cap,
+                       out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
+                       out_b=c["out_b"], out=o, out_capacity_bits=out_cap,
+                       total=tot, status=st, reset_status=False,
+                       seed_stride=stride, kernel=kern)
+
+    log("batched, independent seeds: autotuning (untimed)")
+    tune_report = ctx.tune(sub, sub.numel(), ln, wo, ns, seed, seed_bits, cap,
+                           out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
+                           out_b=c["out_b"], seed_stride=stride, out=out,
+                           out_capacity_bits=out_cap, total=tot, status=st)
+    hash_(ssbh.K_AUTO, out)
+    hash_(ssbh.K_VALU, outv)
+    torch.cuda.synchronize()
+    if int(st.item()) != 0:
+        raise RuntimeError("independent-seed hash: device status nonzero")
+    same = bool(torch.equal(out, outv))
+    hash_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_AUTO, out),
+                                        max(3, args.steps))))
+    hash_(ssbh.K_AUTO, out)
+    schedule = ctx.last_schedule()
+    valu_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res["sample"]()
+        hash_(ssbh.K_AUTO, out)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    if int(st.item()) != 0:
+        raise RuntimeError("independent-seed step: device status nonzero")
+    oracle_equal = digest_equal("batched_independent", out, out_cap)
+    item = {"workload": "batched_independent", "seed_stride": stride,
+            "seed_bits": seed_bits, "hash_kernel": schedule,
+            "ms_per_step": round(ms_step, 4),
+            "gbps_step": round(res["n"] / (ms_step * 1e-3) / 1e9, 3),
+            "hash_ms": round(hash_ms, 4), "hash_ms_valu": round(valu_ms, 4),
+            "gbps_hash": round(res["n"] / (hash_ms * 1e-3) / 1e9, 3),
+            "auto_equals_valu": same, "oracle_digest_equal": oracle_equal,
+            "tuning": tune_report.strip().splitlines()}
+    if schedule.startswith("fft"):
+        # Row pass in the joint mode: each transform is read and written
+        # once (L complex doubles each way); there is no seed spectrum.
+        ctx.set_timing(True)
+        reps = max(3, args.steps)
+        for _ in range(reps):
+            hash_(ssbh.K_AUTO, out)
+        hk = ctx.timing_report()
+        ctx.set_timing(False)
+        n_l, ms = hk["k_fft_rows"]
+        L = int(schedule.split(":L")[1])
+        total_bytes = reps * ns * 2 * L * 16
+        achieved = total_bytes / (ms * 1e-3) / 1e9
+        item["roofline"] = {
+            "bound": "hbm", "kernel": "k_fft_rows", "schedule": schedule,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(ms * 1e3 / n_l, 2),
+            "algorithmic_bytes_per_launch": int(total_bytes / n_l)}
+        item["kernel_avg_us"] = kernel_avgs(hk)
+    del seed, out, outv
+    torch.cuda.empty_cache()
+    return item
 
 
 def run_single(ctx, ssbh, args):
@@ -604,6 +689,15 @@ def run_serving(ssbh, args):
     meas = range(args.serve_warmup, len(made))
     lat = np.array([(results[i].t_done - results[i].t_submit) * 1e3
                     for i in meas])
+    sizes = np.array([made[i][0]["n_bits"] for i in meas])
+    by_size = {}
+    for name, lo, hi in (("below_2^24", 0, 1 << 24), ("2^24_to_2^27", 1 << 24, 1 << 27),
+                         ("from_2^27", 1 << 27, 1 << 40)):
+        sel = lat[(sizes >= lo) & (sizes < hi)]
+        if sel.size:
+            by_size[name] = {"jobs": int(sel.size),
+                             "p50_ms": round(float(np.percentile(sel, 50)), 3),
+                             "p99_ms": round(float(np.percentile(sel, 99)), 3)}
     t0 = min(results[i].t_submit for i in meas)
     t1 = max(results[i].t_done for i in meas)
     bits = sum(made[i][0]["n_bits"] for i in meas)
@@ -627,6 +721,7 @@ def run_serving(ssbh, args):
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3),
             "p99_queue_ms": round(float(np.percentile(queued, 99)), 3),
+            "latency_by_size": by_size,
             "sustained_gbps": round(bits / (t1 - t0) / 1e9, 3),
             "offered_gbps": round(offered / 1e9, 3),
             "busy_frac": round(busy / (t1 - t0), 4),
@@ -741,6 +836,7 @@ def main() -> int:
     ap.add_argument("--cpu-subblocks", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
+    ap.add_argument("--skip-independent", action="store_true")
     ap.add_argument("--skip-contraction", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
@@ -809,6 +905,8 @@ def main() -> int:
               flush=True)
         return 0
     single = None if args.skip_single else run_single(ctx, ssbh, args)
+    indep = (None if args.skip_independent else
+             run_batched_independent(ctx, ssbh, args, res))
 
     hk = res["hash_kernels"]
     if res["schedule"].startswith("fft"):
@@ -896,6 +994,8 @@ def main() -> int:
             "valu_alu_frac": round(single["work"] / (single["ms_valu"] * 1e-3)
                                    / 1e12 / peak, 4)}
         line["speedup_vs_single_block"] = round(line["value"] / sg, 2)
+    if indep is not None:
+        line["batched_independent"] = indep
     if not args.skip_contraction:
         line["contraction"] = run_contraction(ctx, ssbh, args, peak)
     if not args.skip_small:
