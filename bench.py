@@ -617,9 +617,14 @@ def run_small(ctx, ssbh, args):
 
     e_ms = timed(eager)
     g_ms = timed(pipe.launch)
+    # One replay at a time on an idle stream, bracketed by HIP events: the
+    # device's latency per pass (the back-to-back figure above is bound by
+    # the host's graph submissions).
+    dev_ms = float(np.median(time_events(pipe.launch, 50)))
     pipe.close()
     return {"workload": "small", "n_bits": n, "n_sub": ns,
             "eager_ms": round(e_ms, 4), "graph_ms": round(g_ms, 4),
+            "graph_device_ms": round(dev_ms, 4),
             "gbps_graph": round(n / (g_ms * 1e-3) / 1e9, 3),
             "graph_equals_eager": same}
 

@@ -20,6 +20,8 @@ namespace ssbh {
 static ssbh_status enqueue_pipeline(ssbh_pipeline *p, hipStream_t st) {
     const ssbh_pipeline_desc &d = p->d;
     ssbh_status rc;
+    if (small_path_ok(d) && !p->ctx->forced_valu_r)
+        return launch_small_fused(p->ctx, p->ws, d, st);
     if (d.d_in) {
         rc = launch_sample(p->ctx, p->ws, d.d_in, d.d_keep, d.n_bits, d.n_sub,
                            d.mode,

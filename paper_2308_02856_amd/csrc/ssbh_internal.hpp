@@ -198,6 +198,12 @@ ssbh_status launch_permutation(ssbh_ctx *ctx, DevBuf &scratch, uint64_t key,
                                hipStream_t stream);
 size_t permutation_scratch(uint64_t n);
 
+// Fused two-kernel path of a graph pipeline for small permutation-split jobs
+// with equal sub-blocks and 64-bit aligned outputs (small.hip).
+bool small_path_ok(const ssbh_pipeline_desc &d);
+ssbh_status launch_small_fused(ssbh_ctx *ctx, Workspace &ws,
+                               const ssbh_pipeline_desc &d, hipStream_t stream);
+
 // Scratch each launch layer will reserve for the given request (bytes per
 // Workspace buffer), so callers can lend pre-sized memory.
 struct ScratchSizes {
