@@ -995,10 +995,10 @@ struct FftTables {
 std::mutex g_tab_mu;
 std::map<std::pair<int, uint64_t>, FftTables *> g_tables;   // (device, L)
 
-// Levels of the transform: 64 x (L/64) up to 2^18, 64 x 64 x (L/4096) up to
-// 3 * 2^23, 64 x 64 x 64 x (L/2^18) above.
+// Levels of the transform: 64 x (L/64) up to 2^19 (rows of up to 8192
+// points), 64 x 64 x (L/4096) up to 3 * 2^23, 64 x 64 x 64 x (L/2^18) above.
 int fft_levels(uint64_t L) {
-    return L <= (1ull << 18) ? 2 : L <= (3ull << 23) ? 3 : 4;
+    return L <= (1ull << 19) ? 2 : L <= (3ull << 23) ? 3 : 4;
 }
 // Row FFT length.
 uint64_t row_length(uint64_t L) { return L >> (6 * (fft_levels(L) - 1)); }
@@ -1113,12 +1113,12 @@ void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream,
 // 3 * 2^k, 4096 <= L <= 2^31, with two, three or four levels and row FFTs of
 // 64 .. 8192 points; kMaxFftLength + 1 when none holds it.
 uint64_t fft_length(uint64_t seed_bits) {
-    // Every row length is a multiple of 64: 3 * 2^11 (two levels) and
-    // 3 * 2^17 (three levels) are left out.
+    // Every row length is a multiple of 64: 3 * 2^11 (two levels, rows of
+    // 96 points) is left out.
     for (uint64_t L = 4096; L <= kMaxFftLength;) {
         if (L >= seed_bits) return L;
         L = (L % 3 == 0) ? L / 3 * 4 : L / 2 * 3;   // 2^k, 3 * 2^(k-1), 2^(k+1)
-        if (L == 6144 || L == 393216) L = L / 3 * 4;
+        if (L == 6144) L = 8192;
     }
     return kMaxFftLength + 1;
 }

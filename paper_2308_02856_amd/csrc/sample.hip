@@ -745,17 +745,18 @@ uint32_t ceil_log2(uint32_t x) {
 
 }  // namespace
 
-// Segment size: about 32 bits per sub-block per segment (so runs are a few
-// words long), at least 2^14 bits, LDS image at most 32 KiB.
 // Segment length: about 32 rounds per sub-block, 2^14 .. 2^18 - 512 rounds
-// (a quarter stays below 2^16 rounds), a multiple of 512; at most 65024
-// while 32 n_sub <= 2^16, so the workgroup scatter's positions fit 16 bits.
+// (a quarter stays below 2^16 rounds), a multiple of 512; at most 65024 for
+// n_sub <= 4096, so that the workgroup scatter (16-bit positions, LDS for up
+// to 4096 sub-blocks) takes it: above 2032 sub-blocks that is fewer than 32
+// rounds per sub-block, which costs shorter runs but runs 3-5 times faster
+// than the one-wavefront scatters.
 static uint64_t segment_bits(uint32_t ns) {
     uint64_t seg = 32ull * ns;
     seg = std::max<uint64_t>(seg, 1ull << 14);
     seg = std::min<uint64_t>(seg, (1ull << 18) - 512);
     seg = (seg + 511) / 512 * 512;
-    if (seg > kWgMaxSeg && seg <= (1ull << 16)) seg = kWgMaxSeg;
+    if (seg > kWgMaxSeg && ns <= 4096) seg = kWgMaxSeg;
     return seg;
 }
 

@@ -253,7 +253,8 @@ def test_fft_graph_pipeline_replays(ctx, orc):
 
 
 LENGTHS = [4096, 8192, 12288, 16384, 24576, 32768, 49152, 65536, 98304,
-           131072, 196608, 262144, 524288, 786432, 1048576, 1 << 25, 3 << 24]
+           131072, 196608, 262144, 393216, 524288, 786432, 1048576, 1 << 25,
+           3 << 24]
 
 
 @pytest.mark.parametrize("L", LENGTHS)
