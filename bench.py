@@ -236,6 +236,27 @@ def run_batched(ctx, ssbh, args):
     return res
 
 
+def sampling_roofline(res) -> dict:
+    """Sampling (a1-a3) against HBM: per call it must read the N input
+    bits once and write the N bits of the sub-block buffer once (2 N / 8
+    bytes); its two kernels' HIP-event time per call is the denominator.
+    The kernels are bound by their LDS work (match tables, cursors and the
+    image, with bank conflicts on random addresses) and by the SplitMix64
+    draws made in both passes, not by HBM; the fraction shows how far."""
+    sk = res["sample_kernels"]
+    calls = res["timed_calls"]
+    us = {k: ms * 1e3 / calls for k, (n_l, ms) in sk.items()}
+    t_s = sum(us.values()) * 1e-6
+    bytes_call = 2 * res["n"] // 8
+    achieved = bytes_call / t_s / 1e9
+    return {"bound": "hbm", "kernels": sorted(sk), "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_call": bytes_call,
+            "us_per_call": round(t_s * 1e6, 2),
+            "limit": "LDS (profiles/lds_counters__sampling_batched_2p28_2048sub.txt)"}
+
+
 def run_batched_independent(ctx, ssbh, args, res):
     """The batched step with the paper's independent seeds (Sec. III.B
     step 3): sub-block j hashed with its own seed window at stride
@@ -981,6 +1002,7 @@ def main() -> int:
         "sifted_sample_ms": round(res["sift_ms"], 4),
         "bit_products_per_s": float(f"{res['work'] / (res['hash_ms'] * 1e-3):.4g}"),
         "roofline": roof,
+        "roofline_sampling": sampling_roofline(res),
         "kernel_avg_us": {**kernel_avgs(res["sample_kernels"]),
                           **kernel_avgs(res["hash_kernels"])},
         "tuning": res["tune_report"].strip().splitlines(),
