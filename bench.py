@@ -282,27 +282,32 @@ def run_batched_independent(ctx, ssbh, args, res):
                        total=tot, status=st, reset_status=False,
                        seed_stride=stride, kernel=kern)
 
-    log("batched, independent seeds: autotuning (untimed)")
-    tune_report = ctx.tune(sub, sub.numel(), ln, wo, ns, seed, seed_bits, cap,
-                           out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
-                           out_b=c["out_b"], seed_stride=stride, out=out,
-                           out_capacity_bits=out_cap, total=tot, status=st)
-    hash_(ssbh.K_AUTO, out)
+    kern = ssbh.K_AUTO
+    tune_report = ""
+    if args.no_tune:
+        kern = ssbh.K_FFT              # chunk from --fft-chunk (else default)
+    else:
+        log("batched, independent seeds: autotuning (untimed)")
+        tune_report = ctx.tune(sub, sub.numel(), ln, wo, ns, seed, seed_bits,
+                               cap, out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
+                               out_b=c["out_b"], seed_stride=stride, out=out,
+                               out_capacity_bits=out_cap, total=tot, status=st)
+    hash_(kern, out)
     hash_(ssbh.K_VALU, outv)
     torch.cuda.synchronize()
     if int(st.item()) != 0:
         raise RuntimeError("independent-seed hash: device status nonzero")
     same = bool(torch.equal(out, outv))
-    hash_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_AUTO, out),
+    hash_ms = float(np.mean(time_events(lambda: hash_(kern, out),
                                         max(3, args.steps))))
-    hash_(ssbh.K_AUTO, out)
+    hash_(kern, out)
     schedule = ctx.last_schedule()
     valu_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res["sample"]()
-        hash_(ssbh.K_AUTO, out)
+        hash_(kern, out)
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     if int(st.item()) != 0:
@@ -322,7 +327,7 @@ def run_batched_independent(ctx, ssbh, args, res):
         ctx.set_timing(True)
         reps = max(3, args.steps)
         for _ in range(reps):
-            hash_(ssbh.K_AUTO, out)
+            hash_(kern, out)
         hk = ctx.timing_report()
         ctx.set_timing(False)
         n_l, ms = hk["k_fft_rows"]
@@ -333,6 +338,8 @@ def run_batched_independent(ctx, ssbh, args, res):
             "bound": "hbm", "kernel": "k_fft_rows", "schedule": schedule,
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic("k_fft_rows", "batched_independent",
+                                    schedule),
             "avg_launch_us": round(ms * 1e3 / n_l, 2),
             "algorithmic_bytes_per_launch": int(total_bytes / n_l)}
         item["kernel_avg_us"] = kernel_avgs(hk)
@@ -874,7 +881,8 @@ def main() -> int:
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-budget-mib", type=int, default=512)
     ap.add_argument("--mode", default="full",
-                    choices=["full", "hash-batched", "hash-single", "copy",
+                    choices=["full", "hash-batched", "hash-independent",
+                             "hash-single", "copy",
                              "contraction", "small", "serving", "table1"],
                     help="full = the benchmark line; the others run one "
                          "part only, for profiler passes")
@@ -922,6 +930,10 @@ def main() -> int:
         print(json.dumps(run_small(ctx, ssbh, args)), flush=True)
         return 0
     res = run_batched(ctx, ssbh, args)
+    if args.mode == "hash-independent":
+        print(json.dumps(run_batched_independent(ctx, ssbh, args, res)),
+              flush=True)
+        return 0
     if args.mode == "hash-batched":
         print(json.dumps({"mode": args.mode, "hash_ms": res["hash_ms"],
                           "sample_ms": res["sample_ms"],
