@@ -14,8 +14,9 @@ CASES = [  # (n, n_sub, keep probability or None)
     (1, 1, None), (63, 2, None), (1000, 7, None), ((1 << 20) + 77, 300, None),
     ((1 << 18) + 1, 2048, 0.5), ((1 << 21) + 5, 2048, None), (200000, 256, 0.9),
     (150000, 257, None), (99999, 1000, 0.3), (4096 * 3 + 17, 3, 1.0),
-    (50000, 1500, 0.0),
+    (50000, 1500, 0.0), ((1 << 21) + 3, 4096, None), (300000, 3000, 0.6),
 ]
+PATHS = [0, 1]
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +27,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n,ns,pk", CASES)
 def test_iid_paths_match_oracle(ctx, orc, path, n, ns, pk):
     import torch
@@ -58,7 +59,7 @@ def test_iid_paths_match_oracle(ctx, orc, path, n, ns, pk):
     assert np.array_equal(got, osub), first_diff(got, osub)
 
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", PATHS)
 def test_explicit_paths_match_oracle(ctx, orc, path):
     import torch
     from paper_2308_02856_amd import ssbh
@@ -79,7 +80,7 @@ def test_explicit_paths_match_oracle(ctx, orc, path):
     assert np.array_equal(got, osub), first_diff(got, osub)
 
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", PATHS)
 def test_explicit_concentrated_assignment(ctx, orc, path):
     """Every round of whole segments in one sub-block (the largest per-quarter
     counts the scatter sees), the rest spread over a few sub-blocks."""
