@@ -553,6 +553,25 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     same_f4 = bool(torch.equal(out, out4))
     oracle_equal = digest_equal("contraction", out, ns * m)
     g_ms = float(np.mean(time_events(sample, 3)))
+    # Per-kernel times of the streaming gather, and the direct gather (one
+    # random input-word read per output bit) on the same permutation.
+    ctx.set_timing(True)
+    for _ in range(3):
+        sample()
+    gather_kernels = kernel_avgs(ctx.timing_report())
+    ctx.set_timing(False)
+    ctx.set_sample_path(1)
+    sub_direct = torch.empty_like(sub)
+    ctx.sample(d_in, n, ns, ssbh.SAMPLE_PERMUTE, assign=perm, sub=sub_direct,
+               sub_capacity=sub_cap, length=ln, word_off=wo, status=st)
+    gd_ms = float(np.mean(time_events(
+        lambda: ctx.sample(d_in, n, ns, ssbh.SAMPLE_PERMUTE, assign=perm,
+                           sub=sub_direct, sub_capacity=sub_cap, length=ln,
+                           word_off=wo, status=st), 2)))
+    ctx.set_sample_path(0)
+    torch.cuda.synchronize()
+    gather_equal = bool(torch.equal(sub, sub_direct)) and int(st.item()) == 0
+    del sub_direct
     mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
     mfma_sched = ctx.last_schedule()
     f4_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_F4, out4), 3)))
@@ -565,6 +584,9 @@ def run_contraction(ctx, ssbh, args, peak_alu):
         "workload": "contraction", "n_bits": n, "n_sub": ns, "sub_bits": L,
         "m_bits": m, "permutation_ms": round(perm_ms, 3),
         "gather_ms": round(g_ms, 3),
+        "gather_kernel_avg_us": gather_kernels,
+        "gather_direct_ms": round(gd_ms, 3),
+        "gather_equals_direct": gather_equal,
         "mfma_ms": round(mf_ms, 3), "valu_ms": round(va_ms, 3),
         "gbps_step_mfma": round(n / ((g_ms + mf_ms) * 1e-3) / 1e9, 3),
         "gbps_hash_mfma": round(n / (mf_ms * 1e-3) / 1e9, 3),

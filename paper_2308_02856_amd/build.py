@@ -15,7 +15,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["api.hip", "sample.hip", "hash_valu.hip", "hash_mfma.hip",
            "serve.hip", "tune.hip", "pipeline.hip", "threshold.hip",
            "hash_fft.hip", "geat.hip", "permute.hip",
-           "noalloc.hip", "small.hip"]
+           "noalloc.hip", "small.hip", "gather.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -21,8 +21,7 @@
 // round (the draws do not depend on the flags) but only rounds with keep_i = 1
 // are counted and placed, which equals sifting every sub-block after the
 // division.
-// permutation mode: one wavefront gathers 64 bits B[k] = A[pi[k]] per step
-// and writes one 64-bit word with a ballot.
+// permutation mode: the gather B[k] = A[pi[k]] (gather.hip).
 #include <algorithm>
 
 #include "ssbh_internal.hpp"
@@ -693,31 +692,6 @@ __global__ __launch_bounds__(256) void k_scatter_wg(SampleArgs a) {
     flush_runs_t(a, seg, cur + 3 * ns, stage, t, 256);
 }
 
-// Permutation mode: B[k] = A[pi[k]], sub-block j = B[jL, (j+1)L).
-__global__ __launch_bounds__(256) void k_perm_gather(
-        const uint64_t *in, uint64_t n, const uint32_t *perm, uint32_t ns,
-        uint64_t L, uint64_t wl, uint64_t *sub, int32_t *status) {
-    if (*status) return;
-    const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwave = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    const uint64_t total = (uint64_t)ns * wl;
-    bool bad = false;
-    for (uint64_t w = wave; w < total; w += nwave) {
-        const uint64_t j = w / wl, ww = w - j * wl;
-        const uint64_t c = ww * 64 + lane;
-        bool bit = false;
-        if (c < L) {
-            const uint32_t p = perm[j * L + c];
-            if (p < n) bit = (in[p >> 6] >> (p & 63)) & 1ull;
-            else bad = true;
-        }
-        const uint64_t word = ballot64(bit);
-        if (lane == 0) sub[w] = word;
-    }
-    if (bad) atomicExch(status, (int32_t)SSBH_E_INVAL);
-}
-
 __global__ void k_perm_meta(uint32_t ns, uint64_t L, uint64_t wl,
                             uint64_t l_ub, uint64_t *len, uint64_t *woff,
                             int32_t *status) {
@@ -845,16 +819,9 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
         }
         hipLaunchKernelGGL(k_perm_meta, dim3((ns + 255) / 256), dim3(256), 0,
                            stream, ns, L, wl, l_ub, d_len, d_woff, d_status);
-        const uint64_t total = (uint64_t)ns * wl;
-        if (total) {
-            const uint64_t waves = std::min<uint64_t>(total, (uint64_t)ctx->num_cus * 32);
-            TimedLaunch timed(ws.timer, "k_perm_gather", stream);
-            hipLaunchKernelGGL(k_perm_gather, dim3((uint32_t)((waves + 3) / 4)),
-                               dim3(256), 0, stream, d_in, n, d_assign, ns, L,
-                               wl, d_sub, d_status);
-        }
         SSBH_CHECK_HIP(hipGetLastError());
-        return SSBH_OK;
+        return launch_perm_gather(ctx, ws, d_in, n, d_assign, ns, L, wl, d_sub,
+                                  d_status, stream);
     }
     if (mode != SSBH_SAMPLE_IID && mode != SSBH_SAMPLE_EXPLICIT)
         SSBH_INVAL("unknown sampling mode %u", mode);

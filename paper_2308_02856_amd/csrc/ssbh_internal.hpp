@@ -86,6 +86,7 @@ struct Workspace {
     DevBuf fft_qbuf;   // FFT hash: parity words in transform order
     DevBuf perm_tmp;   // keyed permutation: counts, groups, chain links
     DevBuf perm_pi;    // keyed permutation built for permutation sampling
+    DevBuf pg;         // permutation gather: cells, slots, looked-up bits
     char last_schedule[48] = "";   // kernel and schedule of the last hash
     KernelTimer *timer = nullptr;  // per-kernel event timing (optional)
     void release();
@@ -197,6 +198,13 @@ ssbh_status launch_permutation(ssbh_ctx *ctx, DevBuf &scratch, uint64_t key,
                                uint64_t n, uint32_t *d_perm,
                                hipStream_t stream);
 size_t permutation_scratch(uint64_t n);
+
+// Permutation sampling's gather B[k] = A[pi[k]] (gather.hip).
+ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
+                               const uint64_t *d_in, uint64_t n,
+                               const uint32_t *d_perm, uint32_t ns, uint64_t L,
+                               uint64_t wl, uint64_t *d_sub, int32_t *d_status,
+                               hipStream_t stream);
 
 // Fused two-kernel path of a graph pipeline for small permutation-split jobs
 // with equal sub-blocks and 64-bit aligned outputs (small.hip).
