@@ -52,39 +52,67 @@ __global__ void k_pg_init(uint32_t *flag) { *flag = 0u; }
 // for 64 ww + lane < L (w = j wl + ww).  A wavefront walks words at a fixed
 // stride, so (j, ww) advance without a division; all of it is the same for
 // the whole wavefront and runs on the scalar unit.
+// A wavefront-uniform 64-bit value, marked as such so that addresses built
+// from it stay in scalar registers (one vector offset serves every load).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <bool ALIGNED>
 struct WordPos {
-    uint64_t j, ww;
-    __device__ __forceinline__ void start(uint64_t w, uint64_t wl) {
-        j = w / wl;
-        ww = w - j * wl;
+    uint64_t kw0, cw0;       // k of the word's bit 0, and 64 ww
+    __device__ __forceinline__ void start(uint64_t w, uint64_t wl, uint64_t L) {
+        if constexpr (ALIGNED) {
+            kw0 = w * 64;
+            cw0 = 0;
+        } else {
+            const uint64_t j = w / wl, ww = w - j * wl;
+            cw0 = ww * 64;
+            kw0 = j * L + cw0;
+        }
     }
-    __device__ __forceinline__ void advance(uint64_t step, uint64_t wl) {
-        ww += step;
-        while (ww >= wl) { ww -= wl; ++j; }
+    // Advance by step words (a sub-block is 64 wl buffer bits, L of them
+    // real; with ALIGNED, L = 64 wl and buffer bit = k).
+    __device__ __forceinline__ void advance(uint64_t step, uint64_t wl, uint64_t L) {
+        kw0 += 64 * step;
+        if constexpr (!ALIGNED) {
+            cw0 += 64 * step;
+            while (cw0 >= 64 * wl) { cw0 -= 64 * wl; kw0 -= 64 * wl - L; }
+        }
     }
-    __device__ __forceinline__ uint64_t k0(uint64_t L) const { return j * L + ww * 64; }
-    __device__ __forceinline__ uint64_t c0() const { return ww * 64; }
+    __device__ __forceinline__ uint64_t k0() const { return kw0; }
+    // Real bits of the word: lanes below L - 64 ww.
+    __device__ __forceinline__ bool real(int lane, uint64_t L) const {
+        if constexpr (ALIGNED) return true;
+        else return cw0 + (uint64_t)lane < L;
+    }
 };
 
 // Bucket pass: one workgroup per chunk, in sub-chunks of kPgSubWords output
-// words (2^13 bits).  Per sub-chunk: each thread's 8 entries of pi, ranks
-// from LDS counters, a scan of the counts, the window offsets sorted by
-// window in LDS with their cell slots beside them, then one coalesced copy
-// of the stage into the cells.  cc[b] is cell b's fill so far.
-constexpr uint32_t kPgSubWords = 128;
+// words (2^14 bits).  Per sub-chunk: each thread's 16 entries of pi, counts
+// per window (LDS atomics), a scan of the counts, the entries placed in LDS
+// sorted by window (atomics on a copy of the run starts; k's slot is set
+// then), and one coalesced copy of the stage into the cells.  The stage
+// holds pi itself: window = p >> 20, offset = p mod 2^20, and an entry's
+// rank in its cell is the cell's fill before the sub-chunk plus its place
+// in the window's run.  cc[b] is cell b's fill so far.
+constexpr uint32_t kPgSubWords = 256;
 constexpr uint32_t kPgPer = kPgSubWords / 16;   // words per wavefront
 
+template <bool ALIGNED>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void k_pg_bucket(PgArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ int live_s;
+    __shared__ uint32_t part[16];
     const uint32_t nb4 = (a.nb + 3u) & ~3u;
     uint32_t *cl = lds;                       // [nb] sub-chunk counts
-    uint32_t *lb = cl + nb4;                  // [nb] sub-chunk run starts
-    uint32_t *cc = lb + nb4;                  // [nb] cell fill
-    uint32_t *part = cc + nb4;                // [16] wave sums of the scan
-    uint32_t *stage = part + 16;              // [kPgSubWords * 64] offsets
-    uint32_t *sslot = stage + kPgSubWords * 64;  // their slots in the chunk
+    uint32_t *lc = cl + nb4;                  // [nb] placement cursors
+    uint32_t *db = lc + nb4;                  // [nb] slot = db + stage index
+    uint16_t *cc = reinterpret_cast<uint16_t *>(db + nb4);  // cell fill
+    uint32_t *stage = reinterpret_cast<uint32_t *>(cc + nb4);  // pi values
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const uint32_t g = blockIdx.x;
@@ -99,33 +127,37 @@ void k_pg_bucket(PgArgs a) {
     uint32_t *cell = a.items + (uint64_t)g * a.nb * a.cap;
     bool bad = false, over = false;
     const bool live = live_s != 0;
-    WordPos pos;
-    pos.start(w0 + (uint64_t)wv, a.wl);
+    WordPos<ALIGNED> pos;
+    pos.start(w0 + (uint64_t)wv, a.wl, a.L);
     for (uint64_t s0 = w0; live && s0 < w1; s0 += kPgSubWords) {
-        // 1. pi of words s0 + 16 i + wv, one word per wavefront and step.
-        uint32_t pv[kPgPer], rv[kPgPer];
-        uint64_t k0v[kPgPer];
+        // 1. pi of words s0 + 16 i + wv, one word per wavefront and step;
+        //    counts per window.
+        // The entries stay in the stage in load order (thread t's entry i
+        // at 1024 i + t) until step 3 sorts them in place.
         uint32_t okm = 0;                     // bit i: entry i is a real bit
+        const WordPos<ALIGNED> first = pos;   // walked again for the slots
+        for (int h = 0; h < (int)kPgPer; h += 8) {   // 8 loads in flight
+            uint32_t pv[8];
 #pragma unroll
-        for (int i = 0; i < (int)kPgPer; ++i) {
-            const uint64_t w = s0 + 16u * i + (uint64_t)wv;
-            k0v[i] = pos.k0(a.L);
-            const bool ok = w < w1 && pos.c0() + (uint64_t)lane < a.L;
-            okm |= ok ? 1u << i : 0u;
-            pv[i] = ok ? a.perm[k0v[i] + lane] : 0xffffffffu;
-            pos.advance(16, a.wl);
-        }
-        // 2. ranks within the sub-chunk (any order: the slot records it).
+            for (int u = 0; u < 8; ++u) {
+                const int i = h + u;
+                const uint64_t w = s0 + 16u * i + (uint64_t)wv;
+                const bool ok = w < w1 && pos.real(lane, a.L);
+                okm |= ok ? 1u << i : 0u;
+                pv[u] = ok ? (a.perm + uniform64(pos.k0()))[lane] : 0xffffffffu;
+                pos.advance(16, a.wl, a.L);
+            }
 #pragma unroll
-        for (int i = 0; i < (int)kPgPer; ++i) {
-            rv[i] = 0u;
-            if ((okm >> i) & 1u) {
-                if (pv[i] < a.n) rv[i] = atomicAdd(&cl[pv[i] >> kPgWinBits], 1u);
-                else bad = true;
+            for (int u = 0; u < 8; ++u) {
+                stage[1024u * (h + u) + t] = pv[u];
+                if ((okm >> (h + u)) & 1u) {
+                    if (pv[u] < a.n) atomicAdd(&cl[pv[u] >> kPgWinBits], 1u);
+                    else bad = true;
+                }
             }
         }
         __syncthreads();
-        // 3. run starts: exclusive scan of cl over the windows.
+        // 2. run starts: exclusive scan of cl over the windows.
         uint32_t tot;
         {
             uint32_t x = 0;
@@ -142,38 +174,58 @@ void k_pg_bucket(PgArgs a) {
             for (int v = 0; v < wv; ++v) run += part[v];
             tot = 0;
             for (int v = 0; v < 16; ++v) tot += part[v];
+            // A window's run at stage [run, run + cl) becomes cell ranks
+            // [cc, cc + cl): slot = b cap + cc + (x - run).  A run that would
+            // pass the capacity marks the chunk overflowed (the direct gather
+            // then writes the output) and is not stored.
             for (uint32_t b = (uint32_t)t * 4u; b < min((uint32_t)t * 4u + 4u, a.nb); ++b) {
-                lb[b] = run;
-                run += cl[b];
+                const uint32_t c = cl[b], f = cc[b];
+                lc[b] = run;
+                if (f + c <= a.cap) {
+                    db[b] = b * a.cap + f - run;
+                } else {
+                    db[b] = 0xffffffffu;
+                    over = true;
+                }
+                run += c;
             }
         }
         __syncthreads();
-        // 4. offsets sorted by window, each with its slot (window * cap +
-        //    rank in the cell; ~0 past the capacity); the slots of k.
+        // 3. entries sorted by window in place (all read before any is
+        //    moved); the slots of k.
+        {
+            uint32_t pv[kPgPer];
 #pragma unroll
-        for (int i = 0; i < (int)kPgPer; ++i) {
-            if (!((okm >> i) & 1u)) continue;
-            uint32_t slot = 0;
-            if (pv[i] < a.n) {
-                const uint32_t b = pv[i] >> kPgWinBits;
-                const uint32_t x = lb[b] + rv[i];
-                const uint32_t r = cc[b] + rv[i];
-                slot = r < a.cap ? b * a.cap + r : 0u;
-                stage[x] = pv[i] & ((1u << kPgWinBits) - 1u);
-                sslot[x] = r < a.cap ? b * a.cap + r : 0xffffffffu;
+            for (int i = 0; i < (int)kPgPer; ++i) pv[i] = stage[1024u * i + t];
+            __syncthreads();
+            WordPos<ALIGNED> again = first;
+#pragma unroll
+            for (int i = 0; i < (int)kPgPer; ++i) {
+                const uint64_t k0 = again.k0();
+                again.advance(16, a.wl, a.L);
+                if (!((okm >> i) & 1u)) continue;
+                uint32_t slot = 0;
+                if (pv[i] < a.n) {
+                    const uint32_t b = pv[i] >> kPgWinBits;
+                    const uint32_t x = atomicAdd(&lc[b], 1u);
+                    stage[x] = pv[i];
+                    const uint32_t d = db[b];
+                    slot = d != 0xffffffffu ? d + x : 0u;
+                }
+                (a.slots + uniform64(k0))[lane] = slot;
             }
-            a.slots[k0v[i] + lane] = slot;
         }
         __syncthreads();
-        // 5. the stage into the cells (runs of a window are contiguous in
-        //    both); 6. cell fills.
+        // 4. the stage into the cells (a window's run is contiguous in
+        //    both); 5. cell fills.
         for (uint32_t x = (uint32_t)t; x < tot; x += 1024) {
-            const uint32_t d = sslot[x];
-            if (d != 0xffffffffu) cell[d] = stage[x];
-            else over = true;
+            const uint32_t p = stage[x];
+            const uint32_t d = db[p >> kPgWinBits];
+            if (d != 0xffffffffu) cell[d + x] = p & ((1u << kPgWinBits) - 1u);
         }
+        __syncthreads();
         for (uint32_t b = t; b < a.nb; b += 1024) {
-            cc[b] += cl[b];
+            cc[b] = (uint16_t)min<uint32_t>(cc[b] + cl[b], 0xffffu);
             cl[b] = 0u;
         }
         __syncthreads();
@@ -184,12 +236,12 @@ void k_pg_bucket(PgArgs a) {
         a.cnt[(uint64_t)b * a.ng + g] = min(cc[b], a.cap);
 }
 
-// Window pass: one workgroup per window; each wavefront takes cells in turn
-// and loads up to 8 x 64 of a cell's entries before looking them up.
+// Window pass: one workgroup per window; each wavefront takes cells in turn.
 __global__ __launch_bounds__(1024) void k_pg_window(PgArgs a) {
     extern __shared__ uint64_t win[];                 // 2^20 bits
     if (*a.status || *a.flag) return;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const uint32_t b = blockIdx.x;
     const uint64_t nw_in = (a.n + 63) / 64;
     const uint64_t wbase = (uint64_t)b << (kPgWinBits - 6);
@@ -198,33 +250,47 @@ __global__ __launch_bounds__(1024) void k_pg_window(PgArgs a) {
         win[i] = wbase + i < nw_in ? a.in[wbase + i] : 0ull;
     __syncthreads();
     const uint32_t *cw = a.cnt + (uint64_t)b * a.ng;
-    for (uint32_t g = wv; g < a.ng; g += 16) {
-        const uint32_t ccount = cw[g];
-        const uint64_t cell = ((uint64_t)g * a.nb + b) * a.cap;
-        const uint32_t *it = a.items + cell;
-        uint64_t *out = a.bits + cell / 64;
-        for (uint32_t q0 = 0; q0 < ccount; q0 += 512) {
-            uint32_t o[8];
+    // Two cells per wavefront at a time: the first 512 entries of both are
+    // loaded before either is looked up.
+    for (uint32_t g = wv; g < a.ng; g += 32) {
+        const uint32_t gB = g + 16;
+        const uint32_t cA = cw[g], cB = gB < a.ng ? cw[gB] : 0u;
+        const uint64_t cellA = ((uint64_t)g * a.nb + b) * a.cap;
+        const uint64_t cellB = ((uint64_t)gB * a.nb + b) * a.cap;
+        uint32_t oA[8], oB[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t q = 64u * u + (uint32_t)lane;
+            oA[u] = q < cA ? a.items[cellA + q] : 0xffffffffu;
+            oB[u] = q < cB ? a.items[cellB + q] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t cc_ = h ? cB : cA;
+            const uint64_t cell = h ? cellB : cellA;
+            uint64_t *out = a.bits + cell / 64;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const uint32_t q = q0 + 64u * u + (uint32_t)lane;
-                o[u] = q < ccount ? it[q] : 0xffffffffu;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t q = q0 + 64u * u;
-                if (q >= ccount) break;
-                const bool bit = o[u] != 0xffffffffu &&
-                                 ((win[o[u] >> 6] >> (o[u] & 63)) & 1ull);
+                const uint32_t o = h ? oB[u] : oA[u];
+                if (64u * u >= cc_) break;
+                const bool bit = o != 0xffffffffu && ((win[o >> 6] >> (o & 63)) & 1ull);
                 const uint64_t word = ballot64(bit);
-                if (lane == 0) out[q / 64] = word;
+                if (lane == 0) out[u] = word;
+            }
+            for (uint32_t q0 = 512; q0 < cc_; q0 += 64) {
+                const uint32_t q = q0 + (uint32_t)lane;
+                const uint32_t o = q < cc_ ? a.items[cell + q] : 0xffffffffu;
+                const bool bit = o != 0xffffffffu && ((win[o >> 6] >> (o & 63)) & 1ull);
+                const uint64_t word = ballot64(bit);
+                if (lane == 0) out[q0 / 64] = word;
             }
         }
     }
 }
 
 // Merge pass: one workgroup per chunk; each wavefront loads the slots of
-// four output words before looking them up.
+// eight output words before looking them up.
+template <bool ALIGNED>
 __global__ __launch_bounds__(1024) void k_pg_merge(PgArgs a) {
     extern __shared__ uint64_t cells[];               // nb * cap bits
     if (*a.status || *a.flag) return;
@@ -238,22 +304,22 @@ __global__ __launch_bounds__(1024) void k_pg_merge(PgArgs a) {
     const uint64_t total = (uint64_t)a.ns * a.wl;
     const uint64_t w0 = (uint64_t)g * kPgChunkWords;
     const uint64_t w1 = min(w0 + kPgChunkWords, total);
-    WordPos pos;
-    pos.start(w0 + 4u * (uint64_t)wv, a.wl);
-    for (uint64_t wq = w0 + 4u * (uint64_t)wv; wq < w1; wq += 64) {
-        uint32_t sv[4];
-        bool okv[4];
-        WordPos pu = pos;
+    WordPos<ALIGNED> pos;
+    pos.start(w0 + 8u * (uint64_t)wv, a.wl, a.L);
+    for (uint64_t wq = w0 + 8u * (uint64_t)wv; wq < w1; wq += 128) {
+        uint32_t sv[8];
+        bool okv[8];
+        WordPos<ALIGNED> pu = pos;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const uint64_t w = wq + u;
-            okv[u] = w < w1 && pu.c0() + (uint64_t)lane < a.L;
-            sv[u] = okv[u] ? a.slots[pu.k0(a.L) + lane] : 0u;
-            pu.advance(1, a.wl);
+            okv[u] = w < w1 && pu.real(lane, a.L);
+            sv[u] = okv[u] ? (a.slots + uniform64(pu.k0()))[lane] : 0u;
+            pu.advance(1, a.wl, a.L);
         }
-        pos.advance(64, a.wl);
+        pos.advance(128, a.wl, a.L);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             if (wq + u >= w1) break;
             const bool bit = okv[u] && ((cells[sv[u] >> 6] >> (sv[u] & 63)) & 1ull);
             const uint64_t word = ballot64(bit);
@@ -345,18 +411,27 @@ ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
             ssbh_status st;
             const size_t win_lds = (size_t)8 << (kPgWinBits - 6);
             const size_t bucket_lds =
-                ((size_t)3 * ((P.nb + 3) & ~3u) + 16 + 2 * kPgSubWords * 64) * 4;
-            if ((st = ensure_dynamic_lds((const void *)k_pg_bucket, bucket_lds)) != SSBH_OK)
+                (size_t)14 * ((P.nb + 3) & ~3u) + (size_t)kPgSubWords * 64 * 4;
+            const bool aligned = L == 64 * wl;
+            const void *kb = aligned ? (const void *)k_pg_bucket<true>
+                                     : (const void *)k_pg_bucket<false>;
+            const void *km = aligned ? (const void *)k_pg_merge<true>
+                                     : (const void *)k_pg_merge<false>;
+            if ((st = ensure_dynamic_lds(kb, bucket_lds)) != SSBH_OK)
                 return st;
             if ((st = ensure_dynamic_lds((const void *)k_pg_window, win_lds)) != SSBH_OK)
                 return st;
-            if ((st = ensure_dynamic_lds((const void *)k_pg_merge, merge_lds)) != SSBH_OK)
+            if ((st = ensure_dynamic_lds(km, merge_lds)) != SSBH_OK)
                 return st;
             hipLaunchKernelGGL(k_pg_init, dim3(1), dim3(1), 0, stream, a.flag);
             {
                 TimedLaunch timed(ws.timer, "k_pg_bucket", stream);
-                hipLaunchKernelGGL(k_pg_bucket, dim3(P.ng), dim3(1024),
-                                   bucket_lds, stream, a);
+                if (aligned)
+                    hipLaunchKernelGGL(k_pg_bucket<true>, dim3(P.ng), dim3(1024),
+                                       bucket_lds, stream, a);
+                else
+                    hipLaunchKernelGGL(k_pg_bucket<false>, dim3(P.ng), dim3(1024),
+                                       bucket_lds, stream, a);
             }
             {
                 TimedLaunch timed(ws.timer, "k_pg_window", stream);
@@ -365,8 +440,12 @@ ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
             }
             {
                 TimedLaunch timed(ws.timer, "k_pg_merge", stream);
-                hipLaunchKernelGGL(k_pg_merge, dim3(P.ng), dim3(1024), merge_lds,
-                                   stream, a);
+                if (aligned)
+                    hipLaunchKernelGGL(k_pg_merge<true>, dim3(P.ng), dim3(1024),
+                                       merge_lds, stream, a);
+                else
+                    hipLaunchKernelGGL(k_pg_merge<false>, dim3(P.ng), dim3(1024),
+                                       merge_lds, stream, a);
             }
             only_if = a.flag;
             streamed = true;
