@@ -435,7 +435,8 @@ ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
 
 /* Autotuner: run ssbh_hash_batch on the given (real) arguments once per
  * candidate kernel and schedule (bit-sliced VALU schedules, FFT chunks of
- * 64 .. 256 MiB of transforms, and int8 matrix-core schedules when the seed
+ * 64 .. 256 MiB of transforms (two chunks in flight on two streams), and
+ * int8 matrix-core schedules when the seed
  * is shared), `reps` timed runs each with HIP events,
  * and remember the fastest for the shape bucket of these arguments (seed
  * sharing, log2 of n_sub, m_cap and mean sub-block words).  Later calls with

@@ -369,6 +369,9 @@ void ssbh_destroy(ssbh_ctx *ctx) {
     ssbh_serve_shutdown(ctx);
     hipDeviceSynchronize();
     ctx->ws.release();
+    if (ctx->fft_side) hipStreamDestroy(ctx->fft_side);
+    for (hipEvent_t e : ctx->fft_ev)
+        if (e) hipEventDestroy(e);
     delete ctx;
 }
 

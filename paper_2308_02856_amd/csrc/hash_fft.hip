@@ -1132,8 +1132,9 @@ uint64_t fft_length(uint64_t seed_bits) {
 // all-one inputs, against the 1/4 every output is checked for.
 // Transforms of length L in `mib` MiB (at least one).  A chunk's transforms
 // are written by one pass and read by the next: below the 256 MB
-// last-level cache much of that traffic stays on chip (160 MiB measured
-// best at the batched length, 6 % less time per transform than 192 MiB).
+// last-level cache much of that traffic stays on chip.  With two chunks in
+// flight (see FftSchedule::overlap) 96 MiB chunks measured best at the
+// batched length.
 uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib) {
     return (uint32_t)std::max<uint64_t>(1, (mib << 20) / (L * sizeof(double2)));
 }
@@ -1160,7 +1161,9 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
-    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : fft_chunk_of_bytes(L, 160);
+    // Default chunk: 96 MiB of transforms (two chunks in flight fit the
+    // 256 MB last-level cache).
+    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : fft_chunk_of_bytes(L, 96);
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
@@ -1184,7 +1187,26 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     const uint32_t cp = (uint32_t)((pairs + nchunks - 1) / nchunks);
     if (!joint && (st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK)
         return st;
-    if ((st = ws.fft_work.reserve((size_t)cp * L * sizeof(double2))) != SSBH_OK)
+    // Two chunks in flight on two streams (see FftSchedule::overlap).
+    bool fork = s.overlap && !ws.timer && nchunks > 1;
+    if (fork) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) != hipSuccess ||
+            cs != hipStreamCaptureStatusNone) {
+            (void)hipGetLastError();
+            fork = false;
+        }
+    }
+    if (fork && !ctx->fft_side) {
+        if (hipStreamCreateWithFlags(&ctx->fft_side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->fft_ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->fft_ev[1], hipEventDisableTiming) != hipSuccess) {
+            set_error("FFT hash: second stream or events could not be created");
+            return SSBH_E_DEVICE;
+        }
+    }
+    const size_t work_b = (size_t)cp * L * sizeof(double2);
+    if ((st = ws.fft_work.reserve(fork ? 2 * work_b : work_b)) != SSBH_OK)
         return st;
     // Parity words: the regions of q_range, out_cap_bits / 64 + 3 n_sub words.
     if ((st = ws.fft_qbuf.reserve(((q.out_cap_bits >> 6) + 3ull * q.n_sub + 4) *
@@ -1212,16 +1234,16 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     a.rlo = a.wlo[levels - 2];
     a.rhi = a.whi[levels - 2];
     // Middle passes, forward (levels 1, 2) and inverse (2, 1).
-    auto mids = [&](bool inv, uint32_t np) {
+    auto mids = [&](bool inv, uint32_t np, hipStream_t sm) {
         for (int i = 0; i < levels - 2; ++i) {
             const int d = inv ? levels - 2 - i : 1 + i;
             a.lvl = d;
             const uint64_t C = (L >> (6 * d)) >> 6;
             const dim3 g((uint32_t)(C / kN1), 1u << (6 * d), np);
             if (inv)
-                hipLaunchKernelGGL(k_fft_mid<true>, g, dim3(kThreads), 0, stream, a);
+                hipLaunchKernelGGL(k_fft_mid<true>, g, dim3(kThreads), 0, sm, a);
             else
-                hipLaunchKernelGGL(k_fft_mid<false>, g, dim3(kThreads), 0, stream, a);
+                hipLaunchKernelGGL(k_fft_mid<false>, g, dim3(kThreads), 0, sm, a);
         }
     };
     a.out = q.out;
@@ -1238,40 +1260,56 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         TimedLaunch timed(ws.timer, "k_fft_spectrum", stream);
         hipLaunchKernelGGL((k_fft_cols<true, false>), dim3(tiles, 1),
                            dim3(kThreads), 0, stream, a);
-        mids(false, 1);
+        mids(false, 1, stream);
         rows(a, 1, true, stream);
     };
     if (!joint) spectrum(0);
-    for (uint64_t p0 = 0; p0 < pairs; p0 += cp) {
+    double2 *work0 = ws.fft_work.as<double2>();
+    if (fork) {
+        // The second stream starts after everything queued so far (the plan,
+        // the output fill, the spectrum).
+        SSBH_CHECK_HIP(hipEventRecord(ctx->fft_ev[0], stream));
+        SSBH_CHECK_HIP(hipStreamWaitEvent(ctx->fft_side, ctx->fft_ev[0], 0));
+    }
+    uint64_t ci = 0;
+    for (uint64_t p0 = 0; p0 < pairs; p0 += cp, ++ci) {
         const uint32_t np = (uint32_t)std::min<uint64_t>(cp, pairs - p0);
+        const bool odd = fork && (ci & 1);
+        hipStream_t sc = odd ? ctx->fft_side : stream;
         a.pair0 = (uint32_t)p0;
+        a.work = odd ? work0 + (size_t)cp * L : work0;
         if (joint)
             launch_timed(&ws, "k_fft_cols", k_fft_cols<false, false, true>,
-                         dim3(tiles, np), dim3(kThreads), stream, a);
+                         dim3(tiles, np), dim3(kThreads), sc, a);
         else if (per == 4)
             launch_timed(&ws, "k_fft_cols", k_fft_cols<false, true>, dim3(tiles, np),
-                         dim3(kThreads), stream, a);
+                         dim3(kThreads), sc, a);
         else
             launch_timed(&ws, "k_fft_cols", k_fft_cols<false, false>, dim3(tiles, np),
-                         dim3(kThreads), stream, a);
+                         dim3(kThreads), sc, a);
         if (levels > 2) {
-            TimedLaunch timed(ws.timer, "k_fft_mid", stream);
-            mids(false, np);
+            TimedLaunch timed(ws.timer, "k_fft_mid", sc);
+            mids(false, np, sc);
         }
-        rows(a, np, false, stream, &ws, joint);
+        rows(a, np, false, sc, &ws, joint);
         if (levels > 2) {
-            TimedLaunch timed(ws.timer, "k_fft_mid", stream);
-            mids(true, np);
+            TimedLaunch timed(ws.timer, "k_fft_mid", sc);
+            mids(true, np, sc);
         }
         if (joint)
             launch_timed(&ws, "k_fft_out", k_fft_out<false, true>, dim3(tiles, np),
-                         dim3(kThreads), stream, a);
+                         dim3(kThreads), sc, a);
         else if (per == 4)
             launch_timed(&ws, "k_fft_out", k_fft_out<true>, dim3(tiles, np),
-                         dim3(kThreads), stream, a);
+                         dim3(kThreads), sc, a);
         else
             launch_timed(&ws, "k_fft_out", k_fft_out<false>, dim3(tiles, np),
-                         dim3(kThreads), stream, a);
+                         dim3(kThreads), sc, a);
+    }
+    if (fork) {
+        // The emit pass (and the caller's later work) after both streams.
+        SSBH_CHECK_HIP(hipEventRecord(ctx->fft_ev[1], ctx->fft_side));
+        SSBH_CHECK_HIP(hipStreamWaitEvent(stream, ctx->fft_ev[1], 0));
     }
     {
         // Every sub-block's rows from the parity words, 2048 output words per

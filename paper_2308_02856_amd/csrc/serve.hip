@@ -192,6 +192,7 @@ static ssbh_status plan_job(const ssbh_ctx *ctx, const ssbh_job &j,
         // the budget stays modest, so several jobs fit at once.
         const uint64_t L = fft_length(p.stride);
         p.fsched.chunk_pairs = fft_chunk_of_bytes(L, kServeFftChunkMiB);
+        p.fsched.overlap = false;
         const uint64_t cp = std::min<uint64_t>(p.fsched.chunk_pairs, j.n_sub);
         p.fft_work_b = (size_t)cp * L * 16;
         p.fft_qbuf_b = (size_t)(q.out_cap_bits / 64 + 3ull * j.n_sub + 4) * 8;

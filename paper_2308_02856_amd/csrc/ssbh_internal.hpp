@@ -113,6 +113,11 @@ struct MfmaSchedule {
 // FFT hash schedule: sub-block pairs transformed per chunk (0 = default).
 struct FftSchedule {
     uint32_t chunk_pairs = 0;
+    // Chunks alternate between the caller's stream and a second stream of
+    // the context (two work buffers), so that one chunk's passes run while
+    // the other's kernel boundaries drain.  Off under graph capture, with
+    // per-kernel timing and for serving jobs (their own streams overlap).
+    bool overlap = true;
 };
 constexpr uint64_t kMaxFftLength = 1ull << 31;   // transform length limit
 
@@ -138,6 +143,8 @@ struct ssbh_ctx {
     uint32_t forced_fft_chunk = 0;
     int forced_fft_pack = 0;       // 0 = library choice, 1 / 2 sub-blocks per part
     int forced_scatter = 0;        // 0 = library choice, 1 = one wave per segment
+    hipStream_t fft_side = nullptr;   // second stream of the FFT hash chunks
+    hipEvent_t fft_ev[2] = {nullptr, nullptr};   // fork and join
 };
 
 namespace ssbh {

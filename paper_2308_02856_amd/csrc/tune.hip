@@ -50,11 +50,12 @@ std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
     }
     const uint64_t span = q.stride ? q.stride : q.seed_bits;
     if (fft_length(span) <= kMaxFftLength) {
-        // Chunks of 64 .. 256 MiB of transforms (below, around and above the
-        // last-level cache), as transform counts at this length.
+        // Chunks of 64 .. 256 MiB of transforms (two are in flight at once:
+        // below, around and above the last-level cache), as transform counts
+        // at this length.
         const uint64_t L = fft_length(span);
         std::vector<uint32_t> cps;
-        for (uint64_t mib : {64ull, 128ull, 160ull, 192ull, 256ull}) {
+        for (uint64_t mib : {64ull, 96ull, 128ull, 160ull, 192ull, 256ull}) {
             const uint32_t cp = fft_chunk_of_bytes(L, mib);
             if (std::find(cps.begin(), cps.end(), cp) == cps.end()) cps.push_back(cp);
         }
