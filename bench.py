@@ -236,6 +236,29 @@ def run_batched(ctx, ssbh, args):
     return res
 
 
+def fft_hash_roofline(schedule: str, ns: int, n_bits: int, out_bits: int,
+                      hash_ms: float, shared: bool, launches: int) -> dict:
+    """The whole FFT hash (all passes, two chunks in flight) against HBM.
+    Algorithmic bytes per hash: every transform is written by the column
+    pass, read and written by the row pass and read by the output pass
+    (64 L bytes); with a shared seed the spectrum is built once (48 L) and
+    read by every row-pass launch (16 L each); the packed input bits are
+    read once and the output bits are written twice and read once (parity
+    words, then their places)."""
+    L = int(schedule.split(":L")[1])
+    per = int(schedule.split(":x")[1].split(":")[0])
+    transforms = (ns + per - 1) // per
+    b = 64 * L * transforms + n_bits // 8 + 3 * out_bits // 8
+    if shared:
+        b += 48 * L + 16 * L * launches
+    achieved = b / (hash_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernels": "k_fft_cols + k_fft_rows + k_fft_out "
+            "+ k_fft_emit (+ spectrum)", "schedule": schedule,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_hash": int(b), "hash_ms": round(hash_ms, 4)}
+
+
 def sampling_roofline(res) -> dict:
     """Sampling (a1-a3) against HBM: per call it must read the N input
     bits once and write the N bits of the sub-block buffer once (2 N / 8
@@ -343,6 +366,8 @@ def run_batched_independent(ctx, ssbh, args, res):
             "avg_launch_us": round(ms * 1e3 / n_l, 2),
             "algorithmic_bytes_per_launch": int(total_bytes / n_l)}
         item["kernel_avg_us"] = kernel_avgs(hk)
+        item["roofline_hash"] = fft_hash_roofline(schedule, ns, res["n"],
+                                                  out_cap, hash_ms, False, 0)
     del seed, out, outv
     torch.cuda.empty_cache()
     return item
@@ -1036,6 +1061,10 @@ def main() -> int:
         "sifted_sample_ms": round(res["sift_ms"], 4),
         "bit_products_per_s": float(f"{res['work'] / (res['hash_ms'] * 1e-3):.4g}"),
         "roofline": roof,
+        "roofline_hash": (fft_hash_roofline(
+            res["schedule"], res["ns"], res["n"], int(res["mlen"].sum()),
+            res["hash_ms"], True, hk["k_fft_rows"][0] // res["timed_calls"])
+            if res["schedule"].startswith("fft") else None),
         "roofline_sampling": sampling_roofline(res),
         "kernel_avg_us": {**kernel_avgs(res["sample_kernels"]),
                           **kernel_avgs(res["hash_kernels"])},
