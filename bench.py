@@ -634,6 +634,33 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     }
 
 
+def run_gather(ctx, ssbh, args):
+    """Permutation sampling of the contraction workload alone (the keyed
+    permutation of 2^30 entries built once, then `steps` gathers), for
+    profiler passes over the gather kernels."""
+    import torch
+    from workloads import config, uniform_bits
+    c = config("contraction")
+    n, ns = c["n_bits"], c["n_sub"]
+    d_in = to_dev(uniform_bits(n, c["input_seed"]))
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.permutation(c["perm_key"], n, out=perm)
+    sub = torch.empty(n // 64, dtype=torch.int64, device="cuda")
+    ln = torch.empty(ns, dtype=torch.int64, device="cuda")
+    wo = torch.empty(ns, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def sample():
+        ctx.sample(d_in, n, ns, ssbh.SAMPLE_PERMUTE, assign=perm, sub=sub,
+                   sub_capacity=n // 64, length=ln, word_off=wo, status=st)
+
+    ms = time_events(sample, max(1, args.steps))
+    torch.cuda.synchronize()
+    return {"mode": "gather", "n_bits": n, "n_sub": ns,
+            "gather_ms": round(float(np.mean(ms)), 3),
+            "status": int(st.item())}
+
+
 # -------------------------------------------------------------------- small
 
 def run_small(ctx, ssbh, args):
@@ -929,7 +956,7 @@ def main() -> int:
     ap.add_argument("--serve-budget-mib", type=int, default=512)
     ap.add_argument("--mode", default="full",
                     choices=["full", "hash-batched", "hash-independent",
-                             "hash-single", "copy",
+                             "hash-single", "copy", "gather",
                              "contraction", "small", "serving", "table1"],
                     help="full = the benchmark line; the others run one "
                          "part only, for profiler passes")
@@ -969,6 +996,9 @@ def main() -> int:
                           "ms_fft": single["ms_fft"],
                           "fft_equals_valu": single["fft_equals_valu"]}),
               flush=True)
+        return 0
+    if args.mode == "gather":
+        print(json.dumps(run_gather(ctx, ssbh, args)), flush=True)
         return 0
     if args.mode == "contraction":
         print(json.dumps(run_contraction(ctx, ssbh, args, peak)), flush=True)
