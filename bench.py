@@ -11,8 +11,11 @@ compared with (bit-sliced kernel and FFT, the faster one counts), the contractio
 int8 matrix cores against the bit-sliced kernel), the small workload through a
 captured HIP graph, the five input/output sizes of the paper's Table I (one
 block and 20 sub-blocks with independent seeds, both by the FFT hash), the serving stream (p50/p99 latency, sustained Gbit/s),
-the roofline of the dominant kernel (timed with HIP events on its stream) and
-the CPU oracle timed on a bounded sample.
+rooflines (the hash's row pass per launch, timed with HIP events on its
+stream; the whole FFT hash; the sampling kernels against HBM) and the CPU
+oracle timed on a bounded sample.  The step's largest kernel is the sampling
+scatter (0.64 ms); its roofline entry shows how far below HBM its LDS work
+keeps it.
 """
 
 from __future__ import annotations
@@ -1025,7 +1028,7 @@ def main() -> int:
 
     hk = res["hash_kernels"]
     if res["schedule"].startswith("fft"):
-        # Dominant kernel: the row pass.  Per launch it reads and writes the
+        # The hash's largest pass: the row pass.  Per launch it reads and writes the
         # transforms of its chunk (L complex doubles per transform each way;
         # a transform holds 2 or 4 sub-blocks, "x<k>" in the schedule) and
         # reads the seed spectrum once.
