@@ -458,3 +458,87 @@ def test_every_transform_length_independent(ctx, orc, L):
                                    seed_bits, j * S, M, r)
         k = int(ooff[j]) + r
         assert ((int(got[k >> 6]) >> (k & 63)) & 1) == want, (j, r)
+
+
+def test_two_streams_of_chunks_on_a_caller_stream(ctx, orc):
+    """Chunks of one transform each alternate between the caller's stream and
+    the library's second stream: two calls back to back on a non-default
+    torch stream, then the caller's own copy of the output on that stream
+    (no host wait between), equal the oracle and the one-chunk result."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    n, ns = 300001, 24
+    a = bernoulli_bits(n, 0.4, 93)
+    key = 0x515
+    sub, ln, wo, st = ctx.sample(to_dev(a), n, ns, ssbh.SAMPLE_IID, key=key)
+    osub, oln, owo, _ = orc.sample(a, n, ns, orc.SAMPLE_IID, key=key)
+    om = orc.out_lengths(oln, orc.OUT_RATIO, 2, 5)
+    cap = int(om.max())
+    seed_bits = int(oln.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 94)
+    want, wtot = orc.hash_batch(osub, oln, owo, om, seed, seed_bits, 0, cap)
+    d_seed = to_dev(seed)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    kw = dict(out_rule=ssbh.OUT_RATIO, out_a=2, out_b=5, kernel=ssbh.K_FFT)
+    ctx.set_fft_schedule(1)
+    try:
+        with torch.cuda.stream(side):
+            o1, t1, s1 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns, d_seed,
+                                        seed_bits, cap, **kw)
+            o2, t2, s2 = ctx.hash_batch(sub, sub.numel(), ln, wo, ns, d_seed,
+                                        seed_bits, cap, **kw)
+            c1, c2 = o1.clone(), o2.clone()
+        side.synchronize()
+    finally:
+        ctx.set_fft_schedule(0)
+    assert int(s1.item()) == 0 and int(s2.item()) == 0
+    assert int(t1.item()) == wtot and int(t2.item()) == wtot
+    for c in (c1, c2):
+        assert np.array_equal(to_host(c)[: want.size], want)
+    one, _ = fft_hash(ctx, sub, ln, wo, ns, d_seed, seed_bits, cap, chunk=64,
+                      out_rule=ssbh.OUT_RATIO, out_a=2, out_b=5)
+    assert np.array_equal(one[: want.size], want)
+
+
+def test_fft_graph_pipeline_many_chunks(ctx, orc):
+    """A captured pipeline with one transform per chunk (the capture keeps
+    every chunk on the pipeline's stream): replays equal the oracle."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    n, ns = (1 << 18) + 5, 12
+    a = bernoulli_bits(n, 0.5, 95)
+    key = 0x9A
+    osub, oln, owo, _ = orc.sample(a, n, ns, orc.SAMPLE_IID, key=key)
+    om = orc.out_lengths(oln, orc.OUT_RATIO, 1, 3)
+    cap = int(om.max())
+    seed_bits = int(oln.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 96)
+    want, wtot = orc.hash_batch(osub, oln, owo, om, seed, seed_bits, 0, cap)
+    sub_cap = (n + 63) // 64 + ns
+    sub = torch.empty(sub_cap, dtype=torch.int64, device="cuda")
+    ln = torch.empty(ns, dtype=torch.int64, device="cuda")
+    wo = torch.empty(ns, dtype=torch.int64, device="cuda")
+    out = torch.empty((wtot + 63) // 64, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.set_fft_schedule(1)
+    try:
+        pipe = ctx.pipeline(d_in=to_dev(a), n_bits=n, n_sub=ns,
+                            mode=ssbh.SAMPLE_IID, sample_key=key, d_sub=sub,
+                            sub_capacity_words=sub_cap, d_len=ln,
+                            d_word_off=wo, out_rule=ssbh.OUT_RATIO, out_a=1,
+                            out_b=3, d_seed=to_dev(seed), seed_bits=seed_bits,
+                            m_cap=cap, kernel=ssbh.K_FFT, d_out=out,
+                            out_capacity_bits=wtot, d_out_total_bits=tot,
+                            d_status=st)
+    finally:
+        ctx.set_fft_schedule(0)
+    for _ in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        pipe.launch()
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0 and int(tot.item()) == wtot
+        assert np.array_equal(to_host(out)[: want.size], want)
+    pipe.close()
