@@ -175,16 +175,17 @@ void k_pg_bucket(PgArgs a) {
             tot = 0;
             for (int v = 0; v < 16; ++v) tot += part[v];
             // A window's run at stage [run, run + cl) becomes cell ranks
-            // [cc, cc + cl): slot = b cap + cc + (x - run).  A run that would
-            // pass the capacity marks the chunk overflowed (the direct gather
-            // then writes the output) and is not stored.
+            // [cc, cc + cl): slot = b cap + cc + (x - run), below nb cap.  A
+            // run that would pass the capacity marks the chunk overflowed
+            // (the direct gather then writes the output); its db puts every
+            // slot at nb cap or above, so nothing of it is stored.
             for (uint32_t b = (uint32_t)t * 4u; b < min((uint32_t)t * 4u + 4u, a.nb); ++b) {
                 const uint32_t c = cl[b], f = cc[b];
                 lc[b] = run;
                 if (f + c <= a.cap) {
-                    db[b] = b * a.cap + f - run;
+                    db[b] = b * a.cap + f - run;       // mod 2^32; + x >= run
                 } else {
-                    db[b] = 0xffffffffu;
+                    db[b] = a.nb * a.cap - run;
                     over = true;
                 }
                 run += c;
@@ -209,8 +210,8 @@ void k_pg_bucket(PgArgs a) {
                     const uint32_t b = pv[i] >> kPgWinBits;
                     const uint32_t x = atomicAdd(&lc[b], 1u);
                     stage[x] = pv[i];
-                    const uint32_t d = db[b];
-                    slot = d != 0xffffffffu ? d + x : 0u;
+                    const uint32_t d = db[b] + x;
+                    slot = d < a.nb * a.cap ? d : 0u;
                 }
                 (a.slots + uniform64(k0))[lane] = slot;
             }
@@ -220,8 +221,8 @@ void k_pg_bucket(PgArgs a) {
         //    both); 5. cell fills.
         for (uint32_t x = (uint32_t)t; x < tot; x += 1024) {
             const uint32_t p = stage[x];
-            const uint32_t d = db[p >> kPgWinBits];
-            if (d != 0xffffffffu) cell[d + x] = p & ((1u << kPgWinBits) - 1u);
+            const uint32_t d = db[p >> kPgWinBits] + x;
+            if (d < a.nb * a.cap) cell[d] = p & ((1u << kPgWinBits) - 1u);
         }
         __syncthreads();
         for (uint32_t b = t; b < a.nb; b += 1024) {
