@@ -102,3 +102,20 @@ def test_streamed_equals_direct_large(ctx):
     s1, _, _, st1 = sample(ctx, d_a, n, ns, perm=perm, path=1)
     assert int(st0.item()) == 0 and int(st1.item()) == 0
     assert torch.equal(s0[: n // 64], s1[: n // 64])
+
+
+def test_one_overfilled_chunk_falls_back(ctx, orc):
+    """A permutation that is random except for its first chunk, which maps
+    into the first window only: that one cell overflows, the whole gather
+    falls back to the direct one, and the output is still the oracle's."""
+    n, ns = 1 << 26, 32
+    a = uniform_bits(n, 268)
+    rng = np.random.default_rng(269)
+    head = 1 << 18
+    perm = np.concatenate([rng.permutation(head),
+                           head + rng.permutation(n - head)]).astype(np.uint32)
+    sub, _, _, st = sample(ctx, to_dev(a), n, ns, perm=to_dev_u32(perm))
+    assert int(st.item()) == 0
+    osub, _, _, _ = orc.sample(a, n, ns, orc.SAMPLE_PERMUTE, assign=perm)
+    got = to_host(sub)[: osub.size]
+    assert np.array_equal(got, osub), first_diff(got, osub)
