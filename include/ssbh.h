@@ -151,7 +151,13 @@ int ssbh_num_cus(const ssbh_ctx *ctx);
  *                or, when d_assign is NULL, the keyed permutation of
  *                sample_key built on the device as ssbh_permutation does
  *                (scratch of about 16 bytes per input bit, held by the
- *                context).
+ *                context).  From 2^26 input bits the gather streams in
+ *                three passes through about 14 bytes of context scratch per
+ *                input bit (cells of window offsets, a slot per output bit,
+ *                looked-up bits); when that cannot be reserved, or when the
+ *                permutation overfills a cell (far outside a random
+ *                permutation's spread), each output bit is read directly.
+ *                The result is the same either way.
  *  l_ub          L_S^UB; 0 disables the abort rule.  If some n_j > l_ub,
  *                *d_status = SSBH_E_ABORT_OVERSIZE.
  *  d_sub         output sub-blocks, sub_capacity_words words.  Needs
@@ -501,10 +507,12 @@ ssbh_status ssbh_set_timing(ssbh_ctx *ctx, int on);
  * "name launches total_ms", then forget them (truncated to len). */
 ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len);
 
-/* Scatter kernel of the i.i.d. / explicit sampling: path 0 = library
- * choice (a workgroup of four wavefronts per segment when its LDS tables fit
- * in 64 KiB), 1 = one wavefront per segment.  The sub-blocks do not depend
- * on it. */
+/* Placement kernels of the sampling: path 0 = library choice (i.i.d. /
+ * explicit: a workgroup of four wavefronts per segment when its LDS tables
+ * fit in 64 KiB; permutation: the streaming gather from 2^26 input bits),
+ * 1 = the one-wavefront kernels (one wavefront per segment; the direct
+ * gather, one random input read per output bit).  The sub-blocks do not
+ * depend on it. */
 ssbh_status ssbh_set_sample_path(ssbh_ctx *ctx, int path);
 
 /* Force the FFT hash's chunk: transforms per pass (each holds two or four

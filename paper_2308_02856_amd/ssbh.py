@@ -440,7 +440,8 @@ class Context:
                                             int(ksplit)))
 
     def set_sample_path(self, path: int = 0):
-        """Scatter kernel of the sampling: 0 = library, 1 = one wave/segment."""
+        """Placement kernels of the sampling: 0 = library choice, 1 = one
+        wavefront per segment / the direct permutation gather."""
         _check(lib().ssbh_set_sample_path(self._h, int(path)))
 
     def set_timing(self, on: bool = True):
