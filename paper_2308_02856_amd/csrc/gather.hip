@@ -48,10 +48,6 @@ struct PgArgs {
 
 __global__ void k_pg_init(uint32_t *flag) { *flag = 0u; }
 
-// Output word w of the sub-block buffer holds bits k = j L + 64 ww + lane
-// for 64 ww + lane < L (w = j wl + ww).  A wavefront walks words at a fixed
-// stride, so (j, ww) advance without a division; all of it is the same for
-// the whole wavefront and runs on the scalar unit.
 // A wavefront-uniform 64-bit value, marked as such so that addresses built
 // from it stay in scalar registers (one vector offset serves every load).
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -60,6 +56,10 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Output word w of the sub-block buffer holds bits k = j L + 64 ww + lane
+// for 64 ww + lane < L (w = j wl + ww).  A wavefront walks words at a fixed
+// stride, so (j, ww) advance without a division; all of it is the same for
+// the whole wavefront and runs on the scalar unit.
 template <bool ALIGNED>
 struct WordPos {
     uint64_t kw0, cw0;       // k of the word's bit 0, and 64 ww
