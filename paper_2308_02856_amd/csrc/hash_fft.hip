@@ -1161,9 +1161,15 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     }
     ssbh_status st = plan_only(ctx, ws, q, stream);
     if (st != SSBH_OK) return st;
-    // Default chunk: 96 MiB of transforms (two chunks in flight fit the
-    // 256 MB last-level cache).
-    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs : fft_chunk_of_bytes(L, 96);
+    // Two chunks in flight on two streams (see FftSchedule::overlap).  The
+    // second stream and its events belong to the context: only calls on the
+    // context's own workspace, which hold its lock, use them (a pipeline's
+    // eager run and serving jobs have workspaces of their own).
+    const bool may_fork = s.overlap && &ws == &ctx->ws && !ws.timer;
+    // Default chunk: 96 MiB of transforms when two are in flight (both fit
+    // the 256 MB last-level cache), else 160 MiB.
+    uint32_t chunk = s.chunk_pairs ? s.chunk_pairs
+                                   : fft_chunk_of_bytes(L, may_fork ? 96 : 160);
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
@@ -1187,8 +1193,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     const uint32_t cp = (uint32_t)((pairs + nchunks - 1) / nchunks);
     if (!joint && (st = ws.fft_spec.reserve(L * sizeof(double2))) != SSBH_OK)
         return st;
-    // Two chunks in flight on two streams (see FftSchedule::overlap).
-    bool fork = s.overlap && !ws.timer && nchunks > 1;
+    bool fork = may_fork && nchunks > 1;
     if (fork) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(stream, &cs) != hipSuccess ||

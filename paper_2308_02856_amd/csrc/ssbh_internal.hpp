@@ -115,8 +115,9 @@ struct FftSchedule {
     uint32_t chunk_pairs = 0;
     // Chunks alternate between the caller's stream and a second stream of
     // the context (two work buffers), so that one chunk's passes run while
-    // the other's kernel boundaries drain.  Off under graph capture, with
-    // per-kernel timing and for serving jobs (their own streams overlap).
+    // the other's kernel boundaries drain.  Only for calls on the context's
+    // own workspace; off under graph capture, with per-kernel timing and for
+    // serving jobs (their own streams overlap).
     bool overlap = true;
 };
 constexpr uint64_t kMaxFftLength = 1ull << 31;   // transform length limit
