@@ -151,7 +151,9 @@ int ssbh_num_cus(const ssbh_ctx *ctx);
  *                or, when d_assign is NULL, the keyed permutation of
  *                sample_key built on the device as ssbh_permutation does
  *                (scratch of about 16 bytes per input bit, held by the
- *                context).  From 2^26 input bits the gather streams in
+ *                context, which keeps the permutation of the last
+ *                (sample_key, n_bits) and builds it again only for another
+ *                pair).  From 2^26 input bits the gather streams in
  *                three passes through about 14 bytes of context scratch per
  *                input bit (cells of window offsets, a slot per output bit,
  *                looked-up bits); when that cannot be reserved, or when the

@@ -150,6 +150,7 @@ void Workspace::release() {
     fft_qbuf.release();
     perm_tmp.release();
     perm_pi.release();
+    perm_ptr = nullptr;
     pg.release();
     delete timer;
     timer = nullptr;

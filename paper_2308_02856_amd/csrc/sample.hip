@@ -809,12 +809,21 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
                        (unsigned long long)sub_cap,
                        (unsigned long long)((uint64_t)ns * wl));
         if (!d_assign && n) {
-            // The keyed permutation of sample_key, built in the workspace.
+            // The keyed permutation of sample_key, built in the workspace
+            // unless it already holds that of (sample_key, n): it depends on
+            // nothing else.
             ssbh_status st = ws.perm_pi.reserve((size_t)n * sizeof(uint32_t));
             if (st != SSBH_OK) return st;
-            st = launch_permutation(ctx, ws.perm_tmp, key, n,
-                                    ws.perm_pi.as<uint32_t>(), stream);
-            if (st != SSBH_OK) return st;
+            if (ws.perm_ptr != ws.perm_pi.ptr || ws.perm_key != key ||
+                ws.perm_n != n) {
+                ws.perm_ptr = nullptr;
+                st = launch_permutation(ctx, ws.perm_tmp, key, n,
+                                        ws.perm_pi.as<uint32_t>(), stream);
+                if (st != SSBH_OK) return st;
+                ws.perm_ptr = ws.perm_pi.ptr;
+                ws.perm_key = key;
+                ws.perm_n = n;
+            }
             d_assign = ws.perm_pi.as<uint32_t>();
         }
         hipLaunchKernelGGL(k_perm_meta, dim3((ns + 255) / 256), dim3(256), 0,

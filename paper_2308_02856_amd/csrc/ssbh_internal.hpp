@@ -86,6 +86,10 @@ struct Workspace {
     DevBuf fft_qbuf;   // FFT hash: parity words in transform order
     DevBuf perm_tmp;   // keyed permutation: counts, groups, chain links
     DevBuf perm_pi;    // keyed permutation built for permutation sampling
+    // perm_pi holds the keyed permutation of (perm_key, perm_n) while
+    // perm_ptr == perm_pi.ptr (a grown buffer starts empty).
+    uint64_t perm_key = 0, perm_n = 0;
+    const void *perm_ptr = nullptr;
     DevBuf pg;         // permutation gather: cells, slots, looked-up bits
     char last_schedule[48] = "";   // kernel and schedule of the last hash
     KernelTimer *timer = nullptr;  // per-kernel event timing (optional)

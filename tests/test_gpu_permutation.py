@@ -92,3 +92,22 @@ def test_keyed_permute_split_matches_oracle(ctx, orc, n, ns):
     assert np.array_equal(got, osub), first_diff(got, osub)
     assert np.array_equal(to_host(ln)[:ns], oln)
     assert np.array_equal(to_host(wo)[:ns], owo)
+
+
+def test_keyed_split_reuses_and_rebuilds_its_permutation(ctx, orc):
+    """The context keeps the keyed permutation of the last (key, n): the
+    same key twice, then another key, then another length, each equal to
+    the oracle's split of the oracle's permutation."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    for n, ns, key in [(1 << 16, 8, 0x11), (1 << 16, 8, 0x11), (1 << 16, 8, 0x12),
+                       ((1 << 16) + 8, 8, 0x12), (1 << 16, 8, 0x11)]:
+        a = uniform_bits(n, 70 + n % 7 + key)
+        sub, ln, wo, st = ctx.sample(to_dev(a), n, ns, ssbh.SAMPLE_PERMUTE,
+                                     key=key)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        osub, _, _, _ = orc.sample(a, n, ns, orc.SAMPLE_PERMUTE,
+                                   assign=orc.permutation(n, key))
+        got = to_host(sub)[: osub.size]
+        assert np.array_equal(got, osub), (n, key, first_diff(got, osub))
