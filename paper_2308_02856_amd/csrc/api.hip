@@ -152,6 +152,7 @@ void Workspace::release() {
     perm_pi.release();
     perm_ptr = nullptr;
     pg.release();
+    pg_ptr = nullptr;
     delete timer;
     timer = nullptr;
 }

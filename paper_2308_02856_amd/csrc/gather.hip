@@ -17,6 +17,8 @@
 // that overfills a cell (far outside the binomial spread of a random one)
 // sets a flag, the window and merge passes then do nothing and the direct
 // gather, which runs after them only when the flag is set, writes the output.
+// The bucket pass depends on pi alone: for the context's keyed permutation
+// its result (and flag) is kept for later calls with the same key and split.
 #include <algorithm>
 
 #include "ssbh_internal.hpp"
@@ -390,7 +392,7 @@ ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
                                const uint64_t *d_in, uint64_t n,
                                const uint32_t *d_perm, uint32_t ns, uint64_t L,
                                uint64_t wl, uint64_t *d_sub, int32_t *d_status,
-                               hipStream_t stream) {
+                               hipStream_t stream, bool keyed, uint64_t key) {
     const uint64_t total = (uint64_t)ns * wl;
     if (!total) return SSBH_OK;
     const uint32_t *only_if = nullptr;
@@ -424,8 +426,15 @@ ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
                 return st;
             if ((st = ensure_dynamic_lds(km, merge_lds)) != SSBH_OK)
                 return st;
-            hipLaunchKernelGGL(k_pg_init, dim3(1), dim3(1), 0, stream, a.flag);
-            {
+            // The cells, slots and overflow flag depend on pi alone: for the
+            // context's keyed permutation they stay valid while the key, the
+            // split and the scratch buffer do (the caller's own pi may
+            // change between calls, so it is always bucketed again).
+            const bool reuse = keyed && ws.pg_ptr == ws.pg.ptr &&
+                               ws.pg_key == key && ws.pg_n == n && ws.pg_ns == ns;
+            if (!reuse) {
+                ws.pg_ptr = nullptr;
+                hipLaunchKernelGGL(k_pg_init, dim3(1), dim3(1), 0, stream, a.flag);
                 TimedLaunch timed(ws.timer, "k_pg_bucket", stream);
                 if (aligned)
                     hipLaunchKernelGGL(k_pg_bucket<true>, dim3(P.ng), dim3(1024),
@@ -433,6 +442,12 @@ ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
                 else
                     hipLaunchKernelGGL(k_pg_bucket<false>, dim3(P.ng), dim3(1024),
                                        bucket_lds, stream, a);
+                if (keyed) {
+                    ws.pg_ptr = ws.pg.ptr;
+                    ws.pg_key = key;
+                    ws.pg_n = n;
+                    ws.pg_ns = ns;
+                }
             }
             {
                 TimedLaunch timed(ws.timer, "k_pg_window", stream);

@@ -808,6 +808,9 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
             SSBH_INVAL("sub_capacity_words %llu < %llu",
                        (unsigned long long)sub_cap,
                        (unsigned long long)((uint64_t)ns * wl));
+        // The keyed path may keep the gather's bucketing, unless this call
+        // aborts (the bucket pass then does nothing).
+        const bool keyed = !d_assign && n && !(l_ub && L > l_ub);
         if (!d_assign && n) {
             // The keyed permutation of sample_key, built in the workspace
             // unless it already holds that of (sample_key, n): it depends on
@@ -830,7 +833,7 @@ ssbh_status launch_sample(ssbh_ctx *ctx, Workspace &ws, const uint64_t *d_in,
                            stream, ns, L, wl, l_ub, d_len, d_woff, d_status);
         SSBH_CHECK_HIP(hipGetLastError());
         return launch_perm_gather(ctx, ws, d_in, n, d_assign, ns, L, wl, d_sub,
-                                  d_status, stream);
+                                  d_status, stream, keyed, key);
     }
     if (mode != SSBH_SAMPLE_IID && mode != SSBH_SAMPLE_EXPLICIT)
         SSBH_INVAL("unknown sampling mode %u", mode);

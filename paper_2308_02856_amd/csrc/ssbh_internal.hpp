@@ -91,6 +91,11 @@ struct Workspace {
     uint64_t perm_key = 0, perm_n = 0;
     const void *perm_ptr = nullptr;
     DevBuf pg;         // permutation gather: cells, slots, looked-up bits
+    // pg holds the bucketing of the keyed permutation (pg_key, pg_n) split
+    // into pg_ns sub-blocks while pg_ptr == pg.ptr.
+    uint64_t pg_key = 0, pg_n = 0;
+    uint32_t pg_ns = 0;
+    const void *pg_ptr = nullptr;
     char last_schedule[48] = "";   // kernel and schedule of the last hash
     KernelTimer *timer = nullptr;  // per-kernel event timing (optional)
     void release();
@@ -212,11 +217,13 @@ ssbh_status launch_permutation(ssbh_ctx *ctx, DevBuf &scratch, uint64_t key,
 size_t permutation_scratch(uint64_t n);
 
 // Permutation sampling's gather B[k] = A[pi[k]] (gather.hip).
+// keyed: d_perm is the workspace's keyed permutation of `key`, so that the
+// gather's bucketing may be kept for the next call with the same key.
 ssbh_status launch_perm_gather(ssbh_ctx *ctx, Workspace &ws,
                                const uint64_t *d_in, uint64_t n,
                                const uint32_t *d_perm, uint32_t ns, uint64_t L,
                                uint64_t wl, uint64_t *d_sub, int32_t *d_status,
-                               hipStream_t stream);
+                               hipStream_t stream, bool keyed, uint64_t key);
 
 // Fused two-kernel path of a graph pipeline for small permutation-split jobs
 // with equal sub-blocks and 64-bit aligned outputs (small.hip).

@@ -119,3 +119,29 @@ def test_one_overfilled_chunk_falls_back(ctx, orc):
     osub, _, _, _ = orc.sample(a, n, ns, orc.SAMPLE_PERMUTE, assign=perm)
     got = to_host(sub)[: osub.size]
     assert np.array_equal(got, osub), first_diff(got, osub)
+
+
+def test_keyed_gather_keeps_its_bucketing(ctx, orc):
+    """The streaming gather of the context's keyed permutation keeps its
+    bucketing for the next call with the same key and split: a second call
+    on new input bits, another key, an aborting call (whose bucket pass does
+    nothing, so nothing may be kept) and the first key again all give the
+    oracle's sub-blocks."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    n, ns = 1 << 26, 64
+    perms = {k: orc.permutation(n, k) for k in (0x71, 0x72)}
+    for key, seed, l_ub in [(0x71, 1, 0), (0x71, 2, 0), (0x72, 3, 0),
+                            (0x71, 4, 1000), (0x71, 5, 0)]:
+        a = uniform_bits(n, 280 + seed)
+        sub, ln, wo, st = ctx.sample(to_dev(a), n, ns, ssbh.SAMPLE_PERMUTE,
+                                     key=key, l_ub=l_ub)
+        torch.cuda.synchronize()
+        if l_ub:
+            assert int(st.item()) == ssbh.E_ABORT_OVERSIZE
+            continue
+        assert int(st.item()) == 0
+        osub, _, _, _ = orc.sample(a, n, ns, orc.SAMPLE_PERMUTE,
+                                   assign=perms[key])
+        got = to_host(sub)[: osub.size]
+        assert np.array_equal(got, osub), (key, seed, first_diff(got, osub))
