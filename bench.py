@@ -599,6 +599,17 @@ def run_contraction(ctx, ssbh, args, peak_alu):
     ctx.set_sample_path(0)
     torch.cuda.synchronize()
     gather_equal = bool(torch.equal(sub, sub_direct)) and int(st.item()) == 0
+    # The same split through the context's keyed permutation of perm_key:
+    # the first call builds it and buckets it, later calls with that key
+    # keep both and run the window and merge passes only.
+    def sample_keyed():
+        ctx.sample(d_in, n, ns, ssbh.SAMPLE_PERMUTE, key=c["perm_key"],
+                   sub=sub_direct, sub_capacity=sub_cap, length=ln,
+                   word_off=wo, status=st)
+    sample_keyed()
+    gk_ms = float(np.mean(time_events(sample_keyed, 3)))
+    torch.cuda.synchronize()
+    gather_keyed_equal = bool(torch.equal(sub, sub_direct)) and int(st.item()) == 0
     del sub_direct
     mf_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_MFMA_I8, out), 3)))
     mfma_sched = ctx.last_schedule()
@@ -615,6 +626,9 @@ def run_contraction(ctx, ssbh, args, peak_alu):
         "gather_kernel_avg_us": gather_kernels,
         "gather_direct_ms": round(gd_ms, 3),
         "gather_equals_direct": gather_equal,
+        "gather_keyed_ms": round(gk_ms, 3),
+        "gather_keyed_equal": gather_keyed_equal,
+        "gbps_step_fft_keyed": round(n / ((gk_ms + ff_ms) * 1e-3) / 1e9, 3),
         "mfma_ms": round(mf_ms, 3), "valu_ms": round(va_ms, 3),
         "gbps_step_mfma": round(n / ((g_ms + mf_ms) * 1e-3) / 1e9, 3),
         "gbps_hash_mfma": round(n / (mf_ms * 1e-3) / 1e9, 3),
