@@ -159,7 +159,11 @@ int ssbh_num_cus(const ssbh_ctx *ctx);
  *                looked-up bits); when that cannot be reserved, or when the
  *                permutation overfills a cell (far outside a random
  *                permutation's spread), each output bit is read directly.
- *                The result is the same either way.
+ *                The result is the same either way.  For the keyed
+ *                permutation the first of the three passes (which depends
+ *                on pi and n_sub only) is kept for the last
+ *                (sample_key, n_bits, n_sub) and skipped when they repeat;
+ *                a caller's d_assign is never cached.
  *  l_ub          L_S^UB; 0 disables the abort rule.  If some n_j > l_ub,
  *                *d_status = SSBH_E_ABORT_OVERSIZE.
  *  d_sub         output sub-blocks, sub_capacity_words words.  Needs
