@@ -239,19 +239,27 @@ def run_batched(ctx, ssbh, args):
     return res
 
 
+def fft_schedule_parts(schedule: str):
+    """(transform length, sub-blocks per transform, bytes per transform
+    point between passes) of an FFT schedule name "fft:<chunk>:x<per>:L<L>"
+    with ":f32" appended when the passes exchange complex floats."""
+    L = int(schedule.split(":L")[1].split(":")[0])
+    per = int(schedule.split(":x")[1].split(":")[0])
+    return L, per, (8 if schedule.endswith(":f32") else 16)
+
+
 def fft_hash_roofline(schedule: str, ns: int, n_bits: int, out_bits: int,
                       hash_ms: float, shared: bool, launches: int) -> dict:
     """The whole FFT hash (all passes, two chunks in flight) against HBM.
     Algorithmic bytes per hash: every transform is written by the column
     pass, read and written by the row pass and read by the output pass
-    (64 L bytes); with a shared seed the spectrum is built once (48 L) and
-    read by every row-pass launch (16 L each); the packed input bits are
-    read once and the output bits are written twice and read once (parity
-    words, then their places)."""
-    L = int(schedule.split(":L")[1])
-    per = int(schedule.split(":x")[1].split(":")[0])
+    (4 L points of 16 bytes, or of 8 with float storage); with a shared
+    seed the spectrum is built once (48 L) and read by every row-pass launch
+    (16 L each); the packed input bits are read once and the output bits are
+    written twice and read once (parity words, then their places)."""
+    L, per, pb = fft_schedule_parts(schedule)
     transforms = (ns + per - 1) // per
-    b = 64 * L * transforms + n_bits // 8 + 3 * out_bits // 8
+    b = 4 * pb * L * transforms + n_bits // 8 + 3 * out_bits // 8
     if shared:
         b += 48 * L + 16 * L * launches
     achieved = b / (hash_ms * 1e-3) / 1e9
@@ -329,6 +337,17 @@ def run_batched_independent(ctx, ssbh, args, res):
     hash_(kern, out)
     schedule = ctx.last_schedule()
     valu_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_VALU, outv), 2)))
+    # The same hash with complex doubles between the FFT passes (the
+    # library keeps floats there at this length): time and equality.
+    ctx.set_fft_storage(64)
+    try:
+        hash_(ssbh.K_FFT, outv)
+        f64_ms = float(np.mean(time_events(lambda: hash_(ssbh.K_FFT, outv), 3)))
+        f64_schedule = ctx.last_schedule()
+    finally:
+        ctx.set_fft_storage(0)
+    torch.cuda.synchronize()
+    f64_equal = bool(torch.equal(out, outv)) and int(st.item()) == 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -344,12 +363,16 @@ def run_batched_independent(ctx, ssbh, args, res):
             "ms_per_step": round(ms_step, 4),
             "gbps_step": round(res["n"] / (ms_step * 1e-3) / 1e9, 3),
             "hash_ms": round(hash_ms, 4), "hash_ms_valu": round(valu_ms, 4),
+            "hash_ms_fft_f64_storage": round(f64_ms, 4),
+            "fft_f64_storage_schedule": f64_schedule,
+            "fft_f64_storage_equal": f64_equal,
             "gbps_hash": round(res["n"] / (hash_ms * 1e-3) / 1e9, 3),
             "auto_equals_valu": same, "oracle_digest_equal": oracle_equal,
             "tuning": tune_report.strip().splitlines()}
     if schedule.startswith("fft"):
         # Row pass in the joint mode: each transform is read and written
-        # once (L complex doubles each way); there is no seed spectrum.
+        # once (L complex points each way, doubles or floats); there is no
+        # seed spectrum.
         ctx.set_timing(True)
         reps = max(3, args.steps)
         for _ in range(reps):
@@ -357,8 +380,8 @@ def run_batched_independent(ctx, ssbh, args, res):
         hk = ctx.timing_report()
         ctx.set_timing(False)
         n_l, ms = hk["k_fft_rows"]
-        L = int(schedule.split(":L")[1])
-        total_bytes = reps * ns * 2 * L * 16
+        L, _, pb = fft_schedule_parts(schedule)
+        total_bytes = reps * ns * 2 * L * pb
         achieved = total_bytes / (ms * 1e-3) / 1e9
         item["roofline"] = {
             "bound": "hbm", "kernel": "k_fft_rows", "schedule": schedule,
@@ -994,8 +1017,13 @@ def main() -> int:
         for _ in range(args.steps):
             b.copy_(a)
         torch.cuda.synchronize()
+        # Rate of the same copy (read + write bytes over event time): what a
+        # plain streaming kernel reaches on this HBM.
+        ms = float(np.mean(time_events(lambda: b.copy_(a), max(3, args.steps))))
         print(json.dumps({"mode": "copy", "bytes_read": nb, "bytes_written": nb,
-                          "launches": args.steps}), flush=True)
+                          "launches": args.steps, "ms_per_copy": round(ms, 4),
+                          "gbps": round(2 * nb / (ms * 1e-3) / 1e9, 1)}),
+              flush=True)
         return 0
     if args.mode == "serving":
         print(json.dumps(run_serving(ssbh, args)), flush=True)
@@ -1048,10 +1076,9 @@ def main() -> int:
         # reads the seed spectrum once.
         kern = "k_fft_rows"
         n_l, ms = hk[kern]
-        L = int(res["schedule"].split(":L")[1])   # transform length
-        per = int(res["schedule"].split(":x")[1].split(":")[0])
+        L, per, pb = fft_schedule_parts(res["schedule"])
         transforms = (res["ns"] + per - 1) // per
-        per_transform = 2 * L * 16
+        per_transform = 2 * L * pb
         total_bytes = (res["timed_calls"] * transforms * per_transform +
                        n_l * L * 16)
         achieved = total_bytes / (ms * 1e-3) / 1e9

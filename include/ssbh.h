@@ -94,7 +94,11 @@ enum {
                                  (imaginary), squared pointwise; needs every
                                  n_j + m_cap - 1 <= the transform length of
                                  S (true when S >= n_max + m_cap - 1), else
-                                 *d_status = SSBH_E_UNSUPPORTED              */
+                                 *d_status = SSBH_E_UNSUPPORTED.  Transform
+                                 lengths up to 2^18 keep the data between
+                                 passes as complex floats (arithmetic in
+                                 double; error bound below the 1/4 checked,
+                                 see ssbh_set_fft_storage)                  */
     SSBH_K_MFMA_F4 = 4        /* fp4 (e2m1) matrix cores, 64 columns per
                                  matrix op, fp32 sums (exact: the host
                                  requires seed_bits + 1 - m_cap <= 2^24, so
@@ -534,6 +538,18 @@ ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs);
  * library choice (2 when allowed).  For tests and tuning; the output bits
  * do not depend on it. */
 ssbh_status ssbh_set_fft_packing(ssbh_ctx *ctx, int per_part);
+
+/* Force the FFT hash's storage of transform data between its passes: 64 =
+ * complex doubles, 32 = complex floats (arithmetic stays double), 0 =
+ * library choice (floats with a seed stride S > 0 and a transform length of
+ * at most 2^18, else doubles).  Floats are allowed only there: elsewhere the
+ * hash returns SSBH_E_UNSUPPORTED.  There, rounding both intermediates to
+ * float moves each entry s_j * xr_j by less than 5 * 2^-24 * (n_j + n_j +
+ * m_cap - 1) < 5/32, below the 1/4 every entry is checked for.  For tests
+ * and tuning of the synchronous entry points (serving takes the library
+ * choice); the output bits do not depend on it.  bits outside {0, 32, 64}:
+ * SSBH_E_INVAL. */
+ssbh_status ssbh_set_fft_storage(ssbh_ctx *ctx, int bits);
 
 /* Where the VALU hash kernel reads the 32-bit column words of the sub-blocks
  * from: 0 = staged in LDS with the seed window, 1 = through the scalar data

@@ -234,6 +234,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             if (sscanf(choice.c_str(), "fft:%u", &d) == 1) {
                 FftSchedule fs;
                 fs.chunk_pairs = d;
+                fs.storage = ctx->forced_fft_storage;
                 r.kernel = SSBH_K_FFT;
                 return launch_hash_fft(ctx, ws, r, fs, stream);
             }
@@ -268,6 +269,7 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     if (q.kernel == SSBH_K_FFT) {
         FftSchedule fs;
         fs.chunk_pairs = ctx->forced_fft_chunk;
+        fs.storage = ctx->forced_fft_storage;
         return launch_hash_fft(ctx, ws, q, fs, stream);
     }
     if (q.kernel != SSBH_K_VALU) SSBH_INVAL("unknown kernel %u", q.kernel);
@@ -524,6 +526,15 @@ ssbh_status ssbh_set_fft_packing(ssbh_ctx *ctx, int per_part) {
     if (per_part < 0 || per_part > 2) SSBH_INVAL("per_part must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->forced_fft_pack = per_part;
+    return SSBH_OK;
+}
+
+ssbh_status ssbh_set_fft_storage(ssbh_ctx *ctx, int bits) {
+    clear_error();
+    if (!ctx) SSBH_INVAL("ctx is null");
+    if (bits != 0 && bits != 32 && bits != 64) SSBH_INVAL("bits must be 0, 32 or 64");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->forced_fft_storage = bits;
     return SSBH_OK;
 }
 

@@ -112,6 +112,19 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) {
 __device__ __forceinline__ double2 conj2(double2 a) {
     return make_double2(a.x, -a.y);
 }
+// Transform data between passes: complex doubles, or (independent seeds,
+// short transforms) complex floats, rounded to nearest on the way out and
+// widened exactly on the way in; every butterfly computes in double.
+template <class W> __device__ __forceinline__ W to_work(double2 v);
+template <> __device__ __forceinline__ double2 to_work<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 to_work<float2>(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
+__device__ __forceinline__ double2 from_work(double2 v) { return v; }
+__device__ __forceinline__ double2 from_work(float2 v) {
+    return make_double2((double)v.x, (double)v.y);
+}
+
 // Multiply by -i (forward) or +i (inverse).
 template <bool INV>
 __device__ __forceinline__ double2 rot90(double2 a) {
@@ -499,7 +512,7 @@ __device__ __forceinline__ uint64_t sub_of(const FftArgs &a, uint32_t pl, int sl
 // reads bits, the last stage stores times w_L^(n2 k1).  A sub-block whose
 // n_j + m_cap - 1 exceeds L (possible only with a seed stride below n_max +
 // m_cap - 1) sets SSBH_E_UNSUPPORTED.
-template <bool SEED, bool PACK, bool JOINT = false>
+template <bool SEED, bool PACK, bool JOINT = false, class W = double2>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     constexpr int SLOTS = PACK ? 4 : 2;
     __shared__ double buf[kN1 * kN1];
@@ -537,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
         win[part][n1] = v;
     }
     __syncthreads();
-    double2 *y = a.work + (size_t)pl * a.L;
+    W *y = reinterpret_cast<W *>(a.work) + (size_t)pl * a.L;
     // Element (column i = f, row n1 = e).
     auto ld = [&](int f, int e) {
         const double b0 = (double)((win[0][e] >> f) & 1ull);
@@ -554,7 +567,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(FftArgs a) {
     auto st = [&](int f, int k0, int span, auto &v) {
         const uint64_t n2i = c0 + f;
         twiddle_run(v, omega_l(a, n2i * k0), omega_l(a, n2i * span),
-                    [&](int r, double2 x) { y[(size_t)(k0 + r * span) * n2 + n2i] = x; });
+                    [&](int r, double2 x) {
+                        y[(size_t)(k0 + r * span) * n2 + n2i] = to_work<W>(x);
+                    });
     };
     fft64_cols<false>(buf, a.tw64, ld, st);
 }
@@ -745,7 +760,7 @@ __device__ __forceinline__ void row_inv_all(double2 *buf, const double2 *tw, int
 // with three or four).  Workgroup x holds rows x RPW .. x RPW + RPW - 1.
 // SQ (independent seeds): the spectrum is squared instead (see the top of
 // the file); the seed spectrum is not read.
-template <int N2, bool SPEC, bool SQ = false>
+template <int N2, bool SPEC, bool SQ = false, class W = double2>
 __global__ __launch_bounds__(rp_threads(N2)) void k_fft_rows(FftArgs a) {
     constexpr int TPR = rp_tpr(N2), RPW = rp_rpw(N2);
     __shared__ double2 lds[N2 * RPW];
@@ -759,10 +774,10 @@ __global__ __launch_bounds__(rp_threads(N2)) void k_fft_rows(FftArgs a) {
     const uint32_t pl = SPEC ? 0u : blockIdx.y;
     const uint64_t k1 = row & 63u;
     double2 *buf = lds + (threadIdx.x / TPR) * N2;
-    double2 *y = a.work + (size_t)pl * a.L + (size_t)row * N2;
+    W *y = reinterpret_cast<W *>(a.work) + (size_t)pl * a.L + (size_t)row * N2;
     double2 *sp = a.spec + (size_t)row * N2;
     const double2 *tw = a.twr;
-    row_fwd_all<N2, 0>(buf, tw, lt, [&](int e) { return y[e]; });
+    row_fwd_all<N2, 0>(buf, tw, lt, [&](int e) { return from_work(y[e]); });
 
     // Last stage: forward DFT in registers, spectrum product, inverse DFT.
     double2 v[TL::PER][TL::R], wr[TL::PER][TL::R];
@@ -811,7 +826,7 @@ __global__ __launch_bounds__(rp_threads(N2)) void k_fft_rows(FftArgs a) {
             dftR<T0::R, true>(u[i]);
             twiddle_run(u[i], conj2(omega_r(a, (uint64_t)g * k1)),
                         conj2(omega_r(a, (uint64_t)T0::G * k1)),
-                        [&](int k, double2 x) { y[T0::in(g, k)] = x; });
+                        [&](int k, double2 x) { y[T0::in(g, k)] = to_work<W>(x); });
         }
     }
 }
@@ -882,9 +897,9 @@ __device__ __forceinline__ QRange q_range(const FftArgs &a, uint64_t j, int64_t 
 // word per sub-block (ballot), stored with a plain store (each word has one
 // writer); k_fft_emit then places them.  PACK: a part's integer is
 // lo + 2^18 hi, the low sub-block's parity is its bit 0, the high one's its
-// bit 18.  JOINT: the imaginary part is 2 (s_j * xr_j), an even integer (an
-// odd one is flagged too), and the real part carries no sub-block.
-template <bool PACK, bool JOINT = false>
+// bit 18.  JOINT: the imaginary part is 2 (s_j * xr_j); its half is rounded
+// and checked like any other entry, and the real part carries no sub-block.
+template <bool PACK, bool JOINT = false, class W = double2>
 __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     constexpr int SLOTS = PACK ? 4 : JOINT ? 1 : 2;
     constexpr int PER_PART = PACK ? 2 : 1;
@@ -893,7 +908,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
     const uint32_t n2 = a.n2;
     const uint32_t c0 = blockIdx.x * kN1;
     const uint32_t pl = blockIdx.y;
-    const double2 *w = a.work + (size_t)pl * a.L;
+    const W *w = reinterpret_cast<const W *>(a.work) + (size_t)pl * a.L;
     const int lane = threadIdx.x & 63;
     const double scale = 1.0 / (double)a.L;
     // The same for the whole workgroup: kept in scalar registers.
@@ -911,7 +926,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
         qr[slot] = QRange{uni(r.q0), uni(r.qlo), uni(r.widx)};
     }
     bool bad = false;
-    auto ld = [&](int f, int e) { return w[(size_t)e * n2 + c0 + f]; };
+    auto ld = [&](int f, int e) { return from_work(w[(size_t)e * n2 + c0 + f]); };
     // Parity of an integer-valued double below 2^53, exactly.
     auto parity = [](double x) { return x != 2.0 * floor(0.5 * x); };
     // Called with the same row n1 on all 64 lanes: entries q = qb + lane.
@@ -920,13 +935,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_out(FftArgs a) {
         const int64_t q = qb + lane;
 #pragma unroll
         for (int part = JOINT ? 1 : 0; part < 2; ++part) {
-            const double v = (part ? x.y : x.x) * scale;
-            double rv = rint(v);
-            bool off = fabs(v - rv) > 0.25 || rv < -0.25;
-            if constexpr (JOINT) {              // rv = 2 c: c's parity is bit 1
-                off = off || parity(rv);
-                rv *= 0.5;
-            }
+            // JOINT: half the imaginary part is the entry.
+            const double v = (part ? x.y : x.x) * (JOINT ? 0.5 * scale : scale);
+            const double rv = rint(v);
+            const bool off = fabs(v - rv) > 0.25 || rv < -0.25;
             // PACK: rv = lo + 2^18 hi, lo < 2^18; parity(lo) = parity(rv).
             const double hi = PACK ? floor(rv * (1.0 / kPackScale)) : 0.0;
 #pragma unroll
@@ -1070,7 +1082,7 @@ void launch_timed(Workspace *ws, const char *name, K kernel, dim3 grid, dim3 blo
 
 template <int N2>
 void launch_rows(const FftArgs &a, uint32_t pairs, bool spec, bool sq,
-                 hipStream_t stream, Workspace *ws) {
+                 bool narrow, hipStream_t stream, Workspace *ws) {
     // Rows per transform (64, 4096 or 2^18) are a multiple of the rows per
     // workgroup (a power of two up to 32).
     const uint32_t rows = (uint32_t)(a.L / N2);
@@ -1079,6 +1091,11 @@ void launch_rows(const FftArgs &a, uint32_t pairs, bool spec, bool sq,
     if (spec)
         hipLaunchKernelGGL((k_fft_rows<N2, true>), grid, dim3(rp_threads(N2)),
                            0, stream, a);
+    else if (sq && narrow) {
+        if constexpr (N2 <= 4096)   // L <= 2^18
+            launch_timed(ws, "k_fft_rows", k_fft_rows<N2, false, true, float2>, grid,
+                         dim3(rp_threads(N2)), stream, a);
+    }
     else if (sq)
         launch_timed(ws, "k_fft_rows", k_fft_rows<N2, false, true>, grid,
                      dim3(rp_threads(N2)), stream, a);
@@ -1088,22 +1105,22 @@ void launch_rows(const FftArgs &a, uint32_t pairs, bool spec, bool sq,
 }
 
 void rows(const FftArgs &a, uint32_t pairs, bool spec, hipStream_t stream,
-          Workspace *ws = nullptr, bool sq = false) {
+          Workspace *ws = nullptr, bool sq = false, bool narrow = false) {
     switch (a.nr) {
-    case 64: launch_rows<64>(a, pairs, spec, sq, stream, ws); break;
-    case 128: launch_rows<128>(a, pairs, spec, sq, stream, ws); break;
-    case 192: launch_rows<192>(a, pairs, spec, sq, stream, ws); break;
-    case 256: launch_rows<256>(a, pairs, spec, sq, stream, ws); break;
-    case 384: launch_rows<384>(a, pairs, spec, sq, stream, ws); break;
-    case 512: launch_rows<512>(a, pairs, spec, sq, stream, ws); break;
-    case 768: launch_rows<768>(a, pairs, spec, sq, stream, ws); break;
-    case 1024: launch_rows<1024>(a, pairs, spec, sq, stream, ws); break;
-    case 1536: launch_rows<1536>(a, pairs, spec, sq, stream, ws); break;
-    case 2048: launch_rows<2048>(a, pairs, spec, sq, stream, ws); break;
-    case 3072: launch_rows<3072>(a, pairs, spec, sq, stream, ws); break;
-    case 4096: launch_rows<4096>(a, pairs, spec, sq, stream, ws); break;
-    case 6144: launch_rows<6144>(a, pairs, spec, sq, stream, ws); break;
-    default: launch_rows<8192>(a, pairs, spec, sq, stream, ws); break;
+    case 64: launch_rows<64>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 128: launch_rows<128>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 192: launch_rows<192>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 256: launch_rows<256>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 384: launch_rows<384>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 512: launch_rows<512>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 768: launch_rows<768>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 1024: launch_rows<1024>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 1536: launch_rows<1536>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 2048: launch_rows<2048>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 3072: launch_rows<3072>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 4096: launch_rows<4096>(a, pairs, spec, sq, narrow, stream, ws); break;
+    case 6144: launch_rows<6144>(a, pairs, spec, sq, narrow, stream, ws); break;
+    default: launch_rows<8192>(a, pairs, spec, sq, narrow, stream, ws); break;
     }
 }
 
@@ -1135,8 +1152,29 @@ uint64_t fft_length(uint64_t seed_bits) {
 // last-level cache much of that traffic stays on chip.  With two chunks in
 // flight (see FftSchedule::overlap) 96 MiB chunks measured best at the
 // batched length.
-uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib) {
-    return (uint32_t)std::max<uint64_t>(1, (mib << 20) / (L * sizeof(double2)));
+uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib, uint64_t point_bytes) {
+    return (uint32_t)std::max<uint64_t>(1, (mib << 20) / (L * point_bytes));
+}
+
+// Complex floats between the passes (8 bytes a point instead of 16) with
+// independent seeds and L <= 2^18.  Rounding the column pass's output Y1 and
+// the row pass's output Y2 to float (relative error u = 2^-24 per entry)
+// moves the result c = z (*) z of the transform of z = s_j + i xr_j by at
+// most (2u + u^2) |z|^2 through Y1 (the spectrum error, sqrt(L) u |z|_2 in
+// 2-norm, meets the spectrum, sqrt(L) |z|_2, in the squaring; the 1/L of the
+// inverse cancels the two square roots) and by at most 8 u |z|^2 through Y2
+// (a column's 64 entries of Y2 are L/64 times the DFT of 64 entries of c,
+// each at most |z|^2 in size).  The entry s_j * xr_j is half the imaginary
+// part, so its error stays below 5 u |z|^2 + (double rounding), and
+// |z|^2 <= n_j + (n_j + m_cap - 1) < 2 L: at L = 2^18 that is 5/32 < 1/4,
+// the distance every entry is checked for.  With a shared seed the second
+// sub-block of a part is scaled by 2^18, far beyond what floats carry.
+constexpr uint64_t kNarrowMaxLength = 1ull << 18;
+bool fft_narrow(const HashRequest &q, uint64_t L, int storage) {
+    return storage != 64 && q.stride != 0 && L <= kNarrowMaxLength;
+}
+uint64_t fft_point_bytes(const HashRequest &q, uint64_t L, int storage) {
+    return fft_narrow(q, L, storage) ? sizeof(float2) : sizeof(double2);
 }
 
 bool fft_can_pack(const HashRequest &q, uint64_t L) {
@@ -1166,22 +1204,29 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     // context's own workspace, which hold its lock, use them (a pipeline's
     // eager run and serving jobs have workspaces of their own).
     const bool may_fork = s.overlap && &ws == &ctx->ws && !ws.timer;
+    const bool joint = q.stride != 0;   // independent seeds: seed and data in one transform
+    if (s.storage == 32 && !fft_narrow(q, L, 32)) {
+        set_error("float transform storage needs a seed stride and a transform "
+                  "length of at most 2^18");
+        return SSBH_E_UNSUPPORTED;
+    }
+    const bool narrow = fft_narrow(q, L, s.storage);
+    const uint64_t pb = narrow ? sizeof(float2) : sizeof(double2);
     // Default chunk: 96 MiB of transforms when two are in flight (both fit
     // the 256 MB last-level cache), else 160 MiB.
     uint32_t chunk = s.chunk_pairs ? s.chunk_pairs
-                                   : fft_chunk_of_bytes(L, may_fork ? 96 : 160);
+                                   : fft_chunk_of_bytes(L, may_fork ? 96 : 160, pb);
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>(chunk, (1ull << 29) / (L * sizeof(double2))));
-    const bool joint = q.stride != 0;   // independent seeds: seed and data in one transform
+        1, std::min<uint64_t>(chunk, (1ull << 29) / (L * pb)));
     const int per = fft_per_transform(ctx, q, L);
     if (per == 4 && !fft_can_pack(q, L)) {
         set_error("four sub-blocks per transform need a shared seed, "
                   "seed_bits + 1 - m_cap < 2^18 and L <= 2^20");
         return SSBH_E_UNSUPPORTED;
     }
-    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u:x%d:L%llu",
-             s.chunk_pairs, per, (unsigned long long)L);
+    snprintf(ws.last_schedule, sizeof ws.last_schedule, "fft:%u:x%d:L%llu%s",
+             s.chunk_pairs, per, (unsigned long long)L, narrow ? ":f32" : "");
     if (!q.n_sub) return SSBH_OK;
     FftTables *tab = nullptr;
     if ((st = get_tables(ctx->device, L, &tab)) != SSBH_OK) return st;
@@ -1210,7 +1255,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             return SSBH_E_DEVICE;
         }
     }
-    const size_t work_b = (size_t)cp * L * sizeof(double2);
+    const size_t work_b = (size_t)cp * L * pb;
     if ((st = ws.fft_work.reserve(fork ? 2 * work_b : work_b)) != SSBH_OK)
         return st;
     // Parity words: the regions of q_range, out_cap_bits / 64 + 3 n_sub words.
@@ -1269,7 +1314,7 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         rows(a, 1, true, stream);
     };
     if (!joint) spectrum(0);
-    double2 *work0 = ws.fft_work.as<double2>();
+    char *work0 = ws.fft_work.as<char>();
     if (fork) {
         // The second stream starts after everything queued so far (the plan,
         // the output fill, the spectrum).
@@ -1282,8 +1327,11 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         const bool odd = fork && (ci & 1);
         hipStream_t sc = odd ? ctx->fft_side : stream;
         a.pair0 = (uint32_t)p0;
-        a.work = odd ? work0 + (size_t)cp * L : work0;
-        if (joint)
+        a.work = reinterpret_cast<double2 *>(odd ? work0 + work_b : work0);
+        if (narrow)
+            launch_timed(&ws, "k_fft_cols", k_fft_cols<false, false, true, float2>,
+                         dim3(tiles, np), dim3(kThreads), sc, a);
+        else if (joint)
             launch_timed(&ws, "k_fft_cols", k_fft_cols<false, false, true>,
                          dim3(tiles, np), dim3(kThreads), sc, a);
         else if (per == 4)
@@ -1296,12 +1344,15 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
             TimedLaunch timed(ws.timer, "k_fft_mid", sc);
             mids(false, np, sc);
         }
-        rows(a, np, false, sc, &ws, joint);
+        rows(a, np, false, sc, &ws, joint, narrow);
         if (levels > 2) {
             TimedLaunch timed(ws.timer, "k_fft_mid", sc);
             mids(true, np, sc);
         }
-        if (joint)
+        if (narrow)
+            launch_timed(&ws, "k_fft_out", k_fft_out<false, true, float2>,
+                         dim3(tiles, np), dim3(kThreads), sc, a);
+        else if (joint)
             launch_timed(&ws, "k_fft_out", k_fft_out<false, true>, dim3(tiles, np),
                          dim3(kThreads), sc, a);
         else if (per == 4)

@@ -191,10 +191,14 @@ static ssbh_status plan_job(const ssbh_ctx *ctx, const ssbh_job &j,
         // Transforms of at most kServeFftChunkMiB per chunk: a job's share of
         // the budget stays modest, so several jobs fit at once.
         const uint64_t L = fft_length(p.stride);
-        p.fsched.chunk_pairs = fft_chunk_of_bytes(L, kServeFftChunkMiB);
+        // Library choice of the transform storage, fixed here with the
+        // footprint.
+        const uint64_t pb = fft_point_bytes(q, L, 0);
+        p.fsched.chunk_pairs = fft_chunk_of_bytes(L, kServeFftChunkMiB, pb);
         p.fsched.overlap = false;
+        p.fsched.storage = pb == 8 ? 32 : 64;
         const uint64_t cp = std::min<uint64_t>(p.fsched.chunk_pairs, j.n_sub);
-        p.fft_work_b = (size_t)cp * L * 16;
+        p.fft_work_b = (size_t)cp * L * pb;
         p.fft_qbuf_b = (size_t)(q.out_cap_bits / 64 + 3ull * j.n_sub + 4) * 8;
         q.kernel = SSBH_K_FFT;
     } else {

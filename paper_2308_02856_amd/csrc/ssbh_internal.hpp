@@ -128,6 +128,9 @@ struct FftSchedule {
     // own workspace; off under graph capture, with per-kernel timing and for
     // serving jobs (their own streams overlap).
     bool overlap = true;
+    // Transform data between passes: 0 = library choice (complex floats
+    // where fft_narrow allows), 64 = complex doubles, 32 = complex floats.
+    int storage = 0;
 };
 constexpr uint64_t kMaxFftLength = 1ull << 31;   // transform length limit
 
@@ -152,6 +155,7 @@ struct ssbh_ctx {
     int forced_mfma[4] = {0, 0, 0, 0};
     uint32_t forced_fft_chunk = 0;
     int forced_fft_pack = 0;       // 0 = library choice, 1 / 2 sub-blocks per part
+    int forced_fft_storage = 0;    // 0 = library choice, 64 / 32 bits per real
     int forced_scatter = 0;        // 0 = library choice, 1 = one wave per segment
     hipStream_t fft_side = nullptr;   // second stream of the FFT hash chunks
     hipEvent_t fft_ev[2] = {nullptr, nullptr};   // fork and join
@@ -203,7 +207,9 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
                             const FftSchedule &s, hipStream_t stream);
 uint64_t fft_length(uint64_t seed_bits);
 bool fft_can_pack(const HashRequest &q, uint64_t L);
-uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib);
+uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib, uint64_t point_bytes);
+bool fft_narrow(const HashRequest &q, uint64_t L, int storage);
+uint64_t fft_point_bytes(const HashRequest &q, uint64_t L, int storage);
 int fft_per_transform(const ssbh_ctx *ctx, const HashRequest &q, uint64_t L);
 
 ssbh_status launch_seed(uint64_t key, uint64_t *d_seed, uint64_t seed_bits,

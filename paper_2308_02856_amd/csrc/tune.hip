@@ -56,7 +56,8 @@ std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
         const uint64_t L = fft_length(span);
         std::vector<uint32_t> cps;
         for (uint64_t mib : {64ull, 96ull, 128ull, 160ull, 192ull, 256ull}) {
-            const uint32_t cp = fft_chunk_of_bytes(L, mib);
+            const uint32_t cp = fft_chunk_of_bytes(
+                L, mib, fft_point_bytes(q, L, ctx->forced_fft_storage));
             if (std::find(cps.begin(), cps.end(), cp) == cps.end()) cps.push_back(cp);
         }
         for (uint32_t cp : cps) {
@@ -64,6 +65,7 @@ std::vector<Candidate> candidates(const ssbh_ctx *ctx, const HashRequest &q) {
             k.mfma = false;
             k.fft = true;
             k.f.chunk_pairs = cp;
+            k.f.storage = ctx->forced_fft_storage;
             char b[64];
             snprintf(b, sizeof b, "fft:%u", cp);
             k.name = b;

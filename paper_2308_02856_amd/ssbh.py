@@ -158,6 +158,8 @@ def lib() -> ctypes.CDLL:
     L.ssbh_set_fft_schedule.argtypes = [_vp, _u32]
     L.ssbh_set_fft_packing.restype = _i32
     L.ssbh_set_fft_packing.argtypes = [_vp, ctypes.c_int]
+    L.ssbh_set_fft_storage.restype = _i32
+    L.ssbh_set_fft_storage.argtypes = [_vp, ctypes.c_int]
     L.ssbh_set_column_path.restype = _i32
     L.ssbh_set_column_path.argtypes = [_vp, ctypes.c_int]
     L.ssbh_job_out_words.restype = _u64
@@ -466,6 +468,11 @@ class Context:
         """Sub-blocks per transform part: 1, 2 (x_lo + 2^18 x_hi) or 0 =
         library choice."""
         _check(lib().ssbh_set_fft_packing(self._h, int(per_part)))
+
+    def set_fft_storage(self, bits: int = 0):
+        """FFT transform data between passes: 64 (doubles), 32 (floats) or
+        0 = library choice."""
+        _check(lib().ssbh_set_fft_storage(self._h, int(bits)))
 
     def set_column_path(self, scalar_x: int = -1):
         """Column words via LDS (0), scalar loads (1) or library choice (-1)."""

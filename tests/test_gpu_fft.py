@@ -444,7 +444,9 @@ def test_every_transform_length_independent(ctx, orc, L):
     kw = dict(out_rule=ssbh.OUT_EXPLICIT, out_len=dl, seed_stride=S)
     got, tot = fft_hash(ctx, args[0], args[2], args[3], ns, args[5],
                         seed_bits, M, **kw)
-    assert ctx.last_schedule().endswith(":L%d" % L)
+    sched = ctx.last_schedule()
+    assert (":L%d" % L) in sched
+    assert sched.endswith(":f32") == (L <= 1 << 18)
     out, tot2, st = ctx.hash_batch(*args, kernel=ssbh.K_VALU, **kw)
     torch.cuda.synchronize()
     assert int(st.item()) == 0 and int(tot2.item()) == tot
@@ -542,3 +544,113 @@ def test_fft_graph_pipeline_many_chunks(ctx, orc):
         assert int(st.item()) == 0 and int(tot.item()) == wtot
         assert np.array_equal(to_host(out)[: want.size], want)
     pipe.close()
+
+
+def _all_ones_subs(lens):
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = np.full(int(words.sum()), np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+    for j in range(lens.size):
+        r = int(lens[j]) % 64
+        if r:
+            sub[int(wo[j] + words[j] - 1)] = np.uint64((1 << r) - 1)
+    return sub, wo
+
+
+def test_float_storage_worst_case_all_ones(ctx):
+    """Independent seeds at the longest transform that keeps complex floats
+    between the passes (L = 2^18), with every seed and input bit set: the
+    largest |z|^2 = n_j + (n_j + m - 1) the rounding bound covers.  Every
+    entry of T_j x_j is then n_j, so every output bit of sub-block j is
+    n_j mod 2; the float and double storage give exactly that."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    S = 1 << 18
+    M = 4096
+    lens = np.array([S - M + 1 - j for j in range(3)], dtype=np.uint64)
+    ns = lens.size
+    sub, wo = _all_ones_subs(lens)
+    seed_bits = ns * S
+    seed = np.full(seed_bits // 64, np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+    want = np.concatenate([np.full(M, int(n) & 1, dtype=np.uint8) for n in lens])
+    args = (to_dev(sub), sub.size, to_dev(lens), to_dev(wo), ns, to_dev(seed),
+            seed_bits, M)
+    kw = dict(out_rule=ssbh.OUT_FIXED, out_a=M, seed_stride=S, kernel=ssbh.K_FFT)
+    for bits, suffix in ((0, ":f32"), (32, ":f32"), (64, ":L%d" % S)):
+        ctx.set_fft_storage(bits)
+        try:
+            out, tot, st = ctx.hash_batch(*args, **kw)
+            torch.cuda.synchronize()
+            sched = ctx.last_schedule()
+        finally:
+            ctx.set_fft_storage(0)
+        assert int(st.item()) == 0, ssbh.status_name(int(st.item()))
+        assert sched.endswith(suffix), (bits, sched)
+        assert int(tot.item()) == ns * M
+        got = np.unpackbits(to_host(out).view(np.uint8), bitorder="little")[: ns * M]
+        assert np.array_equal(got, want), (bits, first_diff(got, want))
+
+
+@pytest.mark.parametrize("ns,lmax,m", [(6, 120000, 48000), (33, 5000, 1700)])
+def test_float_and_double_storage_agree_with_oracle(ctx, orc, ns, lmax, m):
+    """Independent seeds, uneven sub-blocks: the hash with complex floats and
+    with complex doubles between the passes both equal the oracle bit for
+    bit (float storage is the library's choice at these lengths)."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    rng = np.random.default_rng(ns + lmax)
+    lens = rng.integers(lmax // 2, lmax + 1, ns).astype(np.uint64)
+    lens[0] = lmax
+    words = (lens + 63) // 64
+    wo = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    sub = bernoulli_bits(int(words.sum()) * 64, 0.3, ns)
+    for j in range(ns):
+        r = int(lens[j]) % 64
+        if r:
+            sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
+    S = lmax + m - 1
+    seed_bits = ns * S
+    seed = uniform_bits(seed_bits, lmax + 1)
+    want, wtot = orc.hash_batch(sub, lens, wo, np.full(ns, m, np.uint64),
+                                seed, seed_bits, S, m)
+    args = (to_dev(sub), sub.size, to_dev(lens), to_dev(wo), ns, to_dev(seed),
+            seed_bits, m)
+    kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m, seed_stride=S, kernel=ssbh.K_FFT)
+    for bits in (0, 64, 32):
+        ctx.set_fft_storage(bits)
+        try:
+            out, tot, st = ctx.hash_batch(*args, **kw)
+            torch.cuda.synchronize()
+            sched = ctx.last_schedule()
+        finally:
+            ctx.set_fft_storage(0)
+        assert int(st.item()) == 0, ssbh.status_name(int(st.item()))
+        assert sched.endswith(":f32") == (bits != 64), sched
+        got = to_host(out)
+        assert int(tot.item()) == wtot
+        assert np.array_equal(got[: want.size], want), (bits, first_diff(got[: want.size], want))
+
+
+def test_float_storage_refused_where_unbounded(ctx):
+    """Float storage is refused with a shared seed and above L = 2^18 (host
+    error SSBH_E_UNSUPPORTED), and the setter takes only 0, 32 and 64."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    with pytest.raises(ssbh.SsbhError) as e:
+        ctx.set_fft_storage(16)
+    assert e.value.status == ssbh.E_INVAL
+    n, ns = 4096, 4
+    sub = to_dev(uniform_bits(n, 1))
+    ln = torch.full((ns,), n // ns, dtype=torch.int64, device="cuda")
+    wo = torch.arange(ns, dtype=torch.int64, device="cuda") * (n // ns // 64)
+    seed = to_dev(uniform_bits(ns * ((1 << 18) + 1), 2))
+    ctx.set_fft_storage(32)
+    try:
+        for stride, seed_bits in ((0, 2000), ((1 << 18) + 1, ns * ((1 << 18) + 1))):
+            with pytest.raises(ssbh.SsbhError) as e:
+                ctx.hash_batch(sub, sub.numel(), ln, wo, ns, seed, seed_bits, 100,
+                               out_rule=ssbh.OUT_FIXED, out_a=100,
+                               seed_stride=stride, kernel=ssbh.K_FFT)
+            assert e.value.status == ssbh.E_UNSUPPORTED, stride
+    finally:
+        ctx.set_fft_storage(0)
