@@ -145,6 +145,8 @@ FUSED_CASES = [  # (n_sub, L, out rule, a, b, independent seeds)
     (1, 4097, 0, 640, 1, False),            # one sub-block, ragged length
     (16, 1600, 1, 2, 5, True),              # ratio rule: m = 640
     (7, 33, 0, 64, 1, True),                # m > n
+    (5, 1 << 16, 0, 128, 1, True),          # input of 5 * 2^16 bits
+    (2, 1 << 16, 0, 40960, 1, False),       # 80 row tiles a sub-block
 ]
 
 
