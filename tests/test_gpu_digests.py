@@ -43,14 +43,14 @@ def digest(t, bits: int) -> str:
     return hashlib.sha256(w.astype("<u8").tobytes()).hexdigest()
 
 
-def fft_chunks(seed_bits: int, m_cap: int):
+def fft_chunks(seed_bits: int, m_cap: int, point_bytes: int = 16):
     """Transform counts of the tuner's FFT chunk sizes at this seed length:
     L = the smallest 2^k or 3 * 2^k >= seed_bits (4096 <= L; 6144 is not
-    used), 16 bytes per point."""
+    used), 16 bytes per point (8 where the passes exchange floats)."""
     lengths = sorted(v for k in range(12, 32) for v in (1 << k, 3 << k)
                      if v != 6144)
     L = next(v for v in lengths if v >= max(seed_bits, 4096))
-    return sorted({max(1, (mib << 20) // (16 * L)) for mib in FFT_MIB})
+    return sorted({max(1, (mib << 20) // (point_bytes * L)) for mib in FFT_MIB})
 
 
 def run_all(ctx, hash_, seed_bits, cap, want, bits, with_valu=True):
@@ -153,8 +153,9 @@ def test_batched_whole_output(ctx):
 
 def test_batched_independent_whole_output(ctx):
     """The batched workload with the paper's independent seeds (stride
-    max n_j + max m_j - 1): the FFT at every chunk size the tuner tries and
-    the VALU kernel give the oracle's whole output."""
+    max n_j + max m_j - 1): the FFT at every chunk size the tuner tries
+    (floats between the passes, the library's choice at this length, and
+    doubles) and the VALU kernel give the oracle's whole output."""
     import torch
     from paper_2308_02856_amd import ssbh
     ref = reference("batched_independent")
@@ -189,11 +190,16 @@ def test_batched_independent_whole_output(ctx):
         return out
 
     bad = []
-    for cp in fft_chunks(stride, cap):
-        ctx.set_fft_schedule(cp)
-        if digest(hash_(ssbh.K_FFT), out_cap) != ref["sha256"]:
-            bad.append(f"fft:{cp}")
-    ctx.set_fft_schedule(0)
+    for bits, pb in ((0, 8), (64, 16)):
+        ctx.set_fft_storage(bits)
+        try:
+            for cp in fft_chunks(stride, cap, pb):
+                ctx.set_fft_schedule(cp)
+                if digest(hash_(ssbh.K_FFT), out_cap) != ref["sha256"]:
+                    bad.append(f"fft:{cp}:storage{bits}")
+        finally:
+            ctx.set_fft_schedule(0)
+            ctx.set_fft_storage(0)
     if digest(hash_(ssbh.K_VALU), out_cap) != ref["sha256"]:
         bad.append("valu")
     assert not bad, bad
