@@ -544,8 +544,9 @@ ssbh_status ssbh_set_fft_packing(ssbh_ctx *ctx, int per_part);
  * library choice (floats with a seed stride S > 0 and a transform length of
  * at most 2^18, else doubles).  Floats are allowed only there: elsewhere the
  * hash returns SSBH_E_UNSUPPORTED.  There, rounding both intermediates to
- * float moves each entry s_j * xr_j by less than 5 * 2^-24 * (n_j + n_j +
- * m_cap - 1) < 5/32, below the 1/4 every entry is checked for.  For tests
+ * float moves each entry s_j * xr_j by less than 5 * 2^-24 * (L + n_j)
+ * < 5/32 (L seed bits in the real part, n_j input bits in the imaginary
+ * part), below the 1/4 every entry is checked for.  For tests
  * and tuning of the synchronous entry points (serving takes the library
  * choice); the output bits do not depend on it.  bits outside {0, 32, 64}:
  * SSBH_E_INVAL. */

@@ -1166,7 +1166,8 @@ uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib, uint64_t point_bytes) {
 // (a column's 64 entries of Y2 are L/64 times the DFT of 64 entries of c,
 // each at most |z|^2 in size).  The entry s_j * xr_j is half the imaginary
 // part, so its error stays below 5 u |z|^2 + (double rounding), and
-// |z|^2 <= n_j + (n_j + m_cap - 1) < 2 L: at L = 2^18 that is 5/32 < 1/4,
+// |z|^2 <= L + n_j < 2 L (L seed bits in the real part, n_j input bits in
+// the imaginary part): at L = 2^18 that is 5/32 < 1/4,
 // the distance every entry is checked for.  With a shared seed the second
 // sub-block of a part is scaled by 2^18, far beyond what floats carry.
 constexpr uint64_t kNarrowMaxLength = 1ull << 18;

@@ -559,8 +559,9 @@ def _all_ones_subs(lens):
 
 def test_float_storage_worst_case_all_ones(ctx):
     """Independent seeds at the longest transform that keeps complex floats
-    between the passes (L = 2^18), with every seed and input bit set: the
-    largest |z|^2 = n_j + (n_j + m - 1) the rounding bound covers.  Every
+    between the passes (L = 2^18), with every seed and input bit set: |z|^2
+    = L + n_j (the real part holds L seed bits), near the 2 L the rounding
+    bound covers.  Every
     entry of T_j x_j is then n_j, so every output bit of sub-block j is
     n_j mod 2; the float and double storage give exactly that."""
     import torch
