@@ -480,8 +480,10 @@ ssbh_status ssbh_tune_table(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* The kernel and schedule that the last ssbh_hash_batch or ssbh_tune call on
  * this context launched, as "valu:R:waves:chunk_cols:tile_cols" or
- * "mfma:MT:NT:WM:ksplit" (ksplit 0 = automatic) or "fft:chunk:L<length>"
- * (empty before the first call; truncated to len). */
+ * "mfma:MT:NT:WM:ksplit" (ksplit 0 = automatic) or
+ * "fft:chunk:x<sub-blocks per transform>:L<length>", with ":f32" appended
+ * when the passes exchange complex floats (empty before the first call;
+ * truncated to len). */
 ssbh_status ssbh_last_schedule(ssbh_ctx *ctx, char *buf, uint64_t len);
 
 /* Force the schedule of the VALU hash kernel for later calls on this
@@ -526,9 +528,10 @@ ssbh_status ssbh_timing_report(ssbh_ctx *ctx, char *buf, uint64_t len);
 ssbh_status ssbh_set_sample_path(ssbh_ctx *ctx, int path);
 
 /* Force the FFT hash's chunk: transforms per pass (each holds two or four
- * sub-blocks with a shared seed and takes L complex doubles of scratch, at
- * most 512 MiB per pass; 0 = library choice).  The output bits do not
- * depend on it. */
+ * sub-blocks with a shared seed, one with a seed stride, and takes L complex
+ * doubles, or complex floats (ssbh_set_fft_storage), of scratch, at most
+ * 512 MiB per pass; 0 = library choice).  The output bits do not depend on
+ * it. */
 ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs);
 
 /* Force how many sub-blocks share each real and imaginary part of an FFT
