@@ -168,7 +168,8 @@ def run_batched(ctx, ssbh, args):
         tune_report = ctx.tune(sub, sub_cap, ln, wo, ns, seed, seed_bits, cap,
                                out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
                                out_b=c["out_b"], out=out,
-                               out_capacity_bits=out_cap, total=tot, status=st)
+                               out_capacity_bits=out_cap, total=tot, status=st,
+                               reps=5)
 
     def sample():
         ctx.sample(d_in, n, ns, ssbh.SAMPLE_IID, key=key, l_ub=l_ub, sub=sub,
@@ -339,7 +340,8 @@ def run_batched_independent(ctx, ssbh, args, res):
         tune_report = ctx.tune(sub, sub.numel(), ln, wo, ns, seed, seed_bits,
                                cap, out_rule=ssbh.OUT_RATIO, out_a=c["out_a"],
                                out_b=c["out_b"], seed_stride=stride, out=out,
-                               out_capacity_bits=out_cap, total=tot, status=st)
+                               out_capacity_bits=out_cap, total=tot, status=st,
+                               reps=5)
     hash_(kern, out)
     hash_(ssbh.K_VALU, outv)
     torch.cuda.synchronize()

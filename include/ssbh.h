@@ -453,8 +453,8 @@ ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
  * candidate kernel and schedule (bit-sliced VALU schedules, FFT chunks of
  * 64 .. 256 MiB of transforms (two chunks in flight on two streams), and
  * int8 matrix-core schedules when the seed
- * is shared), `reps` timed runs each with HIP events,
- * and remember the fastest for the shape bucket of these arguments (seed
+ * is shared), `reps` timed runs each with HIP events (after one untimed
+ * run; their median counts), and remember the fastest for the shape bucket of these arguments (seed
  * sharing, log2 of n_sub, m_cap and mean sub-block words).  Later calls with
  * kernel = SSBH_K_AUTO in the same bucket use it; without a tuned entry AUTO
  * picks the FFT when n * m_cap >= 1024 L log2 L / k, with n = seed_bits + 1

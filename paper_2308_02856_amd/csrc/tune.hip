@@ -133,7 +133,7 @@ ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,
     std::string table;
     if (!reps) reps = 2;
     for (const Candidate &c : candidates(ctx, q)) {
-        float tot = 0.f;
+        std::vector<float> times;
         ssbh_status rc = SSBH_OK;
         for (uint32_t k = 0; k <= reps && rc == SSBH_OK; ++k) {
             (void)hipEventRecord(e0, st);
@@ -146,7 +146,7 @@ ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (k) tot += ms;          // the first run warms up
+            if (k) times.push_back(ms);   // the first run warms up
         }
         SSBH_CHECK_HIP(hipMemcpyAsync(&h_status, d_status, 4,
                                       hipMemcpyDeviceToHost, st));
@@ -160,7 +160,12 @@ ssbh_status ssbh_tune(ssbh_ctx *ctx, const uint64_t *d_sub,
                 break;              // a device-side argument error: stop
             }
         } else {
-            const float ms = tot / reps;
+            // The median of the timed runs: one slow run (another process,
+            // a clock change) does not decide the choice.
+            std::sort(times.begin(), times.end());
+            const size_t h = times.size() / 2;
+            const float ms = times.size() % 2 ? times[h]
+                                               : 0.5f * (times[h - 1] + times[h]);
             snprintf(line, sizeof line, "%-24s %10.3f ms\n", c.name.c_str(), ms);
             if (ms < best_ms) { best_ms = ms; best = c.name; }
         }

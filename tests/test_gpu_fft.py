@@ -84,8 +84,11 @@ def test_uneven_blocks_match_oracle_valu_and_mfma(ctx, orc, N, ns, chunk):
         assert np.array_equal(to_host(out), got), kern
 
 
-def test_empty_and_degenerate_sub_blocks(ctx, orc):
-    """Empty sub-blocks, m_j = 0 and m_j > n_j, from explicit lengths."""
+@pytest.mark.parametrize("indep", [False, True])
+def test_empty_and_degenerate_sub_blocks(ctx, orc, indep):
+    """Empty sub-blocks, m_j = 0 and m_j > n_j, from explicit lengths, with
+    a shared seed and with independent seeds (complex floats between the
+    passes at this length)."""
     import torch
     from paper_2308_02856_amd import ssbh
     lens = np.array([0, 5, 64, 0, 1000, 3, 700], dtype=np.uint64)
@@ -98,14 +101,18 @@ def test_empty_and_degenerate_sub_blocks(ctx, orc):
         if r and words[j]:
             sub[int(wo[j] + words[j] - 1)] &= np.uint64((1 << r) - 1)
     cap = int(outl.max())
-    seed_bits = int(lens.max()) + cap - 1
-    seed = uniform_bits(seed_bits, 6)
     ns = len(lens)
+    stride = int(lens.max()) + cap - 1 if indep else 0
+    seed_bits = ns * stride if indep else int(lens.max()) + cap - 1
+    seed = uniform_bits(seed_bits, 6)
     dl = torch.from_numpy(outl.view(np.int64)).cuda()
     got, tot = fft_hash(ctx, to_dev(sub), to_dev(lens), to_dev(wo), ns,
                         to_dev(seed), seed_bits, cap,
-                        out_rule=ssbh.OUT_EXPLICIT, out_len=dl)
-    want, wtot = orc.hash_batch(sub, lens, wo, outl, seed, seed_bits, 0, cap)
+                        out_rule=ssbh.OUT_EXPLICIT, out_len=dl,
+                        seed_stride=stride)
+    if indep:
+        assert ctx.last_schedule().endswith(":f32")
+    want, wtot = orc.hash_batch(sub, lens, wo, outl, seed, seed_bits, stride, cap)
     assert tot == wtot
     assert np.array_equal(got[: want.size], want)
 
