@@ -94,8 +94,11 @@ enum {
                                  (imaginary), squared pointwise; needs every
                                  n_j + m_cap - 1 <= the transform length of
                                  S (true when S >= n_max + m_cap - 1), else
-                                 *d_status = SSBH_E_UNSUPPORTED.  Transform
-                                 lengths up to 2^18 keep the data between
+                                 *d_status = SSBH_E_UNSUPPORTED.  A single
+                                 sub-block with a shared seed takes the same
+                                 one-transform form (no seed spectrum)
+                                 unless packing is forced.  Such transforms
+                                 up to 2^18 points keep the data between
                                  passes as complex floats (arithmetic in
                                  double; error bound below the 1/4 checked,
                                  see ssbh_set_fft_storage)                  */
@@ -538,15 +541,17 @@ ssbh_status ssbh_set_fft_schedule(ssbh_ctx *ctx, uint32_t chunk_pairs);
  * transform with a shared seed: 1 (two per transform), 2 (four: the second
  * scaled by 2^18, needs seed_bits + 1 - m_cap < 2^18 and a transform
  * length of at most 2^20, else the hash returns SSBH_E_UNSUPPORTED), or 0 =
- * library choice (2 when allowed).  For tests and tuning; the output bits
+ * library choice (2 when allowed; a single sub-block takes one transform
+ * carrying its seed and its bits instead).  For tests and tuning; the output bits
  * do not depend on it. */
 ssbh_status ssbh_set_fft_packing(ssbh_ctx *ctx, int per_part);
 
 /* Force the FFT hash's storage of transform data between its passes: 64 =
  * complex doubles, 32 = complex floats (arithmetic stays double), 0 =
- * library choice (floats with a seed stride S > 0 and a transform length of
- * at most 2^18, else doubles).  Floats are allowed only there: elsewhere the
- * hash returns SSBH_E_UNSUPPORTED.  There, rounding both intermediates to
+ * library choice (floats for one sub-block per transform -- a seed stride
+ * S > 0, or a single sub-block without forced packing -- and a transform
+ * length of at most 2^18, else doubles).  Floats are allowed only there:
+ * elsewhere the hash returns SSBH_E_UNSUPPORTED.  There, rounding both intermediates to
  * float moves each entry s_j * xr_j by less than 5 * 2^-24 * (L + n_j)
  * < 5/32 (L seed bits in the real part, n_j input bits in the imaginary
  * part), below the 1/4 every entry is checked for.  For tests

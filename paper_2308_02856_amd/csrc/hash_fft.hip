@@ -38,8 +38,11 @@
 // so squaring the spectrum pointwise (no second spectrum, no pairing of the
 // frequencies k and L - k) and inverting gives 2 (s_j * xr_j) as the
 // imaginary part: one transform per sub-block, no separate seed spectra.
-// The seed spectrum comes from the same forward passes.  LDS FFTs are
-// Stockham autosort stages with radix-8 (columns) or radix-16 (rows)
+// A single sub-block with a shared seed (S = 0, j = 0) takes the same joint
+// transform: one transform instead of the seed spectrum's forward passes
+// plus a transform of the sub-block.  With a shared seed and several
+// sub-blocks the seed spectrum comes from the same forward passes.
+// LDS FFTs are Stockham autosort stages with radix-8 (columns) or radix-16 (rows)
 // butterflies in registers, then one smaller stage for the rest of the
 // length; one twiddle-table read per butterfly group, the other powers by
 // squaring and products.  The first stage of each pass reads global memory
@@ -1156,8 +1159,8 @@ uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib, uint64_t point_bytes) {
     return (uint32_t)std::max<uint64_t>(1, (mib << 20) / (L * point_bytes));
 }
 
-// Complex floats between the passes (8 bytes a point instead of 16) with
-// independent seeds and L <= 2^18.  Rounding the column pass's output Y1 and
+// Complex floats between the passes (8 bytes a point instead of 16) for the
+// joint transform (independent seeds, or a single sub-block) and L <= 2^18.  Rounding the column pass's output Y1 and
 // the row pass's output Y2 to float (relative error u = 2^-24 per entry)
 // moves the result c = z (*) z of the transform of z = s_j + i xr_j by at
 // most (2u + u^2) |z|^2 through Y1 (the spectrum error, sqrt(L) u |z|_2 in
@@ -1172,7 +1175,8 @@ uint32_t fft_chunk_of_bytes(uint64_t L, uint64_t mib, uint64_t point_bytes) {
 // sub-block of a part is scaled by 2^18, far beyond what floats carry.
 constexpr uint64_t kNarrowMaxLength = 1ull << 18;
 bool fft_narrow(const HashRequest &q, uint64_t L, int storage) {
-    return storage != 64 && q.stride != 0 && L <= kNarrowMaxLength;
+    return storage != 64 && (q.stride != 0 || q.n_sub == 1) &&
+           L <= kNarrowMaxLength;
 }
 uint64_t fft_point_bytes(const HashRequest &q, uint64_t L, int storage) {
     return fft_narrow(q, L, storage) ? sizeof(float2) : sizeof(double2);
@@ -1182,9 +1186,12 @@ bool fft_can_pack(const HashRequest &q, uint64_t L) {
     return q.stride == 0 && q.seed_bits + 1 < q.m_cap + (1ull << kPackBits) &&
            L <= (1ull << 20);
 }
+// One sub-block per transform (the joint transform) with a seed stride, and
+// for a single sub-block with a shared seed unless packing is forced.
 int fft_per_transform(const ssbh_ctx *ctx, const HashRequest &q, uint64_t L) {
     if (q.stride) return 1;
     if (ctx->forced_fft_pack) return 2 * ctx->forced_fft_pack;
+    if (q.n_sub == 1) return 1;
     return fft_can_pack(q, L) ? 4 : 2;
 }
 
@@ -1205,13 +1212,16 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     // context's own workspace, which hold its lock, use them (a pipeline's
     // eager run and serving jobs have workspaces of their own).
     const bool may_fork = s.overlap && &ws == &ctx->ws && !ws.timer;
-    const bool joint = q.stride != 0;   // independent seeds: seed and data in one transform
-    if (s.storage == 32 && !fft_narrow(q, L, 32)) {
-        set_error("float transform storage needs a seed stride and a transform "
+    const int per = fft_per_transform(ctx, q, L);
+    // Seed and data in one transform (see the top of the file).
+    const bool joint = per == 1;
+    if (s.storage == 32 && !(joint && L <= kNarrowMaxLength)) {
+        set_error("float transform storage needs one sub-block per transform "
+                  "(a seed stride, or a single sub-block) and a transform "
                   "length of at most 2^18");
         return SSBH_E_UNSUPPORTED;
     }
-    const bool narrow = fft_narrow(q, L, s.storage);
+    const bool narrow = joint && L <= kNarrowMaxLength && s.storage != 64;
     const uint64_t pb = narrow ? sizeof(float2) : sizeof(double2);
     // Default chunk: 96 MiB of transforms when two are in flight (both fit
     // the 256 MB last-level cache), else 160 MiB.
@@ -1220,7 +1230,6 @@ ssbh_status launch_hash_fft(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
     // At most 512 MiB of transforms per chunk.
     chunk = (uint32_t)std::max<uint64_t>(
         1, std::min<uint64_t>(chunk, (1ull << 29) / (L * pb)));
-    const int per = fft_per_transform(ctx, q, L);
     if (per == 4 && !fft_can_pack(q, L)) {
         set_error("four sub-blocks per transform need a shared seed, "
                   "seed_bits + 1 - m_cap < 2^18 and L <= 2^20");

@@ -662,3 +662,56 @@ def test_float_storage_refused_where_unbounded(ctx):
             assert e.value.status == ssbh.E_UNSUPPORTED, stride
     finally:
         ctx.set_fft_storage(0)
+
+
+@pytest.mark.parametrize("n,m,ones", [(100000, 40000, False), (1 << 18, 1 << 17, False),
+                                      ((1 << 18) - 4095, 4096, True)])
+def test_single_sub_block_joint_transform(ctx, orc, n, m, ones):
+    """One sub-block with a shared seed takes the joint transform (seed real,
+    bits imaginary, one transform, no seed spectrum; complex floats between
+    the passes up to L = 2^18): equal to the packed two-per-transform layout
+    (forced) and to the oracle bit for bit; with every bit set (ones) each
+    output bit is n mod 2."""
+    import torch
+    from paper_2308_02856_amd import ssbh
+    seed_bits = n + m - 1
+    if ones:
+        x = np.full((n + 63) // 64, np.uint64(0xFFFFFFFFFFFFFFFF), dtype=np.uint64)
+        seed = np.full((seed_bits + 63) // 64, np.uint64(0xFFFFFFFFFFFFFFFF),
+                       dtype=np.uint64)
+        if seed_bits % 64:
+            seed[-1] = np.uint64((1 << (seed_bits % 64)) - 1)
+    else:
+        x = bernoulli_bits(((n + 63) // 64) * 64, 0.5, n)
+        seed = uniform_bits(seed_bits, m)
+    if n % 64:
+        x[-1] &= np.uint64((1 << (n % 64)) - 1)
+    lens = np.array([n], dtype=np.uint64)
+    wo = np.array([0], dtype=np.uint64)
+    args = (to_dev(x), x.size, to_dev(lens), to_dev(wo), 1, to_dev(seed),
+            seed_bits, m)
+    kw = dict(out_rule=ssbh.OUT_FIXED, out_a=m, kernel=ssbh.K_FFT)
+    outs = {}
+    for pack in (0, 1):
+        ctx.set_fft_packing(pack)
+        try:
+            out, tot, st = ctx.hash_batch(*args, **kw)
+            torch.cuda.synchronize()
+            sched = ctx.last_schedule()
+        finally:
+            ctx.set_fft_packing(0)
+        assert int(st.item()) == 0, ssbh.status_name(int(st.item()))
+        assert int(tot.item()) == m
+        assert (":x1:" if pack == 0 else ":x2:") in sched, sched
+        if pack == 0:
+            assert sched.endswith(":f32") == (int(sched.split(":L")[1].split(":")[0]) <= 1 << 18)
+        outs[pack] = to_host(out)
+    assert np.array_equal(outs[0], outs[1]), first_diff(outs[0], outs[1])
+    if ones:
+        bits = np.unpackbits(outs[0].view(np.uint8), bitorder="little")[:m]
+        assert np.all(bits == (n & 1))
+    else:
+        want, wtot = orc.hash_batch(x, lens, wo, np.array([m], np.uint64),
+                                    seed, seed_bits, 0, m)
+        assert wtot == m
+        assert np.array_equal(outs[0][: want.size], want), first_diff(outs[0][: want.size], want)
