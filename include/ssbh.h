@@ -463,7 +463,7 @@ ssbh_status ssbh_serve_counts(ssbh_ctx *ctx, uint64_t *pending,
  * picks the FFT when n * m_cap >= 1024 L log2 L / k, with n = seed_bits + 1
  * - m_cap (shared seed) or S + 1 - m_cap (seed stride S), L the transform
  * length and k the sub-blocks per transform (4 or 2 for a shared seed, 1
- * with a stride); else the matrix cores for a shared seed and n_sub >= 64;
+ * with a stride or a single sub-block); else the matrix cores for a shared seed and n_sub >= 64;
  * the VALU kernel in every other case.  Blocks until the stream is idle; d_out holds a valid result
  * afterwards.  If report is non-null, a text table of the timings is written
  * (truncated to report_len bytes). */

@@ -206,7 +206,9 @@ bool fft_pays(const HashRequest &q) {
     if (L > kMaxFftLength || span + 1 <= q.m_cap) return false;
     const double n = (double)(span + 1 - q.m_cap);
     const double m = (double)q.m_cap;
-    const double per = q.stride ? 1.0 : fft_can_pack(q, L) ? 4.0 : 2.0;
+    // Sub-blocks per transform: one with a stride or a single sub-block
+    // (the joint transform), else four or two.
+    const double per = (q.stride || q.n_sub == 1) ? 1.0 : fft_can_pack(q, L) ? 4.0 : 2.0;
     return n * m >= 1024.0 / per * (double)L * std::log2((double)L);
 }
 
