@@ -70,6 +70,23 @@ def test_fft_hash_bytes_follow_the_passes():
     assert r2["frac"] == round(r2["achieved"] / bench.HBM_PEAK_GBS, 4)
 
 
+def test_fft_schedule_strings_with_float_storage():
+    """Schedule names carry the transform length, the sub-blocks per
+    transform and, with complex floats between the passes, ":f32" (8 bytes a
+    point): the whole-hash bytes halve the transform traffic then."""
+    assert bench.fft_schedule_parts("fft:42:x4:L196608") == (196608, 4, 16)
+    assert bench.fft_schedule_parts("fft:0:x1:L196608:f32") == (196608, 1, 8)
+    assert bench.fft_schedule_parts("fft:0:x1:L2147483648") == (1 << 31, 1, 16)
+    L, ns, n_bits, out_bits = 196608, 6, 1000, 64
+    r16 = bench.fft_hash_roofline(f"fft:0:x1:L{L}", ns, n_bits, out_bits, 1.0,
+                                  False, 0)
+    r8 = bench.fft_hash_roofline(f"fft:0:x1:L{L}:f32", ns, n_bits, out_bits,
+                                 1.0, False, 0)
+    rest = n_bits // 8 + 3 * out_bits // 8
+    assert r16["algorithmic_bytes_per_hash"] == ns * 64 * L + rest
+    assert r8["algorithmic_bytes_per_hash"] == ns * 32 * L + rest
+
+
 def test_digest_file_is_complete():
     with open(os.path.join(HERE, "golden", "digests.json")) as fh:
         d = json.load(fh)
