@@ -223,10 +223,13 @@ def test_batched_workload_fft_equals_mfma(ctx, orc):
         assert ((int(got[k >> 6]) >> (k & 63)) & 1) == want, (j, r)
 
 
-def test_fft_graph_pipeline_replays(ctx, orc):
+@pytest.mark.parametrize("n,ns", [((1 << 19) + 3, 40), (150001, 1)])
+def test_fft_graph_pipeline_replays(ctx, orc, n, ns):
+    """Sampling and the FFT hash captured in a graph: every replay gives the
+    oracle's output (40 sub-blocks with a shared seed: the packed layout;
+    one sub-block: the joint transform with floats between the passes)."""
     import torch
     from paper_2308_02856_amd import ssbh
-    n, ns = (1 << 19) + 3, 40
     a = bernoulli_bits(n, 0.5, 91)
     key = 0x99
     osub, oln, owo, _ = orc.sample(a, n, ns, orc.SAMPLE_IID, key=key)
