@@ -325,6 +325,12 @@ void k_toeplitz_mfma(MfmaArgs a) {
 // tile p at step s is the 32-bit seed window W(2s + h - p); a ring of MT
 // windows indexed by 2s - p (uniform across lanes) gets two new entries per
 // step, W(2s + h) and W(2s - 1 + h).
+// Bits become codes once per workgroup, when a chunk is staged: each 32-bit
+// word of the sub-blocks and of the seed window is stored in LDS as the four
+// registers of its nibble codes (byte d -> register d).  A wave then reads a
+// B operand as one 16-byte LDS load, and a seed window that starts at bit b
+// as the five code registers from b / 8 on, joined by four funnel shifts of
+// 4 (b mod 8) bits; no wave expands bits in its step loop.
 __device__ __forceinline__ uint32_t spread8(uint32_t b) {   // bit i -> code 2
     uint32_t t = b & 0xFFu;
     t = (t | (t << 12)) & 0x000F000Fu;
@@ -350,10 +356,14 @@ void k_toeplitz_mfma_f4(MfmaArgs a) {
     constexpr int WINW = TT::WINW, PFX = TT::PFX, PFW = TT::PFW;
     constexpr int OBW = TT::OBW;
     constexpr int U = MT / 2;                 // steps per ring turn
+    // Code registers per sub-block row: 4 per word, padded by 4 so that the
+    // 16-byte loads of 16 consecutive lanes (rows) cover all banks.
+    constexpr int XS4 = 4 * kKCW + 4;
+    (void)XS;
     static_assert(BN * kKCW % NTH == 0, "staging must divide evenly");
-    static_assert(OBW <= XS, "epilogue image must fit the staging area");
-    __shared__ uint32_t xs[BN * XS];
-    __shared__ uint32_t win[WINW];
+    static_assert(OBW <= XS4, "epilogue image must fit the staging area");
+    __shared__ __align__(16) uint32_t xs4[BN * XS4];
+    __shared__ __align__(16) uint32_t winx[4 * WINW];
     __shared__ uint64_t woff_s[BN], mlen_s[BN], ooff_s[BN];
     __shared__ uint32_t nw_s[BN], tail_s[BN];
     __shared__ uint64_t nmax_s, mmax_s;
@@ -440,46 +450,86 @@ void k_toeplitz_mfma_f4(MfmaArgs a) {
         for (int i = 0; i < PFX; ++i) {
             const int t = threadIdx.x + i * NTH;
             const int jl = t / kKCW, w = t - jl * kKCW;
-            xs[jl * XS + w] = pfx[i];
+            *reinterpret_cast<v4i *>(&xs4[jl * XS4 + 4 * w]) = expand32_f4(pfx[i]);
         }
 #pragma unroll
         for (int i = 0; i < PFW; ++i) {
             const int t = threadIdx.x + i * NTH;
-            if (t < WINW) win[t] = pfw[i];
+            if (t < WINW) *reinterpret_cast<v4i *>(&winx[4 * t]) = expand32_f4(pfw[i]);
         }
         const int64_t lo_w = window_lo(cw0);
         __syncthreads();
         if (cw0 + kKCW < cw_end) prefetch(cw0 + kKCW);
 
         // Seed window W(t) for this lane's row at tile 0: bits at column
-        // 32 cw0 + 32 t of the chunk.
+        // 32 cw0 + 32 t of the chunk, that is bits 32 (qa + t) + sha .. +31
+        // of the staged window: code registers from 4 (qa + t) + sha / 8 on,
+        // shifted by 4 (sha mod 8) bits.
         const int64_t e = 32 * (int64_t)cw0 - (R0w + li) + (int64_t)a.mcap - 1 -
                           (lo_w << 5);
         const int qa = (int)(e >> 5);
         const uint32_t sha = (uint32_t)(e & 31);
-        auto W = [&](int tt) {
-            return expand32_f4(__builtin_amdgcn_alignbit(win[qa + tt + 1],
-                                                         win[qa + tt], sha));
+        const int cq = (int)(sha >> 3);
+        const uint32_t sh4 = 4u * (sha & 7u);
+        const uint32_t words = min((uint32_t)kKCW, cw_end - cw0);
+        const uint32_t steps = ((words + 1) / 2 + U - 1) / U * U;
+        // The LDS words of one step's operands: the five code registers of
+        // each new seed window (W(2s + h), W(2s - 1 + h)) and the B codes.
+        uint32_t rw[2][5];
+        v4i rb[NT];
+        auto load = [&](uint32_t s) {
+            // Step s' <= steps - 1 keeps every LDS read inside its row; the
+            // operands loaded for the step after the last are never used.
+            const uint32_t sc = min(s, steps - 1);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t *c = winx + 4 * (qa + 2 * (int)sc - k + h) + cq;
+#pragma unroll
+                for (int d = 0; d < 5; ++d) rw[k][d] = c[d];
+            }
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                rb[q] = *reinterpret_cast<const v4i *>(
+                    &xs4[(32 * q + li) * XS4 + 4 * (2 * sc + h)]);
+        };
+        // W(t) from its five code registers: four funnel shifts.
+        auto window = [&](const uint32_t (&c)[5]) {
+            v4i r;
+            r.x = (int)__builtin_amdgcn_alignbit(c[1], c[0], sh4);
+            r.y = (int)__builtin_amdgcn_alignbit(c[2], c[1], sh4);
+            r.z = (int)__builtin_amdgcn_alignbit(c[3], c[2], sh4);
+            r.w = (int)__builtin_amdgcn_alignbit(c[4], c[3], sh4);
+            return r;
         };
         if (cw0 == cw_begin) {
             // Slots -2 .. -(MT-1): W(h - p) for tiles p = 2 .. MT-1 at step 0.
 #pragma unroll
-            for (int p = 2; p < MT; ++p) ring[MT - p] = W(h - p);
-        }
-        const uint32_t words = min((uint32_t)kKCW, cw_end - cw0);
-        const uint32_t steps = ((words + 1) / 2 + U - 1) / U * U;
-        v4i a0_next, a1_next, b_next[NT];
-        auto build = [&](uint32_t s, v4i &a0, v4i &a1, v4i (&bn)[NT]) {
-            // Step s' <= steps - 1 keeps every LDS read inside its row; the
-            // operands built for the step after the last are never used.
-            const uint32_t sc = min(s, steps - 1);
-            a0 = W(2 * (int)sc + h);
-            a1 = W(2 * (int)sc - 1 + h);
+            for (int p = 2; p < MT; ++p) {
+                uint32_t c[5];
+                const uint32_t *src = winx + 4 * (qa + h - p) + cq;
 #pragma unroll
-            for (int q = 0; q < NT; ++q)
-                bn[q] = expand32_f4(xs[(32 * q + li) * XS + 2 * sc + h]);
+                for (int d = 0; d < 5; ++d) c[d] = src[d];
+                ring[MT - p] = window(c);
+            }
+        }
+        load(0);
+        v4i a0_next = window(rw[0]), a1_next = window(rw[1]), b_next[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) b_next[q] = rb[q];
+        auto mfma_tiles = [&](int u, int p0, int p1, const v4i (&bcur)[NT]) {
+#pragma unroll
+            for (int p = p0; p < p1; ++p) {
+                const v4i ar = ring[(2 * u - p + 2 * MT) % MT];
+                v8i A8 = {ar.x, ar.y, ar.z, ar.w, 0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    v8i B8 = {bcur[q].x, bcur[q].y, bcur[q].z, bcur[q].w,
+                              0, 0, 0, 0};
+                    acc[p][q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        A8, B8, acc[p][q], 4, 4, 0, 127, 0, 127);
+                }
+            }
         };
-        build(0, a0_next, a1_next, b_next);
         for (uint32_t s0 = 0; s0 < steps; s0 += U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -489,31 +539,25 @@ void k_toeplitz_mfma_f4(MfmaArgs a) {
                 v4i bcur[NT];
 #pragma unroll
                 for (int q = 0; q < NT; ++q) bcur[q] = b_next[q];
-                build(s + 1, a0_next, a1_next, b_next);
+                // The next step's LDS loads go out before this step's first
+                // matrix ops and are shifted into operands halfway through,
+                // so their latency hides behind the matrix cores.
+                load(s + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_tiles(u, 0, MT / 2, bcur);
+                __builtin_amdgcn_sched_barrier(0);
+                a0_next = window(rw[0]);
+                a1_next = window(rw[1]);
 #pragma unroll
-                for (int p = 0; p < MT; ++p) {
-                    const v4i ar = ring[(2 * u - p + 2 * MT) % MT];
-                    v8i A8 = {ar.x, ar.y, ar.z, ar.w, 0, 0, 0, 0};
-#pragma unroll
-                    for (int q = 0; q < NT; ++q) {
-                        v8i B8 = {bcur[q].x, bcur[q].y, bcur[q].z, bcur[q].w,
-                                  0, 0, 0, 0};
-                        acc[p][q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            A8, B8, acc[p][q], 4, 4, 0, 127, 0, 127);
-                    }
-                }
-                __builtin_amdgcn_sched_group_barrier(0x100, 1 + NT, 0);
-#pragma unroll
-                for (int k = 0; k < MT * NT; ++k) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
-                }
+                for (int q = 0; q < NT; ++q) b_next[q] = rb[q];
+                mfma_tiles(u, MT / 2, MT, bcur);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         __syncthreads();
     }
 
-    uint32_t *ob = xs;
+    uint32_t *ob = xs4;
 #pragma unroll
     for (int p = 0; p < MT; ++p) {
 #pragma unroll
