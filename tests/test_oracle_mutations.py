@@ -136,3 +136,114 @@ def test_permutation_pins_reject_planted_mistake(tmp_path, name, old, new):
             mod, 4, 6000),
     ]
     assert any(fails(c) for c in checks), name
+
+
+# ------------------------------------- Toeplitz, sampling, concatenation ---
+
+def fails_any(fn) -> bool:
+    """True when a pin rejects the copy: a failed assertion, or an error
+    the copy's wrong arithmetic provokes (a refused argument, say)."""
+    try:
+        fn()
+    except Exception:
+        return True
+    return False
+
+
+def toeplitz_pins(mod):
+    return [
+        lambda: pins.test_toeplitz_exhaustive_tiny_against_clmul(mod),
+        lambda: pins.test_toeplitz_against_fft_and_clmul(mod, 100, 37),
+        lambda: pins.test_toeplitz_closed_forms(mod),
+        lambda: pins.test_toeplitz_ignores_input_bits_past_n(mod),
+        lambda: pins.test_row_functions_agree_with_block(mod),
+    ]
+
+
+def sampling_pins(mod):
+    return [
+        lambda: pins.test_partition_equals_boolean_selection(mod, 10007, 13),
+        lambda: pins.test_partition_equals_boolean_selection(mod, 5000, 2048),
+        lambda: pins.test_sample_iid_is_partition_by_splitmix_assignment(mod),
+    ]
+
+
+def sifting_pins(mod):
+    return [lambda: pins.test_sift_equals_selection_by_v_and_keep(
+        mod, 5000, 7, 0.6)]
+
+
+def batch_pins(mod):
+    return [lambda: pins.test_hash_batch_concatenates_per_block_hashes(mod, s)
+            for s in ("shared", "independent")]
+
+
+# (name, text in oracle.c, planted replacement, pins that must catch it).
+# Every planted mistake keeps each access inside its buffer, so a copy can
+# only give wrong answers, never touch memory it does not own.
+C_MUTATIONS = [
+    ("Toeplitz: first column dropped",
+     "    for (uint64_t c = 0; c < n; ++c)\n        acc ^= get_bit",
+     "    for (uint64_t c = 1; c < n; ++c)\n        acc ^= get_bit",
+     toeplitz_pins),
+    ("Toeplitz: AND of seed and input bit replaced by OR",
+     "acc ^= get_bit(seed, base + c - r + cap - 1) & get_bit(x, c);",
+     "acc ^= get_bit(seed, base + c - r + cap - 1) | get_bit(x, c);",
+     toeplitz_pins),
+    ("Toeplitz: XOR accumulation replaced by OR",
+     "acc ^= get_bit(seed, base + c - r + cap - 1) & get_bit(x, c);",
+     "acc |= get_bit(seed, base + c - r + cap - 1) & get_bit(x, c);",
+     toeplitz_pins),
+    ("row windows: tail mask of the last input word dropped",
+     "if (w == nw - 1 && (n & 63)) xw &= (1ull << (n & 63)) - 1ull;",
+     "(void)0;",
+     toeplitz_pins),
+    ("row windows: window start one bit late",
+     "uint64_t start = base + cap - 1 - r, nw",
+     "uint64_t start = base + cap - r, nw",
+     toeplitz_pins),
+    ("row windows: seed window read with the wrong shift",
+     "return (lo >> sh) | (hi << (64 - sh));",
+     "return (lo << sh) | (hi >> (64 - sh));",
+     toeplitz_pins),
+    ("sampling: a sub-block's bits in descending order",
+     "put_bit(sub, 64ull * word_off[j] + cursor[j], get_bit(a, i));",
+     "put_bit(sub, 64ull * word_off[j] + (len[j] - 1 - cursor[j]), get_bit(a, i));",
+     sampling_pins),
+    ("sampling: word offsets rounded down",
+     "        word_off[j] = acc;\n        acc += (len[j] + 63) / 64;",
+     "        word_off[j] = acc;\n        acc += len[j] / 64;",
+     sampling_pins),
+    ("sifting: the flag stored instead of the data bit",
+     "put_bit(out, 64ull * out_off[j] + pos, get_bit(sub, b));",
+     "put_bit(out, 64ull * out_off[j] + pos, get_bit(keep_sub, b));",
+     sifting_pins),
+    ("concatenation: output offset never advanced",
+     "        if (rc) return -1;\n        off += out_len[j];",
+     "        if (rc) return -1;",
+     batch_pins),
+    ("concatenation: the seed offset of sub-block j + 1",
+     "uint64_t base = (uint64_t)j * stride;",
+     "uint64_t base = (uint64_t)(j + 1 < n_sub ? j + 1 : j) * stride;",
+     batch_pins),
+    ("output lengths rounded up",
+     "out_len[j] = (uint64_t)(p / b);",
+     "out_len[j] = (uint64_t)((p + b - 1) / b);",
+     lambda mod: [lambda: pins.test_out_lengths(mod)]),
+    ("seed tail not masked",
+     "    if (n_bits & 63) seed[nw - 1] &= (1ull << (n_bits & 63)) - 1ull;\n}",
+     "}",
+     lambda mod: [lambda: pins.test_seed_from_key(mod)]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,checks", C_MUTATIONS,
+                         ids=[c[0] for c in C_MUTATIONS])
+def test_core_pins_reject_planted_mistake(tmp_path, name, old, new, checks):
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc missing")
+    # The real oracle passes the same pins ...
+    assert not any(fails_any(c) for c in checks(oracle)), name
+    # ... and the copy with the planted mistake fails at least one.
+    mod = mutated_oracle(tmp_path, c_old=old, c_new=new)
+    assert any(fails_any(c) for c in checks(mod)), name
