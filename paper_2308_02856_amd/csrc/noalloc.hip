@@ -102,7 +102,6 @@ extern "C" ssbh_status ssbh_hash_batch_noalloc(
     if (q.kernel == SSBH_K_VALU)
         return launch_hash_valu(ctx, ws, q, choose_valu(ctx, q),
                                 (hipStream_t)stream);
-    const MfmaSchedule ms =
-        explicit_mfma_schedule(ctx, q.kernel == SSBH_K_MFMA_F4);
+    const MfmaSchedule ms = explicit_mfma_schedule(ctx);
     return launch_hash_mfma(ctx, ws, q, ms, (hipStream_t)stream);
 }

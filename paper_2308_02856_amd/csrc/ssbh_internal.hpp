@@ -164,20 +164,18 @@ struct ssbh_ctx {
 namespace ssbh {
 
 // Schedule of an explicit matrix-core request: the one forced with
-// ssbh_set_mfma_schedule, else (8,2,4) for int8 and (4,2,4) for fp4.  At two
-// waves per SIMD one wave's operand loads and funnel shifts run beside the
-// other's matrix ops, which pays for the fp4 kernel (21.2 against 23.5 ms on
-// 8192 sub-blocks of 2^17 bits) more than for int8 (36.5 against 38.0 ms).
-inline MfmaSchedule explicit_mfma_schedule(const ssbh_ctx *ctx, bool fp4) {
+// ssbh_set_mfma_schedule, else (4,2,4).  At two waves per SIMD one wave's
+// operand work runs beside the other's matrix ops: on 8192 sub-blocks of
+// 2^17 bits, fp4 21.2 against 23.5 ms at (8,2,4), int8 36.5 against 38.0 ms.
+inline MfmaSchedule explicit_mfma_schedule(const ssbh_ctx *ctx) {
     MfmaSchedule ms;
+    ms.mt = 4;
+    ms.nt = 2;
+    ms.wm = 4;
     if (ctx->forced_mfma[0]) {
         ms.mt = ctx->forced_mfma[0];
         ms.nt = ctx->forced_mfma[1];
         ms.wm = ctx->forced_mfma[2];
-    } else if (fp4) {
-        ms.mt = 4;
-        ms.nt = 2;
-        ms.wm = 4;
     }
     ms.ksplit = ctx->forced_mfma[3];
     return ms;
