@@ -501,9 +501,9 @@ ssbh_status ssbh_set_schedule(ssbh_ctx *ctx, int r, int waves,
 
 /* Force the schedule of the matrix-core kernels (int8 and fp4): mt = 32-row
  * tiles per wavefront, nt = 32-sub-block tiles per wavefront, wm =
- * wavefronts per workgroup (supported: (8,2,4), (4,4,4), (4,2,4), (8,1,4));
- * 0s restore the library's choice ((4,2,4), two waves per SIMD; the tuned
- * choice under SSBH_K_AUTO).  ksplit = K splits per tile (1 .. 64; 0 = chosen so that
+ * wavefronts per workgroup (supported: (8,2,4), (4,4,4), (4,2,4), (4,2,8),
+ * (8,1,4)); 0s restore the library's choice (two waves per SIMD: (4,2,4) for
+ * int8, (4,2,8) for fp4; the tuned choice under SSBH_K_AUTO).  ksplit = K splits per tile (1 .. 64; 0 = chosen so that
  * the tiles fill every compute unit in whole rounds).  The output bits do not
  * depend on any of them. */
 ssbh_status ssbh_set_mfma_schedule(ssbh_ctx *ctx, int mt, int nt, int wm,

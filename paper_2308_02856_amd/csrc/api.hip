@@ -259,7 +259,8 @@ ssbh_status launch_hash(ssbh_ctx *ctx, Workspace &ws, const HashRequest &q,
         return launch_hash_valu(ctx, ws, r, choose_valu(ctx, r), stream);
     }
     if (q.kernel == SSBH_K_MFMA_I8 || q.kernel == SSBH_K_MFMA_F4) {
-        const MfmaSchedule ms = explicit_mfma_schedule(ctx);
+        const MfmaSchedule ms =
+            explicit_mfma_schedule(ctx, q.kernel == SSBH_K_MFMA_F4);
         return launch_hash_mfma(ctx, ws, q, ms, stream);
     }
     if (q.kernel == SSBH_K_FFT) {

@@ -690,6 +690,7 @@ ssbh_status launch_hash_mfma(ssbh_ctx *ctx, Workspace &ws,
     SSBH_MFMA_CASE(8, 2, 4, 1)
     SSBH_MFMA_CASE(4, 4, 4, 1)
     SSBH_MFMA_CASE(4, 2, 4, 2)
+    SSBH_MFMA_CASE(4, 2, 8, 2)
     SSBH_MFMA_CASE(8, 1, 4, 1)
 #undef SSBH_MFMA_CASE
     set_error("unsupported MFMA schedule");

@@ -102,6 +102,7 @@ extern "C" ssbh_status ssbh_hash_batch_noalloc(
     if (q.kernel == SSBH_K_VALU)
         return launch_hash_valu(ctx, ws, q, choose_valu(ctx, q),
                                 (hipStream_t)stream);
-    const MfmaSchedule ms = explicit_mfma_schedule(ctx);
+    const MfmaSchedule ms =
+        explicit_mfma_schedule(ctx, q.kernel == SSBH_K_MFMA_F4);
     return launch_hash_mfma(ctx, ws, q, ms, (hipStream_t)stream);
 }

@@ -164,14 +164,16 @@ struct ssbh_ctx {
 namespace ssbh {
 
 // Schedule of an explicit matrix-core request: the one forced with
-// ssbh_set_mfma_schedule, else (4,2,4).  At two waves per SIMD one wave's
-// operand work runs beside the other's matrix ops: on 8192 sub-blocks of
-// 2^17 bits, fp4 21.2 against 23.5 ms at (8,2,4), int8 36.5 against 38.0 ms.
-inline MfmaSchedule explicit_mfma_schedule(const ssbh_ctx *ctx) {
+// ssbh_set_mfma_schedule, else two waves per SIMD, where one wave's operand
+// work runs beside the other's matrix ops: (4,2,4) for int8 (36.5 against
+// 38.0 ms at (8,2,4) on 8192 sub-blocks of 2^17 bits) and (4,2,8) for fp4,
+// whose eight waves share one staging of the codes (20.3 against 22.4 ms at
+// (4,2,4) and 23.0 at (8,2,4)).
+inline MfmaSchedule explicit_mfma_schedule(const ssbh_ctx *ctx, bool fp4) {
     MfmaSchedule ms;
     ms.mt = 4;
     ms.nt = 2;
-    ms.wm = 4;
+    ms.wm = fp4 ? 8 : 4;
     if (ctx->forced_mfma[0]) {
         ms.mt = ctx->forced_mfma[0];
         ms.nt = ctx->forced_mfma[1];

@@ -142,7 +142,7 @@ def test_contraction_shape_sampled_rows(ctx, S, orc):
         assert bit(g_mfma, j * m + r) == want, (j, r)
 
 
-SCHEDULES = [(8, 2, 4), (4, 4, 4), (4, 2, 4), (8, 1, 4)]
+SCHEDULES = [(8, 2, 4), (4, 4, 4), (4, 2, 4), (4, 2, 8), (8, 1, 4)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)

@@ -96,7 +96,8 @@ def test_empty_and_short_blocks(ctx, orc):
     assert np.array_equal(got[: want.size], want)
 
 
-@pytest.mark.parametrize("sched", [(8, 2, 4), (4, 4, 4), (4, 2, 4), (8, 1, 4)])
+@pytest.mark.parametrize("sched", [(8, 2, 4), (4, 4, 4), (4, 2, 4), (4, 2, 8),
+                                   (8, 1, 4)])
 @pytest.mark.parametrize("ksplit", [0, 1, 2, 3])
 def test_every_schedule_and_k_split(ctx, orc, sched, ksplit):
     """Uneven i.i.d. sub-blocks of ~2^14 bits (several K chunks, ragged
